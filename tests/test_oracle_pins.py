@@ -1,0 +1,424 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle.
+
+Each test checks the oracle against an independent source: another
+implementation of a published generator (rocRAND's Philox4x32-10), a closed
+form, an invariant, quadrature, finite differences, or a brute-force search.
+Sizes are chosen so the whole file runs in about a minute on 8 cores.
+"""
+import math
+import os
+import shutil
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+from paper_2605_08916_amd import inputs
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+# ---------------------------------------------------------------------------
+# Generator
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def rocrand_ref():
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available to build the rocRAND reference program")
+    d = tempfile.mkdtemp()
+    exe = os.path.join(d, "rr")
+    subprocess.check_call([hipcc, "-std=c++17", "-O1", os.path.join(HERE, "helpers", "rocrand_philox_ref.cpp"),
+                           "-o", exe], stdout=subprocess.DEVNULL, stderr=subprocess.DEVNULL)
+
+    def run(triples):
+        inp = "\n".join(f"{a} {b} {c}" for a, b, c in triples) + "\n"
+        out = subprocess.run([exe], input=inp, capture_output=True, text=True, check=True).stdout
+        return np.array([[int(v) for v in line.split()] for line in out.strip().splitlines()], np.uint64)
+
+    yield run
+    shutil.rmtree(d, ignore_errors=True)
+
+
+def test_philox_matches_rocrand(orc, rocrand_ref):
+    """Philox4x32-10 (Sec. 4.3 tour state; Salmon et al. 2011) against
+    rocRAND's independent implementation on 300 counters/keys."""
+    rng = np.random.default_rng(0)
+    cases, triples = [], []
+    for k in range(300):
+        ctr = rng.integers(0, 2 ** 32, 4, dtype=np.uint64)
+        key = rng.integers(0, 2 ** 32, 2, dtype=np.uint64)
+        if k < 3:
+            ctr[:] = [0, 0xFFFFFFFF, 1][k]
+            key[:] = [0, 0xFFFFFFFF, 7][k]
+        seed = int(key[0]) | (int(key[1]) << 32)
+        sub = int(ctr[2]) | (int(ctr[3]) << 32)
+        off = 4 * (int(ctr[0]) | (int(ctr[1]) << 32))
+        if off >= 2 ** 64:
+            continue
+        cases.append((ctr, key))
+        triples.append((seed, sub, off))
+    ref = rocrand_ref(triples)
+    got = np.array([orc.philox(c, k) for c, k in cases], np.uint64)
+    assert np.array_equal(got, ref)
+
+
+def test_uniform_stream_layout(orc, rocrand_ref):
+    """U(c, s, tag, i) takes word i&3 of the block at counter
+    (c, s_lo, s_hi, tag<<24 | i>>2), keeps its top 24 bits, scales by 2^-24."""
+    seed, c, s = 0x1234_5678_9ABC_DEF0, 77, (5 << 32) + 3
+    for tag in (0, 1, 2):
+        for i in (0, 1, 2, 3, 4, 13, 59):
+            w = (tag << 24) | (i >> 2)
+            sub = (s >> 32) | (w << 32)
+            off = 4 * (c | ((s & 0xFFFFFFFF) << 32))
+            block = rocrand_ref([(seed, sub, off)])[0]
+            want = int(block[i & 3]) >> 8
+            assert orc.uniform(seed, c, s, tag, i) == want / 2.0 ** 24
+
+
+def test_box_muller_and_exponential_moments(orc):
+    """Box-Muller gives independent N(0,1) pairs; -ln(1-U) has unit mean."""
+    n = 100_000
+    u = np.array([[orc.uniform(3, k, 0, 1, 0), orc.uniform(3, k, 0, 1, 1)] for k in range(n)])
+    z = np.array([orc.box_muller(a, b) for a, b in u])
+    se = 1 / math.sqrt(n)
+    assert abs(z[:, 0].mean()) < 5 * se and abs(z[:, 1].mean()) < 5 * se
+    assert abs(z[:, 0].var() - 1) < 5 * math.sqrt(2) * se and abs(z[:, 1].var() - 1) < 5 * math.sqrt(2) * se
+    assert abs(np.mean(z[:, 0] * z[:, 1])) < 5 * se
+    e = -np.log(1 - u[:, 0])
+    assert abs(e.mean() - 1) < 5 * se
+
+
+# ---------------------------------------------------------------------------
+# Geometry and materials
+# ---------------------------------------------------------------------------
+def _rays(sc, n, seed):
+    rng = np.random.default_rng(seed)
+    V = sc["vertices"].astype(np.float64)
+    lo, hi = V.min(0), V.max(0)
+    o = lo + (hi - lo) * rng.uniform(-0.1, 1.1, (n, 3))
+    d = rng.normal(size=(n, 3))
+    return o, d / np.linalg.norm(d, axis=1, keepdims=True)
+
+
+@pytest.mark.parametrize("which", ["tiny", "spheres_small"])
+def test_bvh_equals_brute_force(orc, which):
+    """The oracle's median-split BVH returns the brute-force closest hit
+    (triangle and t, ties to the lower index) and the same occlusion."""
+    sc = inputs.cornell_tiny() if which == "tiny" else inputs.procedural_spheres(n_spheres=2, subdiv=2)
+    S = orc.Scene(sc)
+    o, d = _rays(sc, 4000 if which == "tiny" else 1500, 1)
+    p1, t1 = S.trace(o, d)
+    o2 = o.copy()
+    S.set_brute(True)
+    p2, t2 = S.trace(o2, d)
+    assert np.array_equal(p1, p2)
+    assert np.array_equal(t1[p1 >= 0], t2[p2 >= 0])
+    tm = np.where(p2 >= 0, t2 * 0.999, 1e3)
+    occ_b = S.occluded(o, d, tm)
+    S.set_brute(False)
+    occ = S.occluded(o, d, tm)
+    assert np.array_equal(occ, occ_b)
+    assert (p1 >= 0).mean() > 0.15
+
+
+def test_onb_orthonormal(orc):
+    rng = np.random.default_rng(2)
+    for _ in range(200):
+        n = rng.normal(size=3)
+        n /= np.linalg.norm(n)
+        t, b = orc.onb(n)
+        M = np.stack([t, b, n])
+        assert np.allclose(M @ M.T, np.eye(3), atol=1e-12)
+        assert np.allclose(np.cross(t, b), n, atol=1e-12)
+
+
+def _hemisphere_quadrature(n, nth=400, nph=800):
+    """Directions and solid-angle weights on the hemisphere around n
+    (midpoint rule in cos(theta) and phi)."""
+    t = np.cross(n, [0.3, 0.5, 0.8])
+    t /= np.linalg.norm(t)
+    b = np.cross(n, t)
+    ct = (np.arange(nth) + 0.5) / nth
+    ph = 2 * np.pi * (np.arange(nph) + 0.5) / nph
+    CT, PH = np.meshgrid(ct, ph, indexing="ij")
+    ST = np.sqrt(1 - CT ** 2)
+    dirs = (ST * np.cos(PH))[..., None] * t + (ST * np.sin(PH))[..., None] * b + CT[..., None] * n
+    w = np.full(CT.shape, (1.0 / nth) * (2 * np.pi / nph))
+    return dirs.reshape(-1, 3), w.ravel(), CT.ravel()
+
+
+@pytest.mark.parametrize("mat", [
+    inputs.material(inputs.KIND_LAMBERT, albedo=(0.7, 0.4, 0.2)),
+    inputs.material(inputs.KIND_GGX, rough=0.5, f0=(0.95, 0.7, 0.5)),
+    inputs.material(inputs.KIND_GGX, rough=0.3, f0=(0.9, 0.6, 0.55)),
+])
+def test_bsdf_sampling_matches_evaluation(orc, mat):
+    """E_(u,v)[weight * g(wi)] from the sampler equals the quadrature of
+    f_s cos g over the hemisphere from the evaluator, for several g: pins the
+    BSDF value, the sampling density and their Jacobian against each other."""
+    n = np.array([0.2, -0.3, 0.93])
+    n /= np.linalg.norm(n)
+    wo = np.array([0.5, 0.4, 0.6])
+    wo = wo / np.linalg.norm(wo)
+    assert wo @ n > 0
+    k = 1024
+    g1 = (np.arange(k) + 0.5) / k
+    U, V = np.meshgrid(g1, g1, indexing="ij")
+    ok, wi, wt = orc.bsdf_sample_n(mat, n, wo, U.ravel(), V.ravel())
+    dirs, w, ct = _hemisphere_quadrature(n)
+    fs = orc.bsdf_eval_n(mat, n, wo, dirs)
+    gs = [lambda x: np.ones(len(x)), lambda x: (x @ n) ** 2, lambda x: x @ np.array([0.6, 0.0, 0.8]) + 1.0,
+          lambda x: np.exp(3 * (x @ wo))]
+    for g in gs:
+        est = (wt * np.where(ok, g(wi), 0.0)[:, None]).mean(0)
+        quad = (fs * (ct * w * g(dirs))[:, None]).sum(0)
+        assert np.allclose(est, quad, rtol=1.5e-2, atol=1e-4), (est, quad)
+    if mat[0] == inputs.KIND_LAMBERT:
+        assert np.allclose((fs * (ct * w)[:, None]).sum(0), mat[1:4], rtol=1e-4)
+
+
+def test_bsdf_reciprocity_and_energy(orc):
+    rng = np.random.default_rng(4)
+    n = np.array([0.0, 0.0, 1.0])
+    for rough in (0.1, 0.3, 0.5):
+        mat = inputs.material(inputs.KIND_GGX, rough=rough, f0=(1.0, 1.0, 1.0))
+        for _ in range(50):
+            a, b = rng.normal(size=(2, 3))
+            a[2], b[2] = abs(a[2]), abs(b[2])
+            a /= np.linalg.norm(a)
+            b /= np.linalg.norm(b)
+            assert np.allclose(orc.bsdf_eval(mat, n, a, b), orc.bsdf_eval(mat, n, b, a), rtol=1e-12)
+        dirs, w, ct = _hemisphere_quadrature(n)
+        for wo in ([0, 0, 1], [0.6, 0, 0.8]):
+            alb = (orc.bsdf_eval_n(mat, n, np.array(wo, float), dirs)[:, 0] * ct * w).sum()
+            assert 0.5 < alb <= 1.0 + 2e-3
+
+
+# ---------------------------------------------------------------------------
+# The path sampler f(u) and its gradient
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("L", [2, 3, 4])
+def test_white_furnace_closed_form(orc, L):
+    """Closed cube of inward Lambertian emitters: E_u[f] = Le (1-a^L)/(1-a)."""
+    a, Le = 0.5, 1.0
+    S = orc.Scene(inputs.white_furnace(albedo=a, Le=Le))
+    u = inputs.random_points(4 * (L - 1), 120_000, seed=10 + L).astype(np.float64)
+    f, p, _, _ = S.path_eval(L, u, grad=False)
+    want = Le * (1 - a ** L) / (1 - a)
+    se = f[:, 0].std() / math.sqrt(len(f))
+    assert abs(f[:, 0].mean() - want) < 5 * se
+    assert np.all(f[:, 0] == f[:, 1]) and np.all(f[:, 1] == f[:, 2])
+    assert np.all(f[:, 0] >= Le)  # primary emission always seen
+
+
+def _one_bounce_closed_form(sc, u):
+    """f(u) for path length 2 in the one-bounce scene, written from its
+    geometry: pinhole ray, intersection with the plane z = 0 (or the light
+    quad in front of it), direct light from a point on the quad light."""
+    cam = sc["camera"].astype(np.float64)
+    eye, at, up, fov = cam[:3], cam[3:6], cam[6:9], cam[9]
+    W, H = sc["width"], sc["height"]
+    fwd = (at - eye) / np.linalg.norm(at - eye)
+    right = np.cross(fwd, up)
+    right /= np.linalg.norm(right)
+    upv = np.cross(right, fwd)
+    th = math.tan(math.radians(fov) / 2)
+    lt = sc["lights"][0].astype(np.float64)
+    p0, e1, e2, Le = lt[:3], lt[3:6], lt[6:9], lt[9:12]
+    A = np.linalg.norm(np.cross(e1, e2))
+    alb = sc["materials"][0, 1:4].astype(np.float64)
+    out = np.zeros((len(u), 3))
+    for k, uu in enumerate(u):
+        d = fwd + th * (2 * uu[0] - 1) * (W / H) * right + th * (1 - 2 * uu[1]) * upv
+        d /= np.linalg.norm(d)
+        # does the camera ray meet the light quad (back side: no emission, black)?
+        tl = (p0[2] - eye[2]) / d[2]
+        q = eye + tl * d - p0
+        a_ = q @ e1 / (e1 @ e1)
+        b_ = q @ e2 / (e2 @ e2)
+        if 0 <= a_ <= 1 and 0 <= b_ <= 1:
+            continue
+        t = -eye[2] / d[2]
+        x = eye + t * d
+        if not (abs(x[0]) <= 2 and abs(x[1]) <= 2):
+            continue
+        y = p0 + uu[2] * e1 + uu[3] * e2
+        w = y - x
+        r2 = w @ w
+        cx = w[2] / math.sqrt(r2)
+        cy = w[2] / math.sqrt(r2)
+        out[k] = alb / math.pi * Le * cx * cy / r2 * A
+    return out
+
+
+def test_one_bounce_closed_form_value_and_gradient(orc):
+    sc = inputs.one_bounce_plane()
+    S = orc.Scene(sc)
+    u = inputs.random_points(4, 400, seed=3).astype(np.float64)
+    f, p, score, _ = S.path_eval(2, u)
+    want = _one_bounce_closed_form(sc, u)
+    assert np.allclose(f, want, rtol=1e-10, atol=1e-12)
+    assert (want[:, 0] > 0).mean() > 0.3
+    # gradient of ln(p + eps) against central differences of the closed form
+    lum = np.array([0.2126, 0.7152, 0.0722])
+    h = 1e-6
+    for k in range(60):
+        if want[k, 0] == 0:
+            continue
+        for i in range(4):
+            up, um = u[k].copy(), u[k].copy()
+            up[i] += h
+            um[i] -= h
+            fp, fm = _one_bounce_closed_form(sc, [up, um])
+            if fp[0] == 0 or fm[0] == 0:
+                continue
+            fd = (math.log(fp @ lum + 1e-8) - math.log(fm @ lum + 1e-8)) / (2 * h)
+            assert abs(fd - score[k, i]) <= 1e-5 * max(1.0, abs(fd)), (k, i, fd, score[k, i])
+
+
+@pytest.mark.parametrize("which,L", [("tiny", 4), ("spheres_small", 6)])
+def test_score_matches_finite_differences(orc, which, L):
+    """Forward-mode score equals central differences of ln(p + eps) wherever
+    both perturbed points keep the same discrete path (readings A13, A14)."""
+    sc = inputs.cornell_tiny() if which == "tiny" else inputs.procedural_spheres(n_spheres=3, subdiv=2)
+    S = orc.Scene(sc)
+    d = 4 * (L - 1)
+    u = inputs.random_points(d, 150, seed=21).astype(np.float64)
+    f, p, score, rec = S.path_eval(L, u)
+    h = 1e-6
+    checked = 0
+    for k in range(len(u)):
+        if p[k] <= 0:
+            assert np.all(score[k] == 0)
+            continue
+        for i in range(d):
+            up, um = u[k].copy(), u[k].copy()
+            up[i] += h
+            um[i] -= h
+            fp, pp, _, rp = S.path_eval(L, up[None], grad=False)
+            fm, pm, _, rm = S.path_eval(L, um[None], grad=False)
+            if not (np.array_equal(rp[0], rec[k]) and np.array_equal(rm[0], rec[k])):
+                continue
+            fd = (math.log(pp[0] + 1e-8) - math.log(pm[0] + 1e-8)) / (2 * h)
+            assert abs(fd - score[k, i]) <= 2e-4 * max(1.0, abs(fd)), (k, i, fd, score[k, i])
+            checked += 1
+    assert checked > 200
+
+
+# ---------------------------------------------------------------------------
+# The chain
+# ---------------------------------------------------------------------------
+def test_constant_target_tours(orc):
+    """p constant, k0 = p_lambda/(m dt): each step kills with probability
+    k dt/(1 + k dt) = 1/(m+1); the estimator returns lambda(f) = 1."""
+    N, steps = 1000, 1500
+    C = orc.Chains.mixture(2, [], np.zeros((0, 2)), [], 1.0, N, seed=3, k0=1.0 / (64 * 1e-5))
+    C.init()
+    C.step(steps)
+    a = C.accum()
+    n = N * (steps + 1)
+    q = 1 / 65
+    assert abs(a["tour_count"] / n - q) < 5 * math.sqrt(q * (1 - q) / n)
+    img = C.resolve()[:, 0]
+    assert abs(img[0] - 1.0) < 0.01
+    assert np.all(np.abs(img[1:]) < 0.03)
+
+
+def test_local_dynamics_lyapunov(orc):
+    """Killing off, Gaussian target N(c, s^2 I2): the Euler-Maruyama move with
+    rotation is AR(1), x' - c = A (x - c) + stddev xi, A = alpha I - beta U,
+    alpha = 1 - stddev^2/(2 s^2), beta = gamma_tilde / s^2.  Stationary
+    covariance q I with q = stddev^2/(1 - alpha^2 - beta^2); lag-one cross
+    covariance E[x'_1 x_2] = -beta q (Alg. 5.1, rotate)."""
+    sd, dt, gam, s = 0.02, 1e-5, 100.0, 0.1
+    C = orc.Chains.mixture(2, [1.0], np.array([[0.5, 0.5]]), [s], 0.0, 400, seed=7, stddev=sd, dt=dt, gamma=gam,
+                           k0=1e-30)
+    C.init()
+    C.step(300)
+    x = C.step(3000, trace=True) - 0.5
+    alpha = 1 - sd ** 2 / (2 * s ** 2)
+    beta = dt * gam / 2 / s ** 2
+    q = sd ** 2 / (1 - alpha ** 2 - beta ** 2)
+    assert abs(x[:, 0].var() / q - 1) < 0.02 and abs(x[:, 1].var() / q - 1) < 0.02
+    c12 = (x[1:, 0] * x[:-1, 1]).mean()
+    c21 = (x[1:, 1] * x[:-1, 0]).mean()
+    assert abs(c12 + beta * q) < 0.15 * beta * q
+    assert abs(c21 - beta * q) < 0.15 * beta * q
+
+
+def _mixture_closed_form(w, m, s, c0):
+    d = m.shape[1]
+    damp = np.exp(-2 * np.pi ** 2 * s ** 2)
+    out = [c0 + w.sum()]
+    for i in range(d):
+        out.append((w * damp * np.cos(2 * np.pi * m[:, i])).sum())
+        out.append((w * damp * np.sin(2 * np.pi * m[:, i])).sum())
+    return np.array(out)
+
+
+@pytest.mark.parametrize("d,s,c0", [(2, [0.15, 0.2], 0.3), (4, [0.2, 0.25, 0.2], 0.2)])
+def test_restore_estimator_closed_forms(orc, d, s, c0):
+    """Wrapped Gaussian mixture on T^d, f = p g with g = (1, cos 2 pi x_i,
+    sin 2 pi x_i): k0 accum / tourCount -> lambda(p g) =
+    (c0 + sum w, sum_j w_j exp(-2 pi^2 s_j^2) cos/sin(2 pi m_ji)).  m = 4 keeps
+    tours short so the finite-run renewal bias of the ratio estimator
+    (about 2.5/steps relative here) stays below the noise."""
+    rng = np.random.default_rng(4)
+    s = np.array(s)
+    m = rng.uniform(size=(len(s), d))
+    w = np.array([0.4, 0.3, 0.2, 0.1][: len(s)])
+    w = w / w.sum()
+    want = _mixture_closed_form(w, m, s, c0)
+    ests = []
+    for seed in range(4):
+        C = orc.Chains.mixture(d, w, m, s, c0, 1024, seed=seed, m=4)
+        C.init()
+        C.step(3000)
+        ests.append(C.resolve()[:, 0])
+    ests = np.array(ests)
+    se = ests.std(0, ddof=1) / 2
+    tol = 4.5 * se + 2.5 / 3000 * np.abs(want) + 2e-3
+    assert np.all(np.abs(ests.mean(0) - want) < tol), (ests.mean(0) - want, tol)
+
+
+def test_restore_image_tends_to_path_tracing(orc):
+    """As m -> 0 tours last about one step and the Diffusion Restore image
+    k0 accum W H / tourCount reduces to importance-sampled path tracing: it
+    must match brute-force independent path tracing (pins the estimator's
+    normalisation, the pixel map and the holding weights)."""
+    sc = inputs.cornell_tiny()
+    S = orc.Scene(sc)
+    ref = S.pt_render(4, seed=99, spp=512)
+    ref2 = S.pt_render(4, seed=98, spp=512)
+    C = orc.Chains.scene(S, 4, 4096, seed=1, m=2e-4)
+    C.init()
+    C.step(300)
+    img = C.resolve()
+    lum = lambda a: 0.2126 * a[0] + 0.7152 * a[1] + 0.0722 * a[2]
+    light = lum(ref) > 5
+    # per-sample noise of a 512-spp image, from two independent references
+    var_ref = ((lum(ref) - lum(ref2)) ** 2).mean() / 2
+    for mask in (light, ~light):
+        n = mask.sum()
+        diff = lum(img)[mask].mean() - lum(ref)[mask].mean()
+        # the DR image holds ~300 samples per pixel: allow 6 sigma of both
+        se = math.sqrt(var_ref * (512 / 300 + 1) / n)
+        assert abs(diff) < 6 * se + 0.01 * lum(ref)[mask].mean(), (mask.sum(), diff, se)
+
+
+def test_chain_determinism_and_thread_independence(orc):
+    sc = inputs.cornell_tiny()
+    S = orc.Scene(sc)
+    outs = []
+    for nt in (1, 4):
+        C = orc.Chains.scene(S, 4, 64, seed=5)
+        C.init(nthreads=nt)
+        C.step(20, nthreads=nt)
+        st = C.state()
+        outs.append((st["x"], st["killed"], C.accum()["tour_count"]))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
+    assert outs[0][2] == outs[1][2]
