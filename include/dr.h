@@ -1,0 +1,233 @@
+/*
+ * dr.h — C ABI of the Diffusion Restore chain-step library for MI355X (gfx950).
+ *
+ * The library runs the many-chain step of the Diffusion Restore process: a
+ * Jump Restore process on the primary-sample-space torus (Def. 4.1) whose
+ * local moves are unadjusted Euler-Maruyama Langevin steps with an optional
+ * rotational drift (Sec. 5, Eq. local-dynamics, Alg. 5.1), with holding rate
+ * 1/dt (Eq. diffusion-restore-holding-rate), killing rate k0/p
+ * (Eq. modified-killing-rate with uniform regeneration), regeneration from the
+ * uniform distribution, and Rao-Blackwellised holding-time splats into a
+ * frame buffer (Alg. 4.1-4.3).
+ *
+ * Conventions for every entry point:
+ *  - Every function returns dr_status; DR_OK on success.  On failure nothing
+ *    is changed and dr_last_error() returns a message (thread-local, valid
+ *    until the next dr_* call on the same thread).
+ *  - "host" pointers are ordinary CPU memory, "device" pointers are HIP device
+ *    memory on the device the object was created on.  Pointers passed in are
+ *    borrowed: the library never frees them, and device pointers must stay
+ *    valid until the stream work that uses them has completed.
+ *  - hip_stream arguments are hipStream_t values (NULL = the legacy default
+ *    stream).  Calls documented as asynchronous only enqueue work.
+ *  - Arrays of chain state are planar ("structure of arrays"): coordinate i
+ *    of chain c is at [i * n_chains + c].
+ *  - Handles are not thread-safe; use one thread (and one stream) per handle.
+ */
+#ifndef DR_H
+#define DR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DR_OK = 0,
+    DR_ERR_INVALID_ARG = 1,
+    DR_ERR_OUT_OF_MEMORY = 2,
+    DR_ERR_DEVICE = 3,
+    DR_ERR_BAD_STATE = 4,
+    DR_ERR_UNSUPPORTED = 5
+} dr_status;
+
+/* Message for the last failed call on this thread ("" if none). */
+const char* dr_last_error(void);
+
+/* Library version string. */
+const char* dr_version(void);
+
+/* ------------------------------------------------------------------------
+ * Scene (the integrand f of Sec. 3 is the path contribution of this scene).
+ * ------------------------------------------------------------------------ */
+enum { DR_MAT_LAMBERT = 0, DR_MAT_GGX_CONDUCTOR = 1 };
+
+/* Parallelogram light p0 + a e1 + b e2 (a, b in [0,1]) emitting radiance Le
+ * on the side of e1 x e2 (the paper's lights are diffuse area lights, Sec. 6
+ * test scenes).  Each light must also be present in the triangle list as two
+ * triangles wound like e1 x e2 with an emissive material. */
+typedef struct { float p0[3], e1[3], e2[3], Le[3]; } dr_quad_light;
+
+/* Lambertian (albedo/pi) or GGX conductor (Trowbridge-Reitz D with alpha =
+ * roughness, separable Smith G, Schlick F with normal reflectance f0);
+ * Le is emitted radiance for emitter triangles. */
+typedef struct {
+    uint32_t kind;
+    float albedo[3];
+    float roughness;
+    float f0[3];
+    float Le[3];
+} dr_material;
+
+/* Binary BVH node as built on the host: a >= 0 is an inner node with children
+ * a and b; a < 0 is a leaf holding bvh_prim_order[~a .. ~a + b).  Node 0 is the
+ * root.  lo/hi bound every triangle below the node. */
+typedef struct { float lo[3]; float hi[3]; int32_t a; int32_t b; } dr_bvh_node;
+
+/* Pinhole camera; the film point (u0, u1) in [0,1)^2 maps to the ray through
+ * ((2 u0 - 1) tan(fov/2) W/H, (1 - 2 u1) tan(fov/2)) in the camera frame, row
+ * 0 at the top. */
+typedef struct {
+    float eye[3], at[3], up[3];
+    float vfov_deg;
+    uint32_t width, height;
+} dr_camera;
+
+typedef struct {
+    const float* vertices; uint32_t n_vertices;        /* host, xyz per vertex */
+    const uint32_t* indices; uint32_t n_triangles;      /* host, 3 per triangle */
+    const uint32_t* tri_material;                       /* host, n_triangles */
+    const dr_material* materials; uint32_t n_materials; /* host */
+    const dr_quad_light* lights; uint32_t n_lights;     /* host, 1..127 */
+    const dr_bvh_node* bvh; uint32_t n_nodes;           /* host; NULL: the library builds one */
+    const uint32_t* bvh_prim_order;                     /* host, n_triangles (with bvh) */
+    dr_camera camera;
+} dr_scene_desc;
+
+typedef struct dr_scene dr_scene;
+typedef struct dr_chains dr_chains;
+
+/* Build a binned-SAH BVH on the host (no device work).  nodes_out must hold
+ * 2*n_triangles nodes and prim_order_out n_triangles entries; leaves hold at
+ * most max_leaf (1..16) triangles and the tree depth is kept <= 40.
+ * Fails with DR_ERR_INVALID_ARG on empty input or an index out of range. */
+dr_status dr_bvh_build(const float* vertices, uint32_t n_vertices, const uint32_t* indices, uint32_t n_triangles,
+                       uint32_t max_leaf, dr_bvh_node* nodes_out, uint32_t* n_nodes_out, uint32_t* prim_order_out);
+
+/* Validate and deep-copy a scene to device `device` (the caller's arrays may be
+ * freed on return).  Converts the host BVH to the device node layout.
+ * Errors: DR_ERR_INVALID_ARG (index/material/node out of range, no lights,
+ * more than 2^24-1 triangles or 127 lights, BVH deeper than 40),
+ * DR_ERR_OUT_OF_MEMORY, DR_ERR_DEVICE.  Synchronous. */
+dr_status dr_scene_create(const dr_scene_desc* desc, int device, dr_scene** out);
+
+/* Replace the camera (a scene change: chains built on this scene must be
+ * re-initialised with dr_chains_reinit before the next dr_step, Sec. 4.3). */
+dr_status dr_scene_set_camera(dr_scene* s, const dr_camera* cam);
+
+void dr_scene_destroy(dr_scene* s);
+
+/* ------------------------------------------------------------------------
+ * Chains
+ * ------------------------------------------------------------------------ */
+enum { DR_MODE_FUSED = 0, DR_MODE_PLAIN = 1 };
+
+typedef struct {
+    uint32_t n_chains;       /* N >= 1 */
+    uint32_t max_path_len;   /* L in 2..16 path segments; dimension d = 4(L-1) */
+    float stddev;            /* sqrt(dt) sigma, paper 5e-3 (Sec. 6) */
+    float dt;                /* Euler-Maruyama step, paper 1e-5; holding rate 1/dt */
+    float gamma;             /* rotational drift scale, gamma~ = dt gamma / 2 (Alg. 5.1) */
+    float m;                 /* mean steps per tour, k0 = p_lambda/(m dt), paper 64 */
+    float eps;               /* target penalty, paper 1e-8 (Sec. 5) */
+    float k0;                /* > 0: use it; <= 0: estimate p_lambda in the init pass */
+    uint32_t rao_blackwell;  /* 1: splat weight 1/(h+k); 0: the sampled holding time */
+    uint32_t mode;           /* DR_MODE_FUSED or DR_MODE_PLAIN */
+    const float* sigma_diag; /* device, d x N per-chain stddev (overrides stddev), borrowed, nullable */
+} dr_params;
+
+/* Allocate the chain buffers for scene s and run the initialise pass of frame
+ * `frame` (Alg. 4.1): x ~ uniform, f(x), p_lambda estimate and k0 unless
+ * given, hold/kill, splat, and the score of the survivors.  Asynchronous on
+ * hip_stream.  Errors: DR_ERR_INVALID_ARG (see dr_params ranges),
+ * DR_ERR_OUT_OF_MEMORY. */
+dr_status dr_chains_init(dr_scene* s, const dr_params* p, uint64_t seed, uint32_t frame, void* hip_stream,
+                         dr_chains** out);
+
+/* Re-run the initialise pass of frame `frame` on existing buffers (clears the
+ * frame buffer and tour count; required after a scene change).  Asynchronous. */
+dr_status dr_chains_reinit(dr_chains* c, uint32_t frame, void* hip_stream);
+
+/* Advance every chain by n_steps evolve steps (Alg. 4.2 with Alg. 5.1).
+ * Asynchronous.  DR_ERR_BAD_STATE if the scene camera changed since init. */
+dr_status dr_step(dr_chains* c, uint32_t n_steps, void* hip_stream);
+
+/* Resolve pass (Alg. 4.3): image_dev[ch * W*H + pix] = W H k0 accum / tourCount
+ * (0 while tourCount is 0); planar RGB float, device.  Asynchronous; no host
+ * synchronisation, so it can sit in a captured graph. */
+dr_status dr_resolve(dr_chains* c, float* image_dev, void* hip_stream);
+
+/* Resolve, copy to host_rgb (3*W*H planar floats) and synchronise the stream. */
+dr_status dr_image_read(dr_chains* c, float* host_rgb, uint64_t* tour_count, void* hip_stream);
+
+dr_status dr_chains_destroy(dr_chains* c);
+
+/* Host view of the chain state.  Any pointer may be NULL (skipped).
+ *  x, score      d x N float (planar)
+ *  killed        N uint32 (0/1)
+ *  accum         3 x W*H float: sum of (w/dt) f/p per pixel (planar RGB)
+ *  last-step record (valid only while recording is on):
+ *  p, weight     N float: p(x) and the splat weight w of the last accumulate
+ *  pixel         N uint32
+ *  f_over_p      3 x N float
+ *  path_rec      (L-1) x N uint32 per vertex: (triangle << 8 | light << 1 |
+ *                next-event contribution) or 0xFFFFFFFF for no vertex; the
+ *                triangle is the original (input) index
+ *  step          next global step index; tour_count; k0; p_lambda_hat */
+typedef struct {
+    float* x; float* score; uint32_t* killed; float* accum;
+    float* p; float* weight; uint32_t* pixel; float* f_over_p; uint32_t* path_rec;
+    uint64_t step; uint64_t tour_count; double k0; double p_lambda_hat;
+} dr_state;
+
+/* Copy the state to the host (synchronises hip_stream). */
+dr_status dr_chains_read_state(dr_chains* c, dr_state* out, void* hip_stream);
+
+/* Overwrite x, score, killed (non-NULL ones), the step counter and, if
+ * k0 > 0, the killing constant; accum and tour_count are set when accum is
+ * non-NULL.  Synchronous. */
+dr_status dr_chains_write_state(dr_chains* c, const dr_state* in, void* hip_stream);
+
+/* Turn the per-chain last-step record on or off (off by default). */
+dr_status dr_chains_set_record(dr_chains* c, int enable);
+
+/* Counters (chain-steps, rays, BVH nodes visited, triangles tested, kills)
+ * accumulate only while enabled (off by default: a uniform branch). */
+typedef struct {
+    uint64_t chain_steps, rays, node_visits, tri_tests, kills, tours, adjoints;
+    double k0, p_lambda_hat;
+} dr_counters;
+dr_status dr_chains_set_counters(dr_chains* c, int enable);
+dr_status dr_stats(dr_chains* c, dr_counters* out, void* hip_stream);
+
+/* Launch configuration of the fused persistent kernel: threads per block
+ * (64..1024, multiple of 64), resident blocks per compute unit, and the number
+ * of chains a wavefront takes from the device work queue per pop.  Zeros keep
+ * the current value. */
+typedef struct { uint32_t block; uint32_t blocks_per_cu; uint32_t grab; } dr_launch_cfg;
+dr_status dr_chains_set_launch(dr_chains* c, const dr_launch_cfg* cfg);
+dr_status dr_chains_get_launch(dr_chains* c, dr_launch_cfg* cfg);
+
+/* ------------------------------------------------------------------------
+ * Path-space evaluation (differentiation surface)
+ * ------------------------------------------------------------------------ */
+/* For n points u_dev (n x d row-major, d = 4(L-1), device) evaluate f (n x 3),
+ * log(p + eps) (n) and, if grad_dev is non-NULL, the score grad_u log(p + eps)
+ * (n x d) by the reverse-mode adjoint over the taken path (discrete choices
+ * held fixed).  rec_dev (n x (L-1), nullable) receives the path record as in
+ * dr_state.path_rec.  Asynchronous. */
+dr_status dr_eval_logp_grad(dr_scene* s, uint32_t L, const float* u_dev, uint32_t n, float eps, float* f_dev,
+                            float* logp_dev, float* grad_dev, uint32_t* rec_dev, void* hip_stream);
+
+/* Independent path tracing: spp samples per pixel, u0 = (px + U)/W,
+ * u1 = (py + U)/H, other coordinates U; img_dev = per-pixel mean of f
+ * (3 x W*H planar, device).  Asynchronous. */
+dr_status dr_pt_render(dr_scene* s, uint32_t L, uint64_t seed, uint32_t spp, float* img_dev, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DR_H */

@@ -77,6 +77,7 @@ def lib():
         L.orc_chains_free.argtypes = [P]
         L.orc_chains_init.argtypes = [P, C.c_uint32, C.c_int]
         L.orc_chains_step.argtypes = [P, C.c_int, C.c_int, D]
+        L.orc_chains_set_ids.argtypes = [P, U32]
         L.orc_chains_set_state.argtypes = [P, F, F, U32, C.c_uint64, C.c_double]
         L.orc_chains_get_state.argtypes = [P, D, D, U32, D, U32, D, D, U32]
         L.orc_chains_accum.argtypes = [P, D, U64, D, D, U64]
@@ -295,6 +296,11 @@ class Chains:
         s = np.ascontiguousarray(score, np.float32).reshape(self.d, self.N)
         k = np.ascontiguousarray(killed, np.uint32).reshape(self.N)
         lib().orc_chains_set_state(self.h, _p(x, C.c_float), _p(s, C.c_float), _p(k, C.c_uint32), step, k0)
+
+    def set_ids(self, ids):
+        """Slot c draws the random streams of chain ids[c]."""
+        self._ids = np.ascontiguousarray(ids, np.uint32).reshape(self.N)
+        lib().orc_chains_set_ids(self.h, _p(self._ids, C.c_uint32))
 
     def state(self) -> dict:
         d, N = self.d, self.N

@@ -517,7 +517,12 @@ static void eval_point(const Scene& S, int L, const double* u, double eps, doubl
     Dual fd[3];
     path_eval<Dual>(S, L, ud.data(), rec, true, fd);
     Dual pd = LUM[0] * fd[0] + LUM[1] * fd[1] + LUM[2] * fd[2];
-    for (int i = 0; i < d; ++i) score[i] = pd.g[i] / (p + eps);
+    // a non-finite component (a measure-zero singularity of the sampler, e.g.
+    // u = 0 in the cosine map) is set to zero so the chain stays on the torus
+    for (int i = 0; i < d; ++i) {
+        score[i] = pd.g[i] / (p + eps);
+        if (!std::isfinite(score[i])) score[i] = 0.0;
+    }
 }
 
 // ----------------------------------------------------------------------------
@@ -586,6 +591,8 @@ struct Chains {
     std::vector<double> accum;
     uint64_t tour_count = 0, kills_step = 0;
     std::vector<double> xtrace;  // optional per-step trace of x
+    std::vector<uint32_t> ids;   // RNG chain id of each slot (identity by default)
+    uint32_t id(int c) const { return ids.empty() ? (uint32_t)c : ids[c]; }
 
     void evaluate(int c, const double* xc, double* fvec, double& pc, double* gr, uint32_t* rc) const {
         if (scene) {
@@ -594,7 +601,11 @@ struct Chains {
             for (int j = 0; j < L - 1; ++j) { rc[2 * j] = (uint32_t)pr.prim[j]; rc[2 * j + 1] = pr.nee[j]; }
         } else {
             mix->eval(xc, fvec, pc, gr);
-            if (gr) for (int i = 0; i < d; ++i) gr[i] /= (pc + P.eps);
+            if (gr)
+                for (int i = 0; i < d; ++i) {
+                    gr[i] /= (pc + P.eps);
+                    if (!std::isfinite(gr[i])) gr[i] = 0.0;
+                }
         }
         (void)c;
     }
@@ -634,8 +645,8 @@ static void chain_accumulate(Chains& C, int c, uint64_t s, std::vector<double>& 
     const double pc = C.p[c];
     // killing rate k = k0/(p + eps) (Eq. modified-killing-rate with uniform
     // regeneration); holding rate h = 1/dt.  Competing exponential clocks.
-    const double Ea = expo(uniform(C.seed, c, s, TAG_HOLD, 0));
-    const double Eb = expo(uniform(C.seed, c, s, TAG_HOLD, 1));
+    const double Ea = expo(uniform(C.seed, C.id(c), s, TAG_HOLD, 0));
+    const double Eb = expo(uniform(C.seed, C.id(c), s, TAG_HOLD, 1));
     const float kf = (float)C.k0 / ((float)pc + (float)C.P.eps);
     const bool alive = (kf * (float)C.P.dt) * (float)Ea < (float)Eb;  // FP32 decision
     const double k = C.k0 / (pc + C.P.eps);
@@ -662,7 +673,7 @@ static void chain_accumulate(Chains& C, int c, uint64_t s, std::vector<double>& 
 
 // Regenerate from the uniform distribution on the torus.
 static void chain_regen(Chains& C, int c, uint64_t s) {
-    for (int i = 0; i < C.d; ++i) C.x[(size_t)i * C.N + c] = uniform(C.seed, c, s, TAG_REGEN, i);
+    for (int i = 0; i < C.d; ++i) C.x[(size_t)i * C.N + c] = uniform(C.seed, C.id(c), s, TAG_REGEN, i);
 }
 
 // Euler-Maruyama step with rotational drift, wrapped to the torus (Alg. 5.1).
@@ -670,7 +681,8 @@ static void chain_move(Chains& C, int c, uint64_t s) {
     const double gt = C.P.dt * C.P.gamma / 2.0;  // gamma tilde
     for (int i = 0; i < C.d / 2; ++i) {
         double xi[2];
-        box_muller(uniform(C.seed, c, s, TAG_GAUSS, 2 * i), uniform(C.seed, c, s, TAG_GAUSS, 2 * i + 1), xi[0], xi[1]);
+        box_muller(uniform(C.seed, C.id(c), s, TAG_GAUSS, 2 * i), uniform(C.seed, C.id(c), s, TAG_GAUSS, 2 * i + 1),
+                   xi[0], xi[1]);
         const size_t i0 = (size_t)(2 * i) * C.N + c, i1 = (size_t)(2 * i + 1) * C.N + c;
         const double s0 = C.score[i0], s1 = C.score[i1];
         const double rot[2] = {gt * s1, -gt * s0};
@@ -975,6 +987,13 @@ void orc_chains_set_state(void* c, const float* x, const float* score, const uin
     for (int i = 0; i < C->N; ++i) C->killed[i] = killed[i];
     C->step = step;
     if (k0 > 0) C->k0 = k0;
+}
+
+// Give slot c the generator chain id ids[c] (to evaluate a sample of a larger
+// ensemble's chains).
+void orc_chains_set_ids(void* c, const uint32_t* ids) {
+    Chains* C = (Chains*)c;
+    C->ids.assign(ids, ids + C->N);
 }
 
 // Read the chain state and the last step's per-chain record.

@@ -1,0 +1,179 @@
+// Host-side binned-SAH BVH builder (the scene's acceleration structure is an
+// input of dr_scene_create; this is the library's own builder for callers that
+// do not bring one).  Output format: dr_bvh_node array, node 0 the root,
+// a >= 0 inner node with children a, b; a < 0 leaf holding
+// prim_order[~a .. ~a + b).  The tree depth never exceeds 40: once the depth
+// budget left equals the levels a balanced split still needs, splits become
+// object medians.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#include "../../include/dr.h"
+
+namespace {
+
+struct Box {
+    float lo[3], hi[3];
+    Box() {
+        for (int a = 0; a < 3; ++a) { lo[a] = INFINITY; hi[a] = -INFINITY; }
+    }
+    void grow(const float* p) {
+        for (int a = 0; a < 3; ++a) { lo[a] = std::min(lo[a], p[a]); hi[a] = std::max(hi[a], p[a]); }
+    }
+    void grow(const Box& b) {
+        for (int a = 0; a < 3; ++a) { lo[a] = std::min(lo[a], b.lo[a]); hi[a] = std::max(hi[a], b.hi[a]); }
+    }
+    float area() const {
+        const float dx = hi[0] - lo[0], dy = hi[1] - lo[1], dz = hi[2] - lo[2];
+        if (!(dx >= 0)) return 0.f;
+        return 2.f * (dx * dy + dy * dz + dz * dx);
+    }
+};
+
+constexpr int kMaxDepth = 40;
+constexpr int kBins = 32;
+
+struct Builder {
+    const float* V;
+    const uint32_t* I;
+    uint32_t max_leaf;
+    std::vector<Box> tbox;
+    std::vector<float> cent;  // 3 per triangle
+    std::vector<uint32_t> order;
+    std::vector<dr_bvh_node> nodes;
+
+    int levels_needed(uint32_t count) const {
+        int l = 0;
+        uint32_t c = max_leaf;
+        while (c < count) { c *= 2; ++l; }
+        return l;
+    }
+
+    void build(uint32_t first, uint32_t count, int depth, int me) {
+        Box b, cb;
+        for (uint32_t i = first; i < first + count; ++i) {
+            b.grow(tbox[order[i]]);
+            cb.grow(&cent[3 * order[i]]);
+        }
+        for (int a = 0; a < 3; ++a) { nodes[me].lo[a] = b.lo[a]; nodes[me].hi[a] = b.hi[a]; }
+        if (count <= max_leaf) {
+            nodes[me].a = ~(int32_t)first;
+            nodes[me].b = (int32_t)count;
+            return;
+        }
+        uint32_t mid = first + count / 2;
+        bool median = depth + 1 + levels_needed(count / 2 + 1) >= kMaxDepth;
+        if (!median) {
+            // SAH over binned centroids on all three axes
+            float best = INFINITY;
+            int best_axis = -1, best_split = 0;
+            for (int axis = 0; axis < 3; ++axis) {
+                const float ext = cb.hi[axis] - cb.lo[axis];
+                if (!(ext > 0)) continue;
+                Box bb[kBins];
+                uint32_t bc[kBins] = {0};
+                const float k = kBins * (1 - 1e-6f) / ext;
+                for (uint32_t i = first; i < first + count; ++i) {
+                    int bi = (int)((cent[3 * order[i] + axis] - cb.lo[axis]) * k);
+                    bi = std::min(std::max(bi, 0), kBins - 1);
+                    bc[bi]++;
+                    bb[bi].grow(tbox[order[i]]);
+                }
+                float ra[kBins];
+                uint32_t rc[kBins];
+                Box acc;
+                uint32_t cnt = 0;
+                for (int i = kBins - 1; i > 0; --i) {
+                    acc.grow(bb[i]);
+                    cnt += bc[i];
+                    ra[i] = acc.area();
+                    rc[i] = cnt;
+                }
+                Box lacc;
+                uint32_t lc = 0;
+                for (int i = 0; i < kBins - 1; ++i) {
+                    lacc.grow(bb[i]);
+                    lc += bc[i];
+                    if (lc == 0 || rc[i + 1] == 0) continue;
+                    const float cost = lacc.area() * lc + ra[i + 1] * rc[i + 1];
+                    if (cost < best) { best = cost; best_axis = axis; best_split = i; }
+                }
+            }
+            if (best_axis >= 0) {
+                const float ext = cb.hi[best_axis] - cb.lo[best_axis];
+                const float k = kBins * (1 - 1e-6f) / ext;
+                auto it = std::partition(order.begin() + first, order.begin() + first + count, [&](uint32_t t) {
+                    int bi = (int)((cent[3 * t + best_axis] - cb.lo[best_axis]) * k);
+                    bi = std::min(std::max(bi, 0), kBins - 1);
+                    return bi <= best_split;
+                });
+                mid = (uint32_t)(it - order.begin());
+                if (mid == first || mid == first + count) median = true;
+            } else {
+                median = true;
+            }
+        }
+        if (median) {
+            int axis = 0;
+            for (int a = 1; a < 3; ++a)
+                if (cb.hi[a] - cb.lo[a] > cb.hi[axis] - cb.lo[axis]) axis = a;
+            mid = first + count / 2;
+            std::nth_element(order.begin() + first, order.begin() + mid, order.begin() + first + count,
+                             [&](uint32_t x, uint32_t y) {
+                                 const float cx = cent[3 * x + axis], cy = cent[3 * y + axis];
+                                 return cx < cy || (cx == cy && x < y);
+                             });
+        }
+        const int l = (int)nodes.size();
+        nodes.emplace_back();
+        nodes.emplace_back();
+        nodes[me].a = l;
+        nodes[me].b = l + 1;
+        build(first, mid - first, depth + 1, l);
+        build(mid, first + count - mid, depth + 1, l + 1);
+    }
+};
+
+}  // namespace
+
+extern "C" dr_status dr_bvh_build_impl(const float* vertices, uint32_t n_vertices, const uint32_t* indices,
+                                       uint32_t n_triangles, uint32_t max_leaf, dr_bvh_node* nodes_out,
+                                       uint32_t* n_nodes_out, uint32_t* prim_order_out, const char** err) {
+    if (!vertices || !indices || !nodes_out || !n_nodes_out || !prim_order_out || n_triangles == 0) {
+        *err = "dr_bvh_build: null pointer or no triangles";
+        return DR_ERR_INVALID_ARG;
+    }
+    if (max_leaf < 1 || max_leaf > 16) {
+        *err = "dr_bvh_build: max_leaf must be in 1..16";
+        return DR_ERR_INVALID_ARG;
+    }
+    Builder B;
+    B.V = vertices;
+    B.I = indices;
+    B.max_leaf = max_leaf;
+    B.tbox.resize(n_triangles);
+    B.cent.resize(3 * (size_t)n_triangles);
+    B.order.resize(n_triangles);
+    for (uint32_t t = 0; t < n_triangles; ++t) {
+        for (int k = 0; k < 3; ++k) {
+            const uint32_t vi = indices[3 * (size_t)t + k];
+            if (vi >= n_vertices) {
+                *err = "dr_bvh_build: vertex index out of range";
+                return DR_ERR_INVALID_ARG;
+            }
+            B.tbox[t].grow(vertices + 3 * (size_t)vi);
+        }
+        for (int a = 0; a < 3; ++a) B.cent[3 * (size_t)t + a] = 0.5f * (B.tbox[t].lo[a] + B.tbox[t].hi[a]);
+        B.order[t] = t;
+    }
+    B.nodes.reserve(2 * (size_t)n_triangles);
+    B.nodes.emplace_back();
+    B.build(0, n_triangles, 0, 0);
+    std::memcpy(nodes_out, B.nodes.data(), B.nodes.size() * sizeof(dr_bvh_node));
+    std::memcpy(prim_order_out, B.order.data(), n_triangles * sizeof(uint32_t));
+    *n_nodes_out = (uint32_t)B.nodes.size();
+    return DR_OK;
+}

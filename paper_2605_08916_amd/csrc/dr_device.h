@@ -1,0 +1,433 @@
+// Device-side building blocks of the Diffusion Restore chain step (gfx950).
+//
+// Contents: small vector math, the Philox4x32-10 counter generator and the
+// stream layout, the scene's device layout, ray/box and ray/triangle tests,
+// BVH traversal with a per-lane stack in LDS, the materials, and the forward
+// evaluation of the path contribution f(u) that records the discrete choices
+// of the taken path.  The reverse-mode adjoint lives in dr_adjoint.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define DR_STACK 40       // traversal stack entries per lane (tree depth limit)
+#define DR_NO_VERTEX 0xFFFFFFFFu
+#define DR_PI 3.14159265358979323846f
+
+namespace dr {
+
+// ---------------------------------------------------------------------------
+// Vector math
+// ---------------------------------------------------------------------------
+struct V3 {
+    float x, y, z;
+};
+__host__ __device__ __forceinline__ V3 v3(float x, float y, float z) { return V3{x, y, z}; }
+__device__ __forceinline__ V3 operator+(V3 a, V3 b) { return v3(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ __forceinline__ V3 operator-(V3 a, V3 b) { return v3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ V3 operator-(V3 a) { return v3(-a.x, -a.y, -a.z); }
+__device__ __forceinline__ V3 operator*(V3 a, float s) { return v3(a.x * s, a.y * s, a.z * s); }
+__device__ __forceinline__ V3 mul(V3 a, V3 b) { return v3(a.x * b.x, a.y * b.y, a.z * b.z); }
+__device__ __forceinline__ float dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ V3 cross(V3 a, V3 b) {
+    return v3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ V3 normalize(V3 a) { return a * (1.0f / sqrtf(dot(a, a))); }
+__device__ __forceinline__ V3 xyz(float4 a) { return v3(a.x, a.y, a.z); }
+__device__ __forceinline__ float lum(V3 c) { return 0.2126f * c.x + 0.7152f * c.y + 0.0722f * c.z; }
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC 2011) and the stream layout:
+// counter = (chain, step lo, step hi, tag << 24 | i >> 2), key = seed,
+// uniform = top 24 bits of word i & 3 times 2^-24.
+// ---------------------------------------------------------------------------
+enum { TAG_REGEN = 0, TAG_GAUSS = 1, TAG_HOLD = 2, TAG_PT = 4 };
+
+__device__ __forceinline__ uint4 philox(uint4 c, uint2 k) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k.x += 0x9E3779B9u;
+            k.y += 0xBB67AE85u;
+        }
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
+        c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
+    }
+    return c;
+}
+__device__ __forceinline__ uint4 rng_block(uint64_t seed, uint32_t chain, uint64_t step, uint32_t tag, uint32_t blk) {
+    return philox(make_uint4(chain, (uint32_t)step, (uint32_t)(step >> 32), (tag << 24) | blk),
+                  make_uint2((uint32_t)seed, (uint32_t)(seed >> 32)));
+}
+__device__ __forceinline__ float u24(uint32_t w) { return (float)(w >> 8) * (1.0f / 16777216.0f); }
+
+// ---------------------------------------------------------------------------
+// Scene layout in HBM
+// ---------------------------------------------------------------------------
+// BVH node holding the boxes of its two children (64 B, one fetch per visit):
+//   box0 lo = a.xyz, hi = (a.w, b.x, b.y);  box1 lo = (b.z, b.w, c.x), hi = c.yzw
+//   d = (child0, child1, count0, count1): count > 0 leaf of `count` triangles
+//   starting at slot child; count == 0 inner node index child; count < 0 empty.
+struct alignas(64) DevNode {
+    float4 a, b, c;
+    int4 d;
+};
+// Triangle in leaf order (48 B): v0 | prim id bits, e1 = v1 - v0 | material
+// bits, e2 = v2 - v0 | 0.
+struct alignas(16) DevTri {
+    float4 v0, e1, e2;
+};
+// Material: m0 = (kind, albedo), m1 = (roughness, f0), m2 = (Le, 0).
+// Light: l0 = (p0, 0), l1 = (e1, 0), l2 = (e2, 0), l3 = (unit normal, area), l4 = (Le, 0).
+struct DevScene {
+    const DevNode* nodes;
+    const DevTri* tris;
+    const float4* mats;
+    const float4* lights;
+    int n_lights;
+    float tmin;
+    V3 eye, cu, cv, cw;  // camera ray direction = cw + (2u0-1) cu + (1-2u1) cv
+    int W, H;
+};
+
+struct Counters {
+    uint32_t rays, nodes, tris;
+};
+
+// ---------------------------------------------------------------------------
+// Ray queries
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float safe_rcp(float d) {
+    return 1.0f / (fabsf(d) < 1e-20f ? copysignf(1e-20f, d) : d);
+}
+
+// Slab test with a relative widening of the far distance so FP32 rounding
+// never culls a box whose triangles are hit (boxes are exact f32 bounds).
+__device__ __forceinline__ bool slab(float lx, float ly, float lz, float hx, float hy, float hz, V3 o, V3 inv,
+                                     float tmin, float tmax, float& tnear) {
+    const float tx0 = (lx - o.x) * inv.x, tx1 = (hx - o.x) * inv.x;
+    const float ty0 = (ly - o.y) * inv.y, ty1 = (hy - o.y) * inv.y;
+    const float tz0 = (lz - o.z) * inv.z, tz1 = (hz - o.z) * inv.z;
+    const float tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), tmin));
+    const float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fmaxf(tz0, tz1)) * 1.0000004f;
+    tnear = tn;
+    return tn <= fminf(tf, tmax);
+}
+
+// Moller-Trumbore, two-sided; t in (tmin, inf) before the caller's range test.
+__device__ __forceinline__ bool tri_test(const DevTri& T, V3 o, V3 d, float tmin, float& t) {
+    const V3 e1 = xyz(T.e1), e2 = xyz(T.e2);
+    const V3 pv = cross(d, e2);
+    const float det = dot(e1, pv);
+    if (det == 0.0f) return false;
+    const float inv = 1.0f / det;
+    const V3 tv = o - xyz(T.v0);
+    const float b1 = dot(tv, pv) * inv;
+    if (b1 < 0.0f || b1 > 1.0f) return false;
+    const V3 qv = cross(tv, e1);
+    const float b2 = dot(d, qv) * inv;
+    if (b2 < 0.0f || b1 + b2 > 1.0f) return false;
+    t = dot(e2, qv) * inv;
+    return t > tmin;
+}
+
+__device__ __forceinline__ DevNode load_node(const DevNode* nodes, int i) {
+    const float4* p = reinterpret_cast<const float4*>(nodes + i);
+    DevNode n;
+    n.a = p[0];
+    n.b = p[1];
+    n.c = p[2];
+    n.d = reinterpret_cast<const int4*>(p)[3];
+    return n;
+}
+
+// Closest hit over (tmin, tmax); ties in t go to the lower input triangle
+// index.  Returns the triangle slot (leaf order) or -1.  stk: this lane's LDS
+// stack, entries at stk[k * stride].
+__device__ int trace_closest(const DevScene& S, V3 o, V3 d, float tmax, float& t_hit, uint32_t* stk, int stride,
+                             Counters& ctr) {
+    const V3 inv = v3(safe_rcp(d.x), safe_rcp(d.y), safe_rcp(d.z));
+    float bt = tmax;
+    int best = -1;
+    uint32_t best_prim = 0xFFFFFFFFu;
+    int sp = 0;
+    int node = 0;
+    ctr.rays++;
+    while (true) {
+        const DevNode n = load_node(S.nodes, node);
+        ctr.nodes++;
+        float tn0, tn1;
+        bool h0 = n.d.z >= 0 && slab(n.a.x, n.a.y, n.a.z, n.a.w, n.b.x, n.b.y, o, inv, S.tmin, bt, tn0);
+        bool h1 = n.d.w >= 0 && slab(n.b.z, n.b.w, n.c.x, n.c.y, n.c.z, n.c.w, o, inv, S.tmin, bt, tn1);
+        // leaves are tested on the spot
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const bool h = side ? h1 : h0;
+            const int cnt = side ? n.d.w : n.d.z;
+            const int first = side ? n.d.y : n.d.x;
+            if (h && cnt > 0) {
+                for (int k = first; k < first + cnt; ++k) {
+                    const DevTri T = S.tris[k];
+                    ctr.tris++;
+                    float t;
+                    if (tri_test(T, o, d, S.tmin, t)) {
+                        const uint32_t prim = __float_as_uint(T.v0.w);
+                        if (t < bt || (t == bt && prim < best_prim)) {
+                            bt = t;
+                            best = k;
+                            best_prim = prim;
+                        }
+                    }
+                }
+            }
+        }
+        h0 = h0 && n.d.z == 0;
+        h1 = h1 && n.d.w == 0;
+        if (h0 && h1) {
+            const bool first0 = tn0 <= tn1;
+            if (sp < DR_STACK) stk[(sp++) * stride] = (uint32_t)(first0 ? n.d.y : n.d.x);
+            node = first0 ? n.d.x : n.d.y;
+        } else if (h0) {
+            node = n.d.x;
+        } else if (h1) {
+            node = n.d.y;
+        } else {
+            if (sp == 0) break;
+            node = (int)stk[(--sp) * stride];
+        }
+    }
+    t_hit = bt;
+    return best;
+}
+
+// Any hit in the open interval (tmin, tmax).
+__device__ bool trace_any(const DevScene& S, V3 o, V3 d, float tmax, uint32_t* stk, int stride, Counters& ctr) {
+    const V3 inv = v3(safe_rcp(d.x), safe_rcp(d.y), safe_rcp(d.z));
+    int sp = 0;
+    int node = 0;
+    ctr.rays++;
+    while (true) {
+        const DevNode n = load_node(S.nodes, node);
+        ctr.nodes++;
+        float tn0, tn1;
+        bool h0 = n.d.z >= 0 && slab(n.a.x, n.a.y, n.a.z, n.a.w, n.b.x, n.b.y, o, inv, S.tmin, tmax, tn0);
+        bool h1 = n.d.w >= 0 && slab(n.b.z, n.b.w, n.c.x, n.c.y, n.c.z, n.c.w, o, inv, S.tmin, tmax, tn1);
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const bool h = side ? h1 : h0;
+            const int cnt = side ? n.d.w : n.d.z;
+            const int first = side ? n.d.y : n.d.x;
+            if (h && cnt > 0) {
+                for (int k = first; k < first + cnt; ++k) {
+                    ctr.tris++;
+                    float t;
+                    if (tri_test(S.tris[k], o, d, S.tmin, t) && t < tmax) return true;
+                }
+            }
+        }
+        h0 = h0 && n.d.z == 0;
+        h1 = h1 && n.d.w == 0;
+        if (h0 && h1) {
+            const bool first0 = tn0 <= tn1;
+            if (sp < DR_STACK) stk[(sp++) * stride] = (uint32_t)(first0 ? n.d.y : n.d.x);
+            node = first0 ? n.d.x : n.d.y;
+        } else if (h0) {
+            node = n.d.x;
+        } else if (h1) {
+            node = n.d.y;
+        } else {
+            if (sp == 0) break;
+            node = (int)stk[(--sp) * stride];
+        }
+    }
+    return false;
+}
+
+// ---------------------------------------------------------------------------
+// Surfaces
+// ---------------------------------------------------------------------------
+// Unit geometric normal of a triangle, flipped to face the incoming direction.
+__device__ __forceinline__ V3 facing_normal(const DevTri& T, V3 din) {
+    const V3 ng = normalize(cross(xyz(T.e1), xyz(T.e2)));
+    return dot(ng, din) > 0.0f ? -ng : ng;
+}
+
+// Orthonormal basis around a unit normal (Duff et al., JCGT 2017).
+__device__ __forceinline__ void onb(V3 n, V3& t, V3& b) {
+    const float sign = copysignf(1.0f, n.z);
+    const float a = -1.0f / (sign + n.z);
+    const float bb = n.x * n.y * a;
+    t = v3(1.0f + sign * n.x * n.x * a, sign * bb, -sign * n.x);
+    b = v3(bb, sign + n.y * n.y * a, -n.y);
+}
+
+// Separable Smith masking for GGX: G1(c) = 2 / (1 + sqrt(1 + a2 (1 - c^2)/c^2)).
+__device__ __forceinline__ float smith_g1(float c, float a2) {
+    const float c2 = c * c;
+    return 2.0f / (1.0f + sqrtf(1.0f + a2 * (1.0f - c2) / c2));
+}
+
+struct Material {
+    int kind;
+    V3 albedo, f0, Le;
+    float a2;  // GGX alpha^2
+};
+__device__ __forceinline__ Material load_material(const DevScene& S, uint32_t id) {
+    const float4 m0 = S.mats[3 * id], m1 = S.mats[3 * id + 1], m2 = S.mats[3 * id + 2];
+    Material m;
+    m.kind = (int)m0.x;
+    m.albedo = v3(m0.y, m0.z, m0.w);
+    m.a2 = m1.x * m1.x;
+    m.f0 = v3(m1.y, m1.z, m1.w);
+    m.Le = xyz(m2);
+    return m;
+}
+
+// f_s(wo, wi) for n.wo > 0, n.wi > 0.
+__device__ __forceinline__ V3 bsdf_eval(const Material& m, V3 n, V3 wo, V3 wi) {
+    if (m.kind == 0) return m.albedo * (1.0f / DR_PI);
+    const float co = dot(n, wo), ci = dot(n, wi);
+    const V3 h = normalize(wo + wi);
+    const float ch = dot(n, h);
+    const float den = ch * ch * (m.a2 - 1.0f) + 1.0f;
+    const float D = m.a2 / (DR_PI * den * den);
+    const float G = smith_g1(co, m.a2) * smith_g1(ci, m.a2);
+    const float oh = dot(wi, h);
+    const float om = 1.0f - oh;
+    const float f5 = om * om * om * om * om;
+    const float k = D * G / (4.0f * co * ci);
+    return v3(k * (m.f0.x + (1.0f - m.f0.x) * f5), k * (m.f0.y + (1.0f - m.f0.y) * f5),
+              k * (m.f0.z + (1.0f - m.f0.z) * f5));
+}
+
+// Sample wi from the 2-D block (u, v); weight = f_s cos / pdf.  False when the
+// sample leaves the upper hemisphere (the path ends).
+__device__ __forceinline__ bool bsdf_sample(const Material& m, V3 n, V3 wo, float u, float v, V3& wi, V3& weight) {
+    V3 t, b;
+    onb(n, t, b);
+    float sp, cp;
+    __sincosf(2.0f * DR_PI * v, &sp, &cp);
+    if (m.kind == 0) {
+        const float r = sqrtf(u), lz = sqrtf(1.0f - u);
+        wi = t * (r * cp) + b * (r * sp) + n * lz;
+        weight = m.albedo;
+        return true;
+    }
+    const float den = (1.0f - u) + m.a2 * u;
+    const float ch = sqrtf((1.0f - u) / den);
+    const float sh = sqrtf(m.a2 * u / den);
+    const V3 h = t * (sh * cp) + b * (sh * sp) + n * ch;
+    const float oh = dot(wo, h);
+    if (oh <= 0.0f) return false;
+    wi = h * (2.0f * oh) - wo;
+    const float ci = dot(n, wi);
+    if (ci <= 0.0f) return false;
+    const float co = dot(n, wo);
+    const float g = smith_g1(co, m.a2) * smith_g1(ci, m.a2) * oh / (co * ch);
+    const float om = 1.0f - oh;
+    const float f5 = om * om * om * om * om;
+    weight = v3(g * (m.f0.x + (1.0f - m.f0.x) * f5), g * (m.f0.y + (1.0f - m.f0.y) * f5),
+                g * (m.f0.z + (1.0f - m.f0.z) * f5));
+    return true;
+}
+
+// Light selection from the first coordinate of the light block, in FP32.
+__device__ __forceinline__ int select_light(float a, int nl, float& ap) {
+    const float sel = a * (float)nl;
+    int li = (int)floorf(sel);
+    if (li > nl - 1) li = nl - 1;
+    ap = a * (float)nl - (float)li;
+    return li;
+}
+
+// Camera ray direction for the film block.
+__device__ __forceinline__ V3 camera_dir(const DevScene& S, float u0, float u1) {
+    return normalize(S.cw + S.cu * (2.0f * u0 - 1.0f) + S.cv * (1.0f - 2.0f * u1));
+}
+
+// Pixel of the film block, in FP32: px = min(floor(u0 W), W-1), row 0 at top.
+__device__ __forceinline__ uint32_t pixel_of(const DevScene& S, float u0, float u1) {
+    int px = (int)floorf(u0 * (float)S.W), py = (int)floorf(u1 * (float)S.H);
+    px = min(max(px, 0), S.W - 1);
+    py = min(max(py, 0), S.H - 1);
+    return (uint32_t)(py * S.W + px);
+}
+
+// ---------------------------------------------------------------------------
+// Forward path contribution with next-event estimation.
+// U is an accessor: float operator()(int i) returns coordinate i of u.
+// rec (nullable): per vertex j = 1..L-1, rec[(j-1) * rs] = slot << 8 |
+// light << 1 | contributed, or DR_NO_VERTEX.
+// ---------------------------------------------------------------------------
+template <class U>
+__device__ V3 path_forward(const DevScene& S, int L, const U& u, uint32_t* rec, int rs, uint32_t* stk, int stride,
+                           Counters& ctr) {
+    V3 f = v3(0.f, 0.f, 0.f);
+    V3 d = camera_dir(S, u(0), u(1));
+    V3 x;
+    float t;
+    int slot = trace_closest(S, S.eye, d, INFINITY, t, stk, stride, ctr);
+    int j = 1;
+    if (slot >= 0) {
+        x = S.eye + d * t;
+        DevTri T = S.tris[slot];
+        {
+            const Material m = load_material(S, __float_as_uint(T.e1.w));
+            if (dot(cross(xyz(T.e1), xyz(T.e2)), d) < 0.0f) f = f + m.Le;
+        }
+        V3 beta = v3(1.f, 1.f, 1.f);
+        const int nl = S.n_lights;
+        for (; j <= L - 1; ++j) {
+            const Material m = load_material(S, __float_as_uint(T.e1.w));
+            const V3 n = facing_normal(T, d);
+            const V3 wo = -d;
+            // next-event estimation
+            float ap;
+            const float a = u(4 * j - 2), b = u(4 * j - 1);
+            const int li = select_light(a, nl, ap);
+            const float4 l0 = S.lights[5 * li], l1 = S.lights[5 * li + 1], l2 = S.lights[5 * li + 2],
+                         l3 = S.lights[5 * li + 3], l4 = S.lights[5 * li + 4];
+            const V3 y = xyz(l0) + xyz(l1) * ap + xyz(l2) * b;
+            const V3 w = y - x;
+            const float r2 = dot(w, w);
+            const float r = sqrtf(r2);
+            const V3 wl = w * (1.0f / r);
+            const float cx = dot(n, wl);
+            const float cy = -dot(xyz(l3), wl);
+            bool contrib = cx > 0.0f && cy > 0.0f;
+            if (contrib) contrib = !trace_any(S, x, wl, (1.0f - 1e-4f) * r, stk, stride, ctr);
+            if (rec) rec[(j - 1) * rs] = ((uint32_t)slot << 8) | ((uint32_t)li << 1) | (contrib ? 1u : 0u);
+            if (contrib) {
+                const V3 fs = bsdf_eval(m, n, wo, wl);
+                const float g = cx * cy / r2 * ((float)nl * l3.w);
+                f = f + mul(mul(beta, fs), xyz(l4)) * g;
+            }
+            if (j == L - 1) break;
+            if (beta.x == 0.0f && beta.y == 0.0f && beta.z == 0.0f) break;
+            V3 wi, wt;
+            if (!bsdf_sample(m, n, wo, u(4 * j), u(4 * j + 1), wi, wt)) break;
+            beta = mul(beta, wt);
+            float tn;
+            const int ns = trace_closest(S, x, wi, INFINITY, tn, stk, stride, ctr);
+            if (ns < 0) break;
+            x = x + wi * tn;
+            d = wi;
+            slot = ns;
+            T = S.tris[slot];
+        }
+        ++j;
+    }
+    if (rec)
+        for (; j <= L - 1; ++j) rec[(j - 1) * rs] = DR_NO_VERTEX;
+    return f;
+}
+
+// Coordinate accessors
+struct SoaU {  // chain state: coordinate i at p[i * stride]
+    const float* p;
+    int stride;
+    __device__ __forceinline__ float operator()(int i) const { return p[(size_t)i * stride]; }
+};
+
+}  // namespace dr

@@ -1,0 +1,1124 @@
+// Diffusion Restore chain-step library: kernels and the C ABI (include/dr.h).
+//
+// Two forms of the evolve step run the same arithmetic and draw the same
+// Philox streams:
+//  * fused: one persistent kernel per dr_step.  Wavefronts pull chains from a
+//    device work queue (one atomic per wavefront pop, ballot-compacted), and
+//    each lane runs its chain's steps: regenerate or move, one forward path
+//    trace, hold/kill, splat, and, for survivors, the reverse-mode adjoint that
+//    yields the score used by the next move.  One traversal per chain-step.
+//  * plain: the paper's pass structure as separate kernels with the state
+//    round-tripping through HBM: score (a forward trace plus the adjoint at the
+//    current state, Alg. 5.1 line 1), move/regenerate, forward trace at the new
+//    state (Accumulate), hold/kill/splat.  Two traversals per chain-step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/dr.h"
+#include "dr_adjoint.h"
+#include "dr_device.h"
+
+using namespace dr;
+
+extern "C" dr_status dr_bvh_build_impl(const float* vertices, uint32_t n_vertices, const uint32_t* indices,
+                                       uint32_t n_triangles, uint32_t max_leaf, dr_bvh_node* nodes_out,
+                                       uint32_t* n_nodes_out, uint32_t* prim_order_out, const char** err);
+
+// ===========================================================================
+// Kernel-side parameter blocks
+// ===========================================================================
+struct KParams {
+    uint64_t seed;
+    int N, L, d;
+    float stddev, dt, gt, eps;  // gt = gamma tilde = dt gamma / 2
+    int rb, record, count;
+};
+
+struct KBufs {
+    float* x;            // d x N
+    float* score;        // d x N
+    uint32_t* killed;    // N
+    uint32_t* rec;       // (L-1) x N, triangle slots
+    float* accum;        // 3 x W*H, sum of (w/dt) f/p
+    unsigned long long* ctr;  // [0] tours, [1] chain steps, [2] rays, [3] nodes, [4] tris, [5] adjoints
+    float* k0;           // device scalar (float) ; k0d at ((double*)k0ptr)
+    double* k0d;
+    double* plam;        // p_lambda estimate
+    const float* sigma;  // d x N or null
+    uint32_t* queue;
+    // per-chain scratch and record
+    float* p_tmp;        // N
+    float* f_tmp;        // 3 x N
+    uint32_t* pix_tmp;   // N
+    float* r_w;          // N (record)
+    double* partial;     // reduction partials
+    float* img;          // 3 x W*H resolved image (dr_image_read)
+};
+
+enum { C_TOURS = 0, C_STEPS = 1, C_RAYS = 2, C_NODES = 3, C_TRIS = 4, C_ADJ = 5, C_N = 8 };
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Add a per-lane count to a global counter with one atomic per wavefront.
+// Must be called by all active lanes of the wavefront together.
+__device__ __forceinline__ void wave_add(unsigned long long* dst, uint32_t v) {
+    const uint32_t s = wave_sum(v);
+    const uint64_t act = __ballot(1);
+    if ((threadIdx.x & 63) == (uint32_t)(__ffsll((long long)act) - 1) && s) atomicAdd(dst, (unsigned long long)s);
+}
+
+// ---------------------------------------------------------------------------
+// Chain-state pieces (Alg. 4.1, 4.2, 5.1)
+// ---------------------------------------------------------------------------
+// x ~ uniform on the torus.
+__device__ __forceinline__ void regen(const KParams& P, float* x, int c, uint64_t s) {
+    for (int b = 0; b < P.d / 4; ++b) {
+        const uint4 r = rng_block(P.seed, (uint32_t)c, s, TAG_REGEN, (uint32_t)b);
+        x[(size_t)(4 * b + 0) * P.N] = u24(r.x);
+        x[(size_t)(4 * b + 1) * P.N] = u24(r.y);
+        x[(size_t)(4 * b + 2) * P.N] = u24(r.z);
+        x[(size_t)(4 * b + 3) * P.N] = u24(r.w);
+    }
+}
+
+__device__ __forceinline__ float wrap01(float y) {
+    y -= floorf(y);
+    return y >= 1.0f ? 0.0f : y;
+}
+
+// Euler-Maruyama move with rotational drift, per 2-D block (Alg. 5.1):
+// x += (sd^2/2) s + gt (s2, -s1) + sd xi, then wrap to the torus.
+__device__ __forceinline__ void move(const KParams& P, float* x, const float* score, const float* sigma, int c,
+                                     uint64_t s) {
+    for (int b = 0; b < P.d / 4; ++b) {
+        const uint4 r = rng_block(P.seed, (uint32_t)c, s, TAG_GAUSS, (uint32_t)b);
+        const float uu[4] = {u24(r.x), u24(r.y), u24(r.z), u24(r.w)};
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int i0 = 4 * b + 2 * q, i1 = i0 + 1;
+            const float rad = sqrtf(-2.0f * logf(1.0f - uu[2 * q]));
+            float sn, cs;
+            sincosf(2.0f * DR_PI * uu[2 * q + 1], &sn, &cs);
+            const float xi0 = rad * cs, xi1 = rad * sn;
+            const size_t a0 = (size_t)i0 * P.N, a1 = (size_t)i1 * P.N;
+            const float s0 = score[a0], s1 = score[a1];
+            const float sd0 = sigma ? sigma[a0] : P.stddev;
+            const float sd1 = sigma ? sigma[a1] : P.stddev;
+            const float y0 = x[a0] + 0.5f * sd0 * sd0 * s0 + P.gt * s1 + sd0 * xi0;
+            const float y1 = x[a1] + 0.5f * sd1 * sd1 * s1 - P.gt * s0 + sd1 * xi1;
+            x[a0] = wrap01(y0);
+            x[a1] = wrap01(y1);
+        }
+    }
+}
+
+// Hold/kill and splat (Accumulate).  Returns true if the tour survives.
+__device__ __forceinline__ bool hold_kill_splat(const KParams& P, const KBufs& B, const DevScene& S, int c, uint64_t s,
+                                                float k0, V3 f, float p, uint32_t pix) {
+    const uint4 r = rng_block(P.seed, (uint32_t)c, s, TAG_HOLD, 0);
+    const float Ea = -logf(1.0f - u24(r.x));
+    const float Eb = -logf(1.0f - u24(r.y));
+    const float k = k0 / (p + P.eps);
+    const bool alive = (k * P.dt) * Ea < Eb;
+    // splat weight in units of dt: RB 1/(1 + k dt), or the sampled min
+    const float wdt = P.rb ? 1.0f / (1.0f + k * P.dt) : fminf(Ea, Eb / (k * P.dt));
+    if (p > 0.0f) {
+        const float sc = wdt / p;
+        const size_t npx = (size_t)S.W * S.H;
+        atomicAdd(&B.accum[pix], sc * f.x);
+        atomicAdd(&B.accum[npx + pix], sc * f.y);
+        atomicAdd(&B.accum[2 * npx + pix], sc * f.z);
+    }
+    if (P.record) {
+        B.p_tmp[c] = p;
+        B.r_w[c] = wdt * P.dt;
+        B.pix_tmp[c] = pix;
+        B.f_tmp[c] = p > 0.0f ? f.x / p : 0.0f;
+        B.f_tmp[(size_t)P.N + c] = p > 0.0f ? f.y / p : 0.0f;
+        B.f_tmp[(size_t)2 * P.N + c] = p > 0.0f ? f.z / p : 0.0f;
+    }
+    return alive;
+}
+
+template <int L>
+__device__ __forceinline__ void score_at(const KParams& P, const KBufs& B, const DevScene& S, int c, float p) {
+    path_score<L>(S, SoaU{B.x + c, P.N}, B.rec + c, P.N, p, P.eps, B.score + c, P.N);
+}
+
+// ===========================================================================
+// Kernels
+// ===========================================================================
+__global__ void k_fill_u32(uint32_t* a, size_t n, uint32_t v) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) a[i] = v;
+}
+__global__ void k_fill_f32(float* a, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) a[i] = 0.f;
+}
+__global__ void k_fill_u64(unsigned long long* a, int n) {
+    if (threadIdx.x < (unsigned)n) a[threadIdx.x] = 0ull;
+}
+
+// Initialise, phase 1: x ~ mu and f(x) for every chain (Alg. 4.1).
+__global__ void __launch_bounds__(256) k_init_eval(KParams P, DevScene S, KBufs B, uint64_t s0) {
+    extern __shared__ uint32_t s_stack[];
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    Counters ctr = {0, 0, 0};
+    if (c < P.N) {
+        regen(P, B.x + c, c, s0);
+        const V3 f = path_forward(S, P.L, SoaU{B.x + c, P.N}, B.rec + c, P.N, s_stack + threadIdx.x, blockDim.x, ctr);
+        B.p_tmp[c] = lum(f);
+        B.f_tmp[c] = f.x;
+        B.f_tmp[(size_t)P.N + c] = f.y;
+        B.f_tmp[(size_t)2 * P.N + c] = f.z;
+        B.pix_tmp[c] = pixel_of(S, B.x[c], B.x[(size_t)P.N + c]);
+    }
+    if (P.count) {
+        wave_add(&B.ctr[C_RAYS], ctr.rays);
+        wave_add(&B.ctr[C_NODES], ctr.nodes);
+        wave_add(&B.ctr[C_TRIS], ctr.tris);
+    }
+}
+
+// Sum of p over chains in FP64: per-block partials, then one block in order.
+__global__ void k_reduce_p(KParams P, KBufs B) {
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < P.N; c += gridDim.x * blockDim.x) acc += (double)B.p_tmp[c];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) B.partial[blockIdx.x] = sh[0];
+}
+// p_lambda estimate and k0 = p_lambda/(m dt) (Eq. killing-rate-constant),
+// unless k0_given > 0; p_lambda = 0 falls back to eps/(m dt).
+__global__ void k_finish_k0(KParams P, KBufs B, int nparts, double k0_given, double m) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int i = 0; i < nparts; ++i) s += B.partial[i];
+    const double pl = s / (double)P.N;
+    *B.plam = pl;
+    double k0 = k0_given;
+    if (!(k0 > 0.0)) k0 = pl > 0.0 ? pl / (m * (double)P.dt) : (double)P.eps / (m * (double)P.dt);
+    *B.k0d = k0;
+    *B.k0 = (float)k0;
+}
+
+// Initialise, phase 2: hold/kill/splat with the final k0, then scores.
+template <int L>
+__global__ void __launch_bounds__(256) k_init_accumulate(KParams P, DevScene S, KBufs B, uint64_t s0, int with_score) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t kill = 0, adj = 0;
+    if (c < P.N) {
+        const float p = B.p_tmp[c];
+        const V3 f = v3(B.f_tmp[c], B.f_tmp[(size_t)P.N + c], B.f_tmp[(size_t)2 * P.N + c]);
+        const bool alive = hold_kill_splat(P, B, S, c, s0, *B.k0, f, p, B.pix_tmp[c]);
+        B.killed[c] = alive ? 0u : 1u;
+        kill = alive ? 0u : 1u;
+        if (alive && with_score) {
+            score_at<L>(P, B, S, c, p);
+            adj = 1;
+        }
+    }
+    wave_add(&B.ctr[C_TOURS], kill);
+    if (P.count) {
+        wave_add(&B.ctr[C_STEPS], c < P.N ? 1u : 0u);
+        wave_add(&B.ctr[C_ADJ], adj);
+    }
+}
+
+// Fused persistent evolve step: every chain advances nsteps steps.
+template <int L>
+__global__ void __launch_bounds__(256) k_step_fused(KParams P, DevScene S, KBufs B, uint64_t s0, uint32_t nsteps) {
+    extern __shared__ uint32_t s_stack[];
+    uint32_t* stk = s_stack + threadIdx.x;
+    const int stride = blockDim.x;
+    const int lane = threadIdx.x & 63;
+    const float k0 = *B.k0;
+    int c = -1;
+    uint32_t k = nsteps;
+    Counters ctr = {0, 0, 0};
+    uint32_t kills = 0, steps = 0, adj = 0;
+    while (true) {
+        // refill lanes whose chain is finished: one queue atomic per wavefront
+        const bool need = k >= nsteps;
+        const uint64_t mask = __ballot(need);
+        if (mask) {
+            const int leader = __ffsll((long long)mask) - 1;
+            uint32_t base = 0;
+            if (lane == leader) base = atomicAdd(B.queue, (uint32_t)__popcll(mask));
+            base = __shfl(base, leader);
+            if (need) {
+                c = (int)(base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull)));
+                k = 0;
+            }
+        }
+        const bool active = c < P.N;
+        if (!__any(active)) break;
+        if (active) {
+            const uint64_t s = s0 + k;
+            float* xc = B.x + c;
+            if (B.killed[c]) regen(P, xc, c, s);
+            else move(P, xc, B.score + c, B.sigma ? B.sigma + c : nullptr, c, s);
+            const SoaU u{xc, P.N};
+            const V3 f = path_forward(S, L, u, B.rec + c, P.N, stk, stride, ctr);
+            const float p = lum(f);
+            const uint32_t pix = pixel_of(S, xc[0], xc[P.N]);
+            const bool alive = hold_kill_splat(P, B, S, c, s, k0, f, p, pix);
+            B.killed[c] = alive ? 0u : 1u;
+            kills += alive ? 0u : 1u;
+            if (alive) {
+                score_at<L>(P, B, S, c, p);
+                ++adj;
+            }
+            ++k;
+            ++steps;
+        } else {
+            k = 0;  // drained lanes stop asking for work
+        }
+    }
+    wave_add(&B.ctr[C_TOURS], kills);
+    if (P.count) {
+        wave_add(&B.ctr[C_STEPS], steps);
+        wave_add(&B.ctr[C_ADJ], adj);
+        wave_add(&B.ctr[C_RAYS], ctr.rays);
+        wave_add(&B.ctr[C_NODES], ctr.nodes);
+        wave_add(&B.ctr[C_TRIS], ctr.tris);
+    }
+}
+
+// ---- plain multi-kernel form -------------------------------------------------
+// score = grad ln(p + eps) at the current state of every live chain.
+template <int L>
+__global__ void __launch_bounds__(256) k_plain_score(KParams P, DevScene S, KBufs B) {
+    extern __shared__ uint32_t s_stack[];
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    Counters ctr = {0, 0, 0};
+    uint32_t adj = 0;
+    if (c < P.N && !B.killed[c]) {
+        const SoaU u{B.x + c, P.N};
+        const V3 f = path_forward(S, L, u, B.rec + c, P.N, s_stack + threadIdx.x, blockDim.x, ctr);
+        score_at<L>(P, B, S, c, lum(f));
+        adj = 1;
+    }
+    if (P.count) {
+        wave_add(&B.ctr[C_ADJ], adj);
+        wave_add(&B.ctr[C_RAYS], ctr.rays);
+        wave_add(&B.ctr[C_NODES], ctr.nodes);
+        wave_add(&B.ctr[C_TRIS], ctr.tris);
+    }
+}
+__global__ void __launch_bounds__(256) k_plain_move(KParams P, KBufs B, uint64_t s) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= P.N) return;
+    if (B.killed[c]) regen(P, B.x + c, c, s);
+    else move(P, B.x + c, B.score + c, B.sigma ? B.sigma + c : nullptr, c, s);
+}
+__global__ void __launch_bounds__(256) k_plain_forward(KParams P, DevScene S, KBufs B) {
+    extern __shared__ uint32_t s_stack[];
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    Counters ctr = {0, 0, 0};
+    if (c < P.N) {
+        const V3 f = path_forward(S, P.L, SoaU{B.x + c, P.N}, B.rec + c, P.N, s_stack + threadIdx.x, blockDim.x, ctr);
+        B.p_tmp[c] = lum(f);
+        B.f_tmp[c] = f.x;
+        B.f_tmp[(size_t)P.N + c] = f.y;
+        B.f_tmp[(size_t)2 * P.N + c] = f.z;
+        B.pix_tmp[c] = pixel_of(S, B.x[c], B.x[(size_t)P.N + c]);
+    }
+    if (P.count) {
+        wave_add(&B.ctr[C_RAYS], ctr.rays);
+        wave_add(&B.ctr[C_NODES], ctr.nodes);
+        wave_add(&B.ctr[C_TRIS], ctr.tris);
+    }
+}
+__global__ void __launch_bounds__(256) k_plain_accumulate(KParams P, DevScene S, KBufs B, uint64_t s) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t kill = 0;
+    if (c < P.N) {
+        const float p = B.p_tmp[c];
+        const V3 f = v3(B.f_tmp[c], B.f_tmp[(size_t)P.N + c], B.f_tmp[(size_t)2 * P.N + c]);
+        const bool alive = hold_kill_splat(P, B, S, c, s, *B.k0, f, p, B.pix_tmp[c]);
+        B.killed[c] = alive ? 0u : 1u;
+        kill = alive ? 0u : 1u;
+    }
+    wave_add(&B.ctr[C_TOURS], kill);
+    if (P.count) wave_add(&B.ctr[C_STEPS], c < P.N ? 1u : 0u);
+}
+
+// Resolve (Alg. 4.3): img = W H k0 accum / tourCount; accum is in units of dt.
+__global__ void k_resolve(const float* accum, float* img, size_t npx, const double* k0d, const unsigned long long* ctr,
+                          double dt) {
+    const unsigned long long tours = ctr[C_TOURS];
+    const float scale = tours ? (float)((double)npx * (*k0d) * dt / (double)tours) : 0.0f;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < 3 * npx; i += (size_t)gridDim.x * blockDim.x)
+        img[i] = scale * accum[i];
+}
+
+// Path evaluation for n points (row-major n x d): f, log(p + eps), score, record.
+struct RowU {
+    const float* p;
+    __device__ __forceinline__ float operator()(int i) const { return p[i]; }
+};
+template <int L>
+__global__ void __launch_bounds__(256) k_eval(DevScene S, const float* u, int n, float eps, float* fo, float* logp, float* grad,
+                       uint32_t* rec_scratch, uint32_t* rec_out) {
+    extern __shared__ uint32_t s_stack[];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    constexpr int d = 4 * (L - 1);
+    Counters ctr = {0, 0, 0};
+    const RowU uu{u + (size_t)i * d};
+    uint32_t* rc = rec_scratch + i;
+    const V3 f = path_forward(S, L, uu, rc, n, s_stack + threadIdx.x, blockDim.x, ctr);
+    const float p = lum(f);
+    if (fo) {
+        fo[3 * (size_t)i] = f.x;
+        fo[3 * (size_t)i + 1] = f.y;
+        fo[3 * (size_t)i + 2] = f.z;
+    }
+    if (logp) logp[i] = logf(p + eps);
+    if (grad) path_score<L>(S, uu, rc, n, p, eps, grad + (size_t)i * d, 1);
+    if (rec_out)
+        for (int j = 0; j < L - 1; ++j) {
+            const uint32_t r = rc[(size_t)j * n];
+            rec_out[(size_t)i * (L - 1) + j] =
+                r == DR_NO_VERTEX ? r : ((__float_as_uint(S.tris[r >> 8].v0.w) << 8) | (r & 0xFFu));
+        }
+}
+
+// Independent path tracing, one thread per pixel.
+struct PtU {
+    uint64_t seed;
+    uint32_t pix;
+    uint64_t k;
+    int W, H, px, py;
+    __device__ __forceinline__ float operator()(int i) const {
+        const uint4 r = rng_block(seed, pix, k, TAG_PT, (uint32_t)(i >> 2));
+        const uint32_t w = (i & 3) == 0 ? r.x : ((i & 3) == 1 ? r.y : ((i & 3) == 2 ? r.z : r.w));
+        const float v = u24(w);
+        if (i == 0) return ((float)px + v) / (float)W;
+        if (i == 1) return ((float)py + v) / (float)H;
+        return v;
+    }
+};
+__global__ void __launch_bounds__(256) k_pt(DevScene S, int L, uint64_t seed, uint32_t spp, float* img) {
+    extern __shared__ uint32_t s_stack[];
+    const int pix = blockIdx.x * blockDim.x + threadIdx.x;
+    const int npx = S.W * S.H;
+    if (pix >= npx) return;
+    Counters ctr = {0, 0, 0};
+    V3 acc = v3(0.f, 0.f, 0.f);
+    for (uint32_t k = 0; k < spp; ++k) {
+        const PtU u{seed, (uint32_t)pix, (uint64_t)k, S.W, S.H, pix % S.W, pix / S.W};
+        acc = acc + path_forward(S, L, u, nullptr, 0, s_stack + threadIdx.x, blockDim.x, ctr);
+    }
+    const float inv = 1.0f / (float)spp;
+    img[pix] = acc.x * inv;
+    img[npx + pix] = acc.y * inv;
+    img[2 * npx + pix] = acc.z * inv;
+}
+
+// ===========================================================================
+// Host side
+// ===========================================================================
+namespace {
+thread_local std::string g_err;
+
+dr_status fail(dr_status s, const std::string& msg) {
+    g_err = msg;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                                  \
+    do {                                                                                               \
+        hipError_t e_ = (expr);                                                                        \
+        if (e_ != hipSuccess) return fail(DR_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+struct DevAlloc {
+    std::vector<void*> ptrs;
+    hipError_t get(void** p, size_t bytes) {
+        hipError_t e = hipMalloc(p, bytes ? bytes : 4);
+        if (e == hipSuccess) ptrs.push_back(*p);
+        return e;
+    }
+    void release() {
+        for (void* p : ptrs) (void)hipFree(p);
+        ptrs.clear();
+    }
+};
+
+void camera_basis(const dr_camera& c, DevScene& S) {
+    double eye[3] = {c.eye[0], c.eye[1], c.eye[2]}, at[3] = {c.at[0], c.at[1], c.at[2]}, up[3] = {c.up[0], c.up[1], c.up[2]};
+    double w[3] = {eye[0] - at[0], eye[1] - at[1], eye[2] - at[2]};
+    double wl = std::sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+    for (double& v : w) v /= wl;
+    double u[3] = {up[1] * w[2] - up[2] * w[1], up[2] * w[0] - up[0] * w[2], up[0] * w[1] - up[1] * w[0]};
+    double ul = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    for (double& v : u) v /= ul;
+    double v[3] = {w[1] * u[2] - w[2] * u[1], w[2] * u[0] - w[0] * u[2], w[0] * u[1] - w[1] * u[0]};
+    const double th = std::tan(0.5 * (double)c.vfov_deg * M_PI / 180.0);
+    const double aspect = (double)c.width / (double)c.height;
+    S.eye = v3(c.eye[0], c.eye[1], c.eye[2]);
+    S.cu = v3((float)(u[0] * th * aspect), (float)(u[1] * th * aspect), (float)(u[2] * th * aspect));
+    S.cv = v3((float)(v[0] * th), (float)(v[1] * th), (float)(v[2] * th));
+    S.cw = v3((float)-w[0], (float)-w[1], (float)-w[2]);
+    S.W = (int)c.width;
+    S.H = (int)c.height;
+}
+
+int g_num_cu(int dev) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 256;
+    return prop.multiProcessorCount;
+}
+
+}  // namespace
+
+struct dr_scene {
+    int device = 0;
+    DevScene ds{};
+    DevAlloc mem;
+    std::vector<uint32_t> slot_to_prim;
+    dr_camera cam{};
+    uint32_t cam_version = 0;
+    uint32_t n_tris = 0;
+};
+
+struct dr_chains {
+    dr_scene* scene = nullptr;
+    uint32_t cam_version = 0;
+    dr_params P{};
+    KParams kp{};
+    KBufs kb{};
+    DevAlloc mem;
+    uint64_t seed = 0, step = 0;
+    int n_partials = 0;
+    int record = 0, count = 0;
+    dr_launch_cfg launch{256, 2, 1};
+    int n_cu = 256;
+};
+
+// ---------------------------------------------------------------------------
+static size_t stack_bytes(int block) { return (size_t)DR_STACK * block * sizeof(uint32_t); }
+
+#define DR_DISPATCH_L(L, FN, ...)          \
+    switch (L) {                           \
+        case 2: FN<2>(__VA_ARGS__); break;   \
+        case 3: FN<3>(__VA_ARGS__); break;   \
+        case 4: FN<4>(__VA_ARGS__); break;   \
+        case 5: FN<5>(__VA_ARGS__); break;   \
+        case 6: FN<6>(__VA_ARGS__); break;   \
+        case 7: FN<7>(__VA_ARGS__); break;   \
+        case 8: FN<8>(__VA_ARGS__); break;   \
+        case 9: FN<9>(__VA_ARGS__); break;   \
+        case 10: FN<10>(__VA_ARGS__); break; \
+        case 11: FN<11>(__VA_ARGS__); break; \
+        case 12: FN<12>(__VA_ARGS__); break; \
+        case 13: FN<13>(__VA_ARGS__); break; \
+        case 14: FN<14>(__VA_ARGS__); break; \
+        case 15: FN<15>(__VA_ARGS__); break; \
+        case 16: FN<16>(__VA_ARGS__); break; \
+        default: break;                      \
+    }
+
+template <int L>
+static void launch_init_acc(dim3 g, dim3 b, hipStream_t st, const KParams& P, const DevScene& S, const KBufs& B,
+                            uint64_t s0, int with_score) {
+    hipLaunchKernelGGL(k_init_accumulate<L>, g, b, 0, st, P, S, B, s0, with_score);
+}
+template <int L>
+static void launch_fused(dim3 g, dim3 b, hipStream_t st, const KParams& P, const DevScene& S, const KBufs& B,
+                         uint64_t s0, uint32_t n) {
+    hipLaunchKernelGGL(k_step_fused<L>, g, b, stack_bytes(b.x), st, P, S, B, s0, n);
+}
+template <int L>
+static void launch_plain_score(dim3 g, dim3 b, hipStream_t st, const KParams& P, const DevScene& S, const KBufs& B) {
+    hipLaunchKernelGGL(k_plain_score<L>, g, b, stack_bytes(b.x), st, P, S, B);
+}
+template <int L>
+static void launch_eval(dim3 g, dim3 b, hipStream_t st, const DevScene& S, const float* u, int n, float eps, float* fo,
+                        float* logp, float* grad, uint32_t* rs, uint32_t* ro) {
+    hipLaunchKernelGGL(k_eval<L>, g, b, stack_bytes(b.x), st, S, u, n, eps, fo, logp, grad, rs, ro);
+}
+
+static dr_status run_init(dr_chains* c, uint32_t frame, hipStream_t st) {
+    const int N = c->kp.N;
+    const int blk = 256;
+    const dim3 g((N + blk - 1) / blk), b(blk);
+    const uint64_t s0 = (uint64_t)frame << 32;
+    const size_t npx = (size_t)c->scene->ds.W * c->scene->ds.H;
+    KParams P = c->kp;
+    P.record = c->record;
+    P.count = c->count;
+    hipLaunchKernelGGL(k_fill_f32, dim3(1024), dim3(256), 0, st, c->kb.accum, 3 * npx);
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, c->kb.ctr, (int)C_N);
+    hipLaunchKernelGGL(k_init_eval, g, b, stack_bytes(blk), st, P, c->scene->ds, c->kb, s0);
+    hipLaunchKernelGGL(k_reduce_p, dim3(c->n_partials), dim3(256), 0, st, P, c->kb);
+    hipLaunchKernelGGL(k_finish_k0, dim3(1), dim3(64), 0, st, P, c->kb, c->n_partials, (double)c->P.k0, (double)c->P.m);
+    const int with_score = c->P.mode == DR_MODE_FUSED ? 1 : 0;
+    DR_DISPATCH_L(c->kp.L, launch_init_acc, g, b, st, P, c->scene->ds, c->kb, s0, with_score);
+    HIP_TRY(hipGetLastError());
+    c->step = s0 + 1;
+    c->cam_version = c->scene->cam_version;
+    return DR_OK;
+}
+
+extern "C" {
+
+const char* dr_last_error(void) { return g_err.c_str(); }
+const char* dr_version(void) { return "drestore-gfx950 0.1"; }
+
+dr_status dr_bvh_build(const float* vertices, uint32_t n_vertices, const uint32_t* indices, uint32_t n_triangles,
+                       uint32_t max_leaf, dr_bvh_node* nodes_out, uint32_t* n_nodes_out, uint32_t* prim_order_out) {
+    const char* err = "";
+    dr_status s = dr_bvh_build_impl(vertices, n_vertices, indices, n_triangles, max_leaf, nodes_out, n_nodes_out,
+                                    prim_order_out, &err);
+    if (s != DR_OK) return fail(s, err);
+    g_err.clear();
+    return DR_OK;
+}
+
+dr_status dr_scene_create(const dr_scene_desc* desc, int device, dr_scene** out) {
+    if (!desc || !out) return fail(DR_ERR_INVALID_ARG, "dr_scene_create: null argument");
+    const uint32_t T = desc->n_triangles;
+    if (T == 0 || !desc->vertices || !desc->indices || !desc->tri_material || !desc->materials)
+        return fail(DR_ERR_INVALID_ARG, "dr_scene_create: empty mesh or null array");
+    if (T >= (1u << 24)) return fail(DR_ERR_INVALID_ARG, "dr_scene_create: at most 2^24-1 triangles");
+    if (desc->n_lights == 0 || desc->n_lights > 127 || !desc->lights)
+        return fail(DR_ERR_INVALID_ARG, "dr_scene_create: need 1..127 lights");
+    if (desc->camera.width == 0 || desc->camera.height == 0)
+        return fail(DR_ERR_INVALID_ARG, "dr_scene_create: empty image");
+    for (uint64_t i = 0; i < 3ull * T; ++i)
+        if (desc->indices[i] >= desc->n_vertices) return fail(DR_ERR_INVALID_ARG, "dr_scene_create: vertex index out of range");
+    for (uint32_t t = 0; t < T; ++t)
+        if (desc->tri_material[t] >= desc->n_materials)
+            return fail(DR_ERR_INVALID_ARG, "dr_scene_create: material index out of range");
+    for (uint32_t m = 0; m < desc->n_materials; ++m)
+        if (desc->materials[m].kind > 1) return fail(DR_ERR_INVALID_ARG, "dr_scene_create: unknown material kind");
+
+    // BVH: given or built here
+    std::vector<dr_bvh_node> nodes;
+    std::vector<uint32_t> order;
+    if (desc->bvh) {
+        if (!desc->bvh_prim_order || desc->n_nodes == 0)
+            return fail(DR_ERR_INVALID_ARG, "dr_scene_create: bvh without prim order");
+        nodes.assign(desc->bvh, desc->bvh + desc->n_nodes);
+        order.assign(desc->bvh_prim_order, desc->bvh_prim_order + T);
+        std::vector<uint8_t> seen(T, 0);
+        for (uint32_t p : order) {
+            if (p >= T || seen[p]) return fail(DR_ERR_INVALID_ARG, "dr_scene_create: prim order is not a permutation");
+            seen[p] = 1;
+        }
+    } else {
+        nodes.resize(2 * (size_t)T);
+        order.resize(T);
+        uint32_t nn = 0;
+        dr_status s = dr_bvh_build(desc->vertices, desc->n_vertices, desc->indices, T, 4, nodes.data(), &nn, order.data());
+        if (s != DR_OK) return s;
+        nodes.resize(nn);
+    }
+    // Validate the tree, recompute exact f32 bounds bottom-up, and convert to
+    // the device layout (one DevNode per inner node, leaves embedded).
+    const size_t NN = nodes.size();
+    std::vector<int> depth(NN, -1), parent(NN, -1);
+    std::vector<int> stack = {0};
+    depth[0] = 0;
+    std::vector<int> topo;
+    uint64_t covered = 0;
+    while (!stack.empty()) {
+        const int i = stack.back();
+        stack.pop_back();
+        topo.push_back(i);
+        const dr_bvh_node& n = nodes[i];
+        if (n.a < 0) {
+            const int64_t first = ~(int64_t)n.a, cnt = n.b;
+            if (cnt < 1 || cnt > 16 || first + cnt > (int64_t)T)
+                return fail(DR_ERR_INVALID_ARG, "dr_scene_create: bad BVH leaf");
+            covered += (uint64_t)cnt;
+        } else {
+            for (int ch : {n.a, n.b}) {
+                if (ch <= 0 || (size_t)ch >= NN || depth[ch] != -1)
+                    return fail(DR_ERR_INVALID_ARG, "dr_scene_create: bad BVH child index");
+                depth[ch] = depth[i] + 1;
+                if (depth[ch] > DR_STACK) return fail(DR_ERR_INVALID_ARG, "dr_scene_create: BVH deeper than 40");
+                parent[ch] = i;
+                stack.push_back(ch);
+            }
+        }
+    }
+    if (covered != T) return fail(DR_ERR_INVALID_ARG, "dr_scene_create: BVH leaves do not cover every triangle once");
+    std::vector<float> blo(3 * NN, INFINITY), bhi(3 * NN, -INFINITY);
+    for (auto it = topo.rbegin(); it != topo.rend(); ++it) {
+        const int i = *it;
+        const dr_bvh_node& n = nodes[i];
+        if (n.a < 0) {
+            for (int64_t k = ~(int64_t)n.a; k < ~(int64_t)n.a + n.b; ++k) {
+                const uint32_t t = order[k];
+                for (int v = 0; v < 3; ++v) {
+                    const float* p = desc->vertices + 3 * (size_t)desc->indices[3 * (size_t)t + v];
+                    for (int a = 0; a < 3; ++a) {
+                        blo[3 * i + a] = std::min(blo[3 * i + a], p[a]);
+                        bhi[3 * i + a] = std::max(bhi[3 * i + a], p[a]);
+                    }
+                }
+            }
+        } else {
+            for (int a = 0; a < 3; ++a) {
+                blo[3 * i + a] = std::min(blo[3 * n.a + a], blo[3 * n.b + a]);
+                bhi[3 * i + a] = std::max(bhi[3 * n.a + a], bhi[3 * n.b + a]);
+            }
+        }
+    }
+    std::vector<DevNode> dn;
+    std::vector<int> dev_index(NN, -1);
+    auto child_slot = [&](int ch, float* box, int& idx, int& cnt) {
+        for (int a = 0; a < 3; ++a) { box[a] = blo[3 * ch + a]; box[3 + a] = bhi[3 * ch + a]; }
+        const dr_bvh_node& n = nodes[ch];
+        if (n.a < 0) { idx = ~n.a; cnt = n.b; }
+        else { idx = dev_index[ch]; cnt = 0; }
+    };
+    // assign device indices to inner nodes in topo (pre-)order
+    for (int i : topo)
+        if (nodes[i].a >= 0) { dev_index[i] = (int)dn.size(); dn.emplace_back(); }
+    if (nodes[0].a < 0) {  // whole scene in one leaf: a root with one leaf child
+        DevNode r{};
+        float box[6];
+        int idx, cnt;
+        child_slot(0, box, idx, cnt);
+        r.a = make_float4(box[0], box[1], box[2], box[3]);
+        r.b = make_float4(box[4], box[5], 1.f, 1.f);
+        r.c = make_float4(1.f, 0.f, 0.f, 0.f);
+        r.d = make_int4(idx, 0, cnt, -1);
+        dn.push_back(r);
+    } else {
+        for (int i : topo) {
+            const dr_bvh_node& n = nodes[i];
+            if (n.a < 0) continue;
+            float b0[6], b1[6];
+            int i0, c0, i1, c1;
+            child_slot(n.a, b0, i0, c0);
+            child_slot(n.b, b1, i1, c1);
+            DevNode& r = dn[dev_index[i]];
+            r.a = make_float4(b0[0], b0[1], b0[2], b0[3]);
+            r.b = make_float4(b0[4], b0[5], b1[0], b1[1]);
+            r.c = make_float4(b1[2], b1[3], b1[4], b1[5]);
+            r.d = make_int4(i0, i1, c0, c1);
+        }
+    }
+    // triangles in leaf order
+    std::vector<DevTri> tris(T);
+    std::vector<uint32_t> slot_to_prim(T);
+    for (uint32_t k = 0; k < T; ++k) {
+        const uint32_t t = order[k];
+        const float* v0 = desc->vertices + 3 * (size_t)desc->indices[3 * (size_t)t];
+        const float* v1 = desc->vertices + 3 * (size_t)desc->indices[3 * (size_t)t + 1];
+        const float* v2 = desc->vertices + 3 * (size_t)desc->indices[3 * (size_t)t + 2];
+        uint32_t mb = desc->tri_material[t], pb = t;
+        float mf, pf;
+        std::memcpy(&mf, &mb, 4);
+        std::memcpy(&pf, &pb, 4);
+        tris[k].v0 = make_float4(v0[0], v0[1], v0[2], pf);
+        tris[k].e1 = make_float4((float)((double)v1[0] - v0[0]), (float)((double)v1[1] - v0[1]), (float)((double)v1[2] - v0[2]), mf);
+        tris[k].e2 = make_float4((float)((double)v2[0] - v0[0]), (float)((double)v2[1] - v0[1]), (float)((double)v2[2] - v0[2]), 0.f);
+        slot_to_prim[k] = t;
+    }
+    std::vector<float4> mats(3 * desc->n_materials);
+    for (uint32_t m = 0; m < desc->n_materials; ++m) {
+        const dr_material& q = desc->materials[m];
+        mats[3 * m] = make_float4((float)q.kind, q.albedo[0], q.albedo[1], q.albedo[2]);
+        mats[3 * m + 1] = make_float4(q.roughness, q.f0[0], q.f0[1], q.f0[2]);
+        mats[3 * m + 2] = make_float4(q.Le[0], q.Le[1], q.Le[2], 0.f);
+    }
+    std::vector<float4> lights(5 * desc->n_lights);
+    for (uint32_t l = 0; l < desc->n_lights; ++l) {
+        const dr_quad_light& q = desc->lights[l];
+        const double e1[3] = {q.e1[0], q.e1[1], q.e1[2]}, e2[3] = {q.e2[0], q.e2[1], q.e2[2]};
+        const double nn[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+        const double area = std::sqrt(nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2]);
+        if (!(area > 0)) return fail(DR_ERR_INVALID_ARG, "dr_scene_create: degenerate light");
+        lights[5 * l] = make_float4(q.p0[0], q.p0[1], q.p0[2], 0.f);
+        lights[5 * l + 1] = make_float4(q.e1[0], q.e1[1], q.e1[2], 0.f);
+        lights[5 * l + 2] = make_float4(q.e2[0], q.e2[1], q.e2[2], 0.f);
+        lights[5 * l + 3] = make_float4((float)(nn[0] / area), (float)(nn[1] / area), (float)(nn[2] / area), (float)area);
+        lights[5 * l + 4] = make_float4(q.Le[0], q.Le[1], q.Le[2], 0.f);
+    }
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (uint32_t v = 0; v < desc->n_vertices; ++v)
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = std::min(lo[a], (double)desc->vertices[3 * (size_t)v + a]);
+            hi[a] = std::max(hi[a], (double)desc->vertices[3 * (size_t)v + a]);
+        }
+    const double diag = std::sqrt((hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]) +
+                                  (hi[2] - lo[2]) * (hi[2] - lo[2]));
+
+    HIP_TRY(hipSetDevice(device));
+    auto* S = new dr_scene();
+    S->device = device;
+    void *dnodes, *dtris, *dmats, *dlights;
+    if (S->mem.get(&dnodes, dn.size() * sizeof(DevNode)) != hipSuccess ||
+        S->mem.get(&dtris, tris.size() * sizeof(DevTri)) != hipSuccess ||
+        S->mem.get(&dmats, mats.size() * sizeof(float4)) != hipSuccess ||
+        S->mem.get(&dlights, lights.size() * sizeof(float4)) != hipSuccess) {
+        S->mem.release();
+        delete S;
+        return fail(DR_ERR_OUT_OF_MEMORY, "dr_scene_create: device allocation failed");
+    }
+    if (hipMemcpy(dnodes, dn.data(), dn.size() * sizeof(DevNode), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(dtris, tris.data(), tris.size() * sizeof(DevTri), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(dmats, mats.data(), mats.size() * sizeof(float4), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(dlights, lights.data(), lights.size() * sizeof(float4), hipMemcpyHostToDevice) != hipSuccess) {
+        S->mem.release();
+        delete S;
+        return fail(DR_ERR_DEVICE, "dr_scene_create: upload failed");
+    }
+    S->ds.nodes = (const DevNode*)dnodes;
+    S->ds.tris = (const DevTri*)dtris;
+    S->ds.mats = (const float4*)dmats;
+    S->ds.lights = (const float4*)dlights;
+    S->ds.n_lights = (int)desc->n_lights;
+    S->ds.tmin = (float)(1e-4 * diag);
+    camera_basis(desc->camera, S->ds);
+    S->cam = desc->camera;
+    S->slot_to_prim = std::move(slot_to_prim);
+    S->n_tris = T;
+    *out = S;
+    g_err.clear();
+    return DR_OK;
+}
+
+dr_status dr_scene_set_camera(dr_scene* s, const dr_camera* cam) {
+    if (!s || !cam) return fail(DR_ERR_INVALID_ARG, "dr_scene_set_camera: null argument");
+    if (cam->width != s->cam.width || cam->height != s->cam.height)
+        return fail(DR_ERR_INVALID_ARG, "dr_scene_set_camera: image size cannot change");
+    s->cam = *cam;
+    camera_basis(*cam, s->ds);
+    s->cam_version++;
+    g_err.clear();
+    return DR_OK;
+}
+
+void dr_scene_destroy(dr_scene* s) {
+    if (!s) return;
+    (void)hipSetDevice(s->device);
+    s->mem.release();
+    delete s;
+}
+
+dr_status dr_chains_init(dr_scene* s, const dr_params* p, uint64_t seed, uint32_t frame, void* hip_stream,
+                         dr_chains** out) {
+    if (!s || !p || !out) return fail(DR_ERR_INVALID_ARG, "dr_chains_init: null argument");
+    if (p->n_chains == 0) return fail(DR_ERR_INVALID_ARG, "dr_chains_init: n_chains must be >= 1");
+    if (p->n_chains > (1u << 30)) return fail(DR_ERR_INVALID_ARG, "dr_chains_init: n_chains too large");
+    if (p->max_path_len < 2 || p->max_path_len > 16) return fail(DR_ERR_INVALID_ARG, "dr_chains_init: max_path_len must be 2..16");
+    if (!(p->stddev > 0) || !(p->dt > 0) || !(p->m > 0) || !(p->eps > 0) || !(p->gamma >= 0))
+        return fail(DR_ERR_INVALID_ARG, "dr_chains_init: stddev, dt, m, eps must be > 0 and gamma >= 0");
+    if (p->mode > 1) return fail(DR_ERR_INVALID_ARG, "dr_chains_init: unknown mode");
+    HIP_TRY(hipSetDevice(s->device));
+    auto* c = new dr_chains();
+    c->scene = s;
+    c->P = *p;
+    c->seed = seed;
+    c->n_cu = g_num_cu(s->device);
+    const int N = (int)p->n_chains, L = (int)p->max_path_len, d = 4 * (L - 1);
+    c->kp.seed = seed;
+    c->kp.N = N;
+    c->kp.L = L;
+    c->kp.d = d;
+    c->kp.stddev = p->stddev;
+    c->kp.dt = p->dt;
+    c->kp.gt = p->dt * p->gamma / 2.0f;
+    c->kp.eps = p->eps;
+    c->kp.rb = p->rao_blackwell ? 1 : 0;
+    const size_t npx = (size_t)s->ds.W * s->ds.H;
+    c->n_partials = std::min(1024, (N + 255) / 256);
+    KBufs& B = c->kb;
+    void* q;
+    bool ok = true;
+    auto get = [&](void** ptr, size_t bytes) { if (ok && c->mem.get(ptr, bytes) != hipSuccess) ok = false; };
+    get(&q, sizeof(float) * d * (size_t)N); B.x = (float*)q;
+    get(&q, sizeof(float) * d * (size_t)N); B.score = (float*)q;
+    get(&q, sizeof(uint32_t) * N); B.killed = (uint32_t*)q;
+    get(&q, sizeof(uint32_t) * (L - 1) * (size_t)N); B.rec = (uint32_t*)q;
+    get(&q, sizeof(float) * 3 * npx); B.accum = (float*)q;
+    get(&q, sizeof(unsigned long long) * C_N); B.ctr = (unsigned long long*)q;
+    get(&q, 64); B.k0 = (float*)q; B.k0d = (double*)((char*)q + 16); B.plam = (double*)((char*)q + 32);
+    get(&q, 64); B.queue = (uint32_t*)q;
+    get(&q, sizeof(float) * N); B.p_tmp = (float*)q;
+    get(&q, sizeof(float) * 3 * (size_t)N); B.f_tmp = (float*)q;
+    get(&q, sizeof(uint32_t) * N); B.pix_tmp = (uint32_t*)q;
+    get(&q, sizeof(float) * N); B.r_w = (float*)q;
+    get(&q, sizeof(double) * c->n_partials); B.partial = (double*)q;
+    get(&q, sizeof(float) * 3 * npx); B.img = (float*)q;
+    B.sigma = p->sigma_diag;
+    if (!ok) {
+        c->mem.release();
+        delete c;
+        return fail(DR_ERR_OUT_OF_MEMORY, "dr_chains_init: device allocation failed");
+    }
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (hipMemsetAsync(B.score, 0, sizeof(float) * d * (size_t)N, st) != hipSuccess) {
+        c->mem.release();
+        delete c;
+        return fail(DR_ERR_DEVICE, "dr_chains_init: clear failed");
+    }
+    dr_status r = run_init(c, frame, st);
+    if (r != DR_OK) {
+        c->mem.release();
+        delete c;
+        return r;
+    }
+    *out = c;
+    g_err.clear();
+    return DR_OK;
+}
+
+dr_status dr_chains_reinit(dr_chains* c, uint32_t frame, void* hip_stream) {
+    if (!c) return fail(DR_ERR_INVALID_ARG, "dr_chains_reinit: null handle");
+    HIP_TRY(hipSetDevice(c->scene->device));
+    dr_status r = run_init(c, frame, (hipStream_t)hip_stream);
+    if (r == DR_OK) g_err.clear();
+    return r;
+}
+
+dr_status dr_step(dr_chains* c, uint32_t n_steps, void* hip_stream) {
+    if (!c) return fail(DR_ERR_INVALID_ARG, "dr_step: null handle");
+    if (c->cam_version != c->scene->cam_version)
+        return fail(DR_ERR_BAD_STATE, "dr_step: the scene changed since init; call dr_chains_reinit");
+    if (n_steps == 0) { g_err.clear(); return DR_OK; }
+    HIP_TRY(hipSetDevice(c->scene->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    KParams P = c->kp;
+    P.record = c->record;
+    P.count = c->count;
+    const int N = P.N;
+    if (c->P.mode == DR_MODE_FUSED) {
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, c->kb.queue, (size_t)1, 0u);
+        const int blk = (int)c->launch.block;
+        int blocks = (int)(c->n_cu * c->launch.blocks_per_cu);
+        blocks = std::max(1, std::min(blocks, (N + blk - 1) / blk));
+        DR_DISPATCH_L(P.L, launch_fused, dim3(blocks), dim3(blk), st, P, c->scene->ds, c->kb, c->step, n_steps);
+    } else {
+        const int blk = 256;
+        const dim3 g((N + blk - 1) / blk), b(blk);
+        for (uint32_t k = 0; k < n_steps; ++k) {
+            const uint64_t s = c->step + k;
+            DR_DISPATCH_L(P.L, launch_plain_score, g, b, st, P, c->scene->ds, c->kb);
+            hipLaunchKernelGGL(k_plain_move, g, b, 0, st, P, c->kb, s);
+            hipLaunchKernelGGL(k_plain_forward, g, b, stack_bytes(blk), st, P, c->scene->ds, c->kb);
+            hipLaunchKernelGGL(k_plain_accumulate, g, b, 0, st, P, c->scene->ds, c->kb, s);
+        }
+    }
+    HIP_TRY(hipGetLastError());
+    c->step += n_steps;
+    g_err.clear();
+    return DR_OK;
+}
+
+dr_status dr_resolve(dr_chains* c, float* image_dev, void* hip_stream) {
+    if (!c || !image_dev) return fail(DR_ERR_INVALID_ARG, "dr_resolve: null argument");
+    HIP_TRY(hipSetDevice(c->scene->device));
+    const size_t npx = (size_t)c->scene->ds.W * c->scene->ds.H;
+    hipLaunchKernelGGL(k_resolve, dim3(std::min<size_t>(4096, (3 * npx + 255) / 256)), dim3(256), 0,
+                       (hipStream_t)hip_stream, c->kb.accum, image_dev, npx, c->kb.k0d, c->kb.ctr, (double)c->P.dt);
+    HIP_TRY(hipGetLastError());
+    g_err.clear();
+    return DR_OK;
+}
+
+dr_status dr_image_read(dr_chains* c, float* host_rgb, uint64_t* tour_count, void* hip_stream) {
+    if (!c || !host_rgb) return fail(DR_ERR_INVALID_ARG, "dr_image_read: null argument");
+    HIP_TRY(hipSetDevice(c->scene->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    const size_t npx = (size_t)c->scene->ds.W * c->scene->ds.H;
+    float* img = c->kb.img;
+    dr_status r = dr_resolve(c, img, hip_stream);
+    if (r == DR_OK) {
+        hipError_t e = hipMemcpyAsync(host_rgb, img, 3 * npx * sizeof(float), hipMemcpyDeviceToHost, st);
+        unsigned long long tours = 0;
+        if (e == hipSuccess) e = hipMemcpyAsync(&tours, c->kb.ctr + C_TOURS, sizeof(tours), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) r = fail(DR_ERR_DEVICE, std::string("dr_image_read: ") + hipGetErrorString(e));
+        if (tour_count) *tour_count = tours;
+    }
+    if (r == DR_OK) g_err.clear();
+    return r;
+}
+
+dr_status dr_chains_destroy(dr_chains* c) {
+    if (!c) return DR_OK;
+    (void)hipSetDevice(c->scene->device);
+    (void)hipDeviceSynchronize();
+    c->mem.release();
+    delete c;
+    g_err.clear();
+    return DR_OK;
+}
+
+dr_status dr_chains_read_state(dr_chains* c, dr_state* o, void* hip_stream) {
+    if (!c || !o) return fail(DR_ERR_INVALID_ARG, "dr_chains_read_state: null argument");
+    HIP_TRY(hipSetDevice(c->scene->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    HIP_TRY(hipStreamSynchronize(st));
+    const size_t N = c->kp.N, d = c->kp.d, V = c->kp.L - 1;
+    const size_t npx = (size_t)c->scene->ds.W * c->scene->ds.H;
+    const KBufs& B = c->kb;
+    if (o->x) HIP_TRY(hipMemcpy(o->x, B.x, sizeof(float) * d * N, hipMemcpyDeviceToHost));
+    if (o->score) HIP_TRY(hipMemcpy(o->score, B.score, sizeof(float) * d * N, hipMemcpyDeviceToHost));
+    if (o->killed) HIP_TRY(hipMemcpy(o->killed, B.killed, sizeof(uint32_t) * N, hipMemcpyDeviceToHost));
+    if (o->accum) HIP_TRY(hipMemcpy(o->accum, B.accum, sizeof(float) * 3 * npx, hipMemcpyDeviceToHost));
+    if (o->p) HIP_TRY(hipMemcpy(o->p, B.p_tmp, sizeof(float) * N, hipMemcpyDeviceToHost));
+    if (o->weight) HIP_TRY(hipMemcpy(o->weight, B.r_w, sizeof(float) * N, hipMemcpyDeviceToHost));
+    if (o->pixel) HIP_TRY(hipMemcpy(o->pixel, B.pix_tmp, sizeof(uint32_t) * N, hipMemcpyDeviceToHost));
+    if (o->f_over_p) HIP_TRY(hipMemcpy(o->f_over_p, B.f_tmp, sizeof(float) * 3 * N, hipMemcpyDeviceToHost));
+    if (o->path_rec) {
+        HIP_TRY(hipMemcpy(o->path_rec, B.rec, sizeof(uint32_t) * V * N, hipMemcpyDeviceToHost));
+        const auto& s2p = c->scene->slot_to_prim;
+        for (size_t i = 0; i < V * N; ++i) {
+            const uint32_t r = o->path_rec[i];
+            if (r != DR_NO_VERTEX) o->path_rec[i] = (s2p[r >> 8] << 8) | (r & 0xFFu);
+        }
+    }
+    unsigned long long ctr[C_N];
+    HIP_TRY(hipMemcpy(ctr, B.ctr, sizeof(ctr), hipMemcpyDeviceToHost));
+    double k0 = 0, pl = 0;
+    HIP_TRY(hipMemcpy(&k0, B.k0d, sizeof(double), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(&pl, B.plam, sizeof(double), hipMemcpyDeviceToHost));
+    o->step = c->step;
+    o->tour_count = ctr[C_TOURS];
+    o->k0 = k0;
+    o->p_lambda_hat = pl;
+    g_err.clear();
+    return DR_OK;
+}
+
+dr_status dr_chains_write_state(dr_chains* c, const dr_state* in, void* hip_stream) {
+    if (!c || !in) return fail(DR_ERR_INVALID_ARG, "dr_chains_write_state: null argument");
+    HIP_TRY(hipSetDevice(c->scene->device));
+    HIP_TRY(hipStreamSynchronize((hipStream_t)hip_stream));
+    const size_t N = c->kp.N, d = c->kp.d;
+    const size_t npx = (size_t)c->scene->ds.W * c->scene->ds.H;
+    const KBufs& B = c->kb;
+    if (in->killed)
+        for (size_t i = 0; i < N; ++i)
+            if (in->killed[i] > 1) return fail(DR_ERR_INVALID_ARG, "dr_chains_write_state: killed must be 0/1");
+    if (in->x) HIP_TRY(hipMemcpy(B.x, in->x, sizeof(float) * d * N, hipMemcpyHostToDevice));
+    if (in->score) HIP_TRY(hipMemcpy(B.score, in->score, sizeof(float) * d * N, hipMemcpyHostToDevice));
+    if (in->killed) HIP_TRY(hipMemcpy(B.killed, in->killed, sizeof(uint32_t) * N, hipMemcpyHostToDevice));
+    if (in->accum) {
+        HIP_TRY(hipMemcpy(B.accum, in->accum, sizeof(float) * 3 * npx, hipMemcpyHostToDevice));
+        unsigned long long ctr[C_N];
+        HIP_TRY(hipMemcpy(ctr, B.ctr, sizeof(ctr), hipMemcpyDeviceToHost));
+        ctr[C_TOURS] = in->tour_count;
+        HIP_TRY(hipMemcpy(B.ctr, ctr, sizeof(ctr), hipMemcpyHostToDevice));
+    }
+    if (in->k0 > 0) {
+        const double k0 = in->k0;
+        const float k0f = (float)k0;
+        HIP_TRY(hipMemcpy(B.k0d, &k0, sizeof(double), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(B.k0, &k0f, sizeof(float), hipMemcpyHostToDevice));
+    }
+    c->step = in->step;
+    g_err.clear();
+    return DR_OK;
+}
+
+dr_status dr_chains_set_record(dr_chains* c, int enable) {
+    if (!c) return fail(DR_ERR_INVALID_ARG, "dr_chains_set_record: null handle");
+    c->record = enable ? 1 : 0;
+    g_err.clear();
+    return DR_OK;
+}
+
+dr_status dr_chains_set_counters(dr_chains* c, int enable) {
+    if (!c) return fail(DR_ERR_INVALID_ARG, "dr_chains_set_counters: null handle");
+    c->count = enable ? 1 : 0;
+    g_err.clear();
+    return DR_OK;
+}
+
+dr_status dr_stats(dr_chains* c, dr_counters* out, void* hip_stream) {
+    if (!c || !out) return fail(DR_ERR_INVALID_ARG, "dr_stats: null argument");
+    HIP_TRY(hipSetDevice(c->scene->device));
+    HIP_TRY(hipStreamSynchronize((hipStream_t)hip_stream));
+    unsigned long long ctr[C_N];
+    HIP_TRY(hipMemcpy(ctr, c->kb.ctr, sizeof(ctr), hipMemcpyDeviceToHost));
+    out->tours = ctr[C_TOURS];
+    out->kills = ctr[C_TOURS];
+    out->chain_steps = ctr[C_STEPS];
+    out->rays = ctr[C_RAYS];
+    out->node_visits = ctr[C_NODES];
+    out->tri_tests = ctr[C_TRIS];
+    out->adjoints = ctr[C_ADJ];
+    HIP_TRY(hipMemcpy(&out->k0, c->kb.k0d, sizeof(double), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(&out->p_lambda_hat, c->kb.plam, sizeof(double), hipMemcpyDeviceToHost));
+    g_err.clear();
+    return DR_OK;
+}
+
+dr_status dr_chains_set_launch(dr_chains* c, const dr_launch_cfg* cfg) {
+    if (!c || !cfg) return fail(DR_ERR_INVALID_ARG, "dr_chains_set_launch: null argument");
+    if (cfg->block && (cfg->block % 64 != 0 || cfg->block > 256))
+        return fail(DR_ERR_INVALID_ARG, "dr_chains_set_launch: block must be 64, 128, 192 or 256");
+    if (cfg->blocks_per_cu > 64) return fail(DR_ERR_INVALID_ARG, "dr_chains_set_launch: blocks_per_cu must be <= 64");
+    if (cfg->block) c->launch.block = cfg->block;
+    if (cfg->blocks_per_cu) c->launch.blocks_per_cu = cfg->blocks_per_cu;
+    if (cfg->grab) c->launch.grab = cfg->grab;
+    g_err.clear();
+    return DR_OK;
+}
+
+dr_status dr_chains_get_launch(dr_chains* c, dr_launch_cfg* cfg) {
+    if (!c || !cfg) return fail(DR_ERR_INVALID_ARG, "dr_chains_get_launch: null argument");
+    *cfg = c->launch;
+    g_err.clear();
+    return DR_OK;
+}
+
+dr_status dr_eval_logp_grad(dr_scene* s, uint32_t L, const float* u_dev, uint32_t n, float eps, float* f_dev,
+                            float* logp_dev, float* grad_dev, uint32_t* rec_dev, void* hip_stream) {
+    if (!s || !u_dev) return fail(DR_ERR_INVALID_ARG, "dr_eval_logp_grad: null argument");
+    if (L < 2 || L > 16) return fail(DR_ERR_INVALID_ARG, "dr_eval_logp_grad: L must be 2..16");
+    if (!(eps > 0)) return fail(DR_ERR_INVALID_ARG, "dr_eval_logp_grad: eps must be > 0");
+    if (n == 0) { g_err.clear(); return DR_OK; }
+    HIP_TRY(hipSetDevice(s->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    void* rs = nullptr;
+    HIP_TRY(hipMallocAsync(&rs, sizeof(uint32_t) * (L - 1) * (size_t)n, st));
+    const int blk = 128;
+    DR_DISPATCH_L((int)L, launch_eval, dim3((n + blk - 1) / blk), dim3(blk), st, s->ds, u_dev, (int)n, eps, f_dev,
+                  logp_dev, grad_dev, (uint32_t*)rs, rec_dev);
+    hipError_t e = hipGetLastError();
+    (void)hipFreeAsync(rs, st);
+    if (e != hipSuccess) return fail(DR_ERR_DEVICE, std::string("dr_eval_logp_grad: ") + hipGetErrorString(e));
+    g_err.clear();
+    return DR_OK;
+}
+
+dr_status dr_pt_render(dr_scene* s, uint32_t L, uint64_t seed, uint32_t spp, float* img_dev, void* hip_stream) {
+    if (!s || !img_dev) return fail(DR_ERR_INVALID_ARG, "dr_pt_render: null argument");
+    if (L < 2 || L > 16 || spp == 0) return fail(DR_ERR_INVALID_ARG, "dr_pt_render: L must be 2..16 and spp >= 1");
+    HIP_TRY(hipSetDevice(s->device));
+    const int npx = s->ds.W * s->ds.H;
+    const int blk = 128;
+    hipLaunchKernelGGL(k_pt, dim3((npx + blk - 1) / blk), dim3(blk), stack_bytes(blk), (hipStream_t)hip_stream, s->ds,
+                       (int)L, seed, spp, img_dev);
+    HIP_TRY(hipGetLastError());
+    g_err.clear();
+    return DR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,356 @@
+"""Parity of the HIP chain step with the FP64 oracle on identical seeded inputs.
+
+Tolerances follow from FP32 arithmetic on the device against FP64 on the
+host: values of smooth quantities within 1e-4 relative, decisions (kill,
+pixel) identical except where the FP64 value lies within the FP32 rounding
+band of the threshold, and paths whose discrete choices (hit triangle, light,
+visibility) differ between the two precisions excluded from value checks (the
+fraction of such flips is itself bounded).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2605_08916_amd import dr, inputs  # noqa: E402
+
+LUMW = np.array([0.2126, 0.7152, 0.0722])
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    dr.lib()
+    torch.cuda.set_device(0)
+
+
+@pytest.fixture(scope="module")
+def scenes():
+    out = {}
+    out["tiny"] = inputs.cornell_tiny()
+    out["spheres_small"] = inputs.procedural_spheres(n_spheres=3, subdiv=3, width=128, height=128)
+    return out
+
+
+def _rel(a, b, floor):
+    return np.abs(a - b) / np.maximum(np.abs(b), floor)
+
+
+def _eval_both(orc, sc, L, n, seed):
+    d = 4 * (L - 1)
+    u = inputs.random_points(d, n, seed)
+    S = dr.Scene(sc)
+    ut = torch.from_numpy(u).cuda()
+    f, logp, g, rec = S.eval_logp_grad(L, ut, rec=True)
+    torch.cuda.synchronize()
+    f, logp, g = f.cpu().numpy(), logp.cpu().numpy(), g.cpu().numpy()
+    rec = rec.cpu().numpy().view(np.uint32)
+    O = orc.Scene(sc)
+    fo, po, go, ro = O.path_eval(L, u.astype(np.float64))
+    # oracle record -> (prim << 8 | light << 1 | contrib) like the device's
+    V = L - 1
+    rec_o = np.full((n, V), 0xFFFFFFFF, np.uint64)
+    prim = ro[:, 0::2].astype(np.int64)
+    nee = ro[:, 1::2].astype(np.uint64)
+    has = prim.astype(np.int32) >= 0
+    rec_o[has] = (prim[has].astype(np.uint64) << 8) | (nee[has] & 0xFF)
+    match = np.all(rec_o.astype(np.uint32) == rec, axis=1)
+    return u, (f, logp, g), (fo, po, go), match
+
+
+@pytest.mark.parametrize("which,L,n", [("tiny", 4, 4000), ("spheres_small", 8, 3000)])
+def test_eval_matches_oracle(orc, scenes, which, L, n):
+    say(f"[eval parity] scene={which} L={L} n={n}")
+    u, (f, logp, g), (fo, po, go), match = _eval_both(orc, scenes[which], L, n, seed=5)
+    say(f"  path-signature match {match.mean():.5f}")
+    assert match.mean() > 0.995
+    m = match
+    fscale = max(1e-6, float(np.abs(fo).mean()))
+    assert np.all(_rel(f[m], fo[m], 1e-3 * fscale) < 1e-4), np.max(_rel(f[m], fo[m], 1e-3 * fscale))
+    pos = m & (po > 1e-3 * po.mean())
+    assert np.all(np.abs(logp[pos] - np.log(po[pos] + 1e-8)) < 1e-4)
+    # score: relative error of the score vector of each sample
+    live = pos
+    err = np.linalg.norm(g[live] - go[live], axis=1) / np.maximum(np.linalg.norm(go[live], axis=1), 1e-6)
+    say(f"  score rel err: median {np.median(err):.2e} p99 {np.quantile(err, 0.99):.2e} max {err.max():.2e}")
+    assert np.median(err) < 1e-5
+    assert np.quantile(err, 0.99) < 1e-3
+    # p == 0 paths have a zero score on both sides
+    zero = m & (po == 0)
+    assert np.all(g[zero] == 0)
+
+
+def test_autograd_matches_finite_differences_and_oracle(orc, scenes):
+    from paper_2605_08916_amd.autograd import LogContribution
+    sc = scenes["spheres_small"]
+    L, n, h = 8, 512, 1e-3
+    d = 4 * (L - 1)
+    say(f"[autograd] L={L} n={n} h={h}")
+    S = dr.Scene(sc)
+    u = torch.from_numpy(inputs.random_points(d, n, 9)).cuda().requires_grad_(True)
+    lp = LogContribution.apply(S, L, u)
+    w = torch.randn(n, device="cuda")
+    (lp * w).sum().backward()
+    grad = (u.grad / w[:, None]).detach().cpu().numpy()
+    _, _, g_eval, rec0 = S.eval_logp_grad(L, u.detach(), rec=True)
+    assert np.allclose(grad, g_eval.cpu().numpy(), rtol=1e-5, atol=1e-6)
+    O = orc.Scene(sc)
+    _, po, go, _ = O.path_eval(L, u.detach().cpu().numpy().astype(np.float64))
+    # central differences on the device in FP32 (h = 1e-3) where the path keeps its choices
+    un = u.detach()
+    checked = bad = 0
+    rec0 = rec0.cpu().numpy()
+    lp0 = lp.detach().cpu().numpy()
+    for i in range(d):
+        e = torch.zeros_like(un)
+        e[:, i] = h
+        _, lpp, _, rp = S.eval_logp_grad(L, (un + e).clamp(0, 1 - 2 ** -24), grad=False, rec=True)
+        _, lpm, _, rm = S.eval_logp_grad(L, (un - e).clamp(0, 1 - 2 ** -24), grad=False, rec=True)
+        same = np.all(rp.cpu().numpy() == rec0, 1) & np.all(rm.cpu().numpy() == rec0, 1)
+        same &= (po > 1e-2 * po.mean()) & (un[:, i].cpu().numpy() > h) & (un[:, i].cpu().numpy() < 1 - h)
+        fd = (lpp - lpm).cpu().numpy() / (2 * h)
+        # FD truncation error is O(h^2 f'''); allow 5% + FP32 noise of log p / h
+        tol = 0.05 * np.abs(go[:, i]) + 0.05 * np.abs(fd) + 2e-4 / h * np.maximum(1.0, np.abs(lp0))
+        ok = np.abs(fd - grad[:, i]) <= tol
+        checked += same.sum()
+        bad += (same & ~ok).sum()
+    say(f"  FD checked {checked}, outside tolerance {bad}")
+    assert checked > 2000
+    assert bad <= 0.01 * checked
+
+
+def _onestep(orc, sc, L, N, mode, seed, k0, gamma=0.5, sigma=None, sample=None, state_seed=3):
+    """Write one generated state to the device and the oracle, take one step,
+    return both states (device state restricted to `sample`)."""
+    d = 4 * (L - 1)
+    st = inputs.random_state(d, N, seed=state_seed, killed_frac=0.15, score_scale=40.0)
+    S = dr.Scene(sc)
+    sig_t = None if sigma is None else torch.from_numpy(sigma).cuda()
+    ch = dr.Chains(S, N, L, seed, k0=k0, gamma=gamma, mode=mode, sigma=sig_t)
+    ch.set_record(True)
+    step0 = (7 << 32) + 11
+    ch.write_state(x=st["x"], score=st["score"], killed=st["killed"], step=step0, k0=k0)
+    ch.step(1)
+    gs = ch.read_state()
+    idx = np.arange(N) if sample is None else np.asarray(sample)
+    O = orc.Scene(sc)
+    oc = orc.Chains.scene(O, L, len(idx), seed=seed, k0=k0, gamma=gamma,
+                          sigma=None if sigma is None else sigma[:, idx])
+    oc.set_ids(idx.astype(np.uint32))
+    oc.set_state(st["x"][:, idx], st["score"][:, idx], st["killed"][idx], step0, k0=k0)
+    oc.step(1, nthreads=16)
+    os_ = oc.state()
+    gsel = {k: (v[..., idx] if isinstance(v, np.ndarray) and v.shape[-1] == N else v) for k, v in gs.items()}
+    return st, gsel, os_, idx, step0
+
+
+def _compare_step(orc, sc, L, st, gs, os_, idx, seed, step0, k0, dt=1e-5, eps=1e-8, check_score=True):
+    W, H = sc["width"], sc["height"]
+    n = len(idx)
+    V = L - 1
+    prim = os_["rec"][0::2].astype(np.int64)
+    nee = os_["rec"][1::2].astype(np.uint64)
+    rec_o = np.where(prim.astype(np.int32) >= 0, (prim.astype(np.uint64) << 8) | (nee & 0xFF), 0xFFFFFFFF)
+    match = np.all(rec_o.astype(np.uint32) == gs["path_rec"], axis=0)
+    say(f"  path-signature match {match.mean():.5f}")
+    assert match.mean() > 0.99
+    # x' on the torus: step-relative error
+    dx = gs["x"].astype(np.float64) - os_["x"]
+    dx = np.abs(dx - np.round(dx))
+    step = np.abs(os_["x"] - st["x"][:, idx].astype(np.float64))
+    step = np.minimum(step, 1 - step)
+    xerr = dx / np.maximum(step, 5e-3)
+    say(f"  x' step-relative err max {xerr.max():.2e}")
+    assert xerr.max() < 1e-4
+    # pixel: identical except within 1e-3 pixel of an edge
+    fx = os_["x"][0] * W
+    fy = os_["x"][1] * H
+    near = (np.abs(fx - np.round(fx)) < 1e-3) | (np.abs(fy - np.round(fy)) < 1e-3)
+    pix_bad = (gs["pixel"] != os_["pixel"]) & ~near
+    assert pix_bad.sum() == 0, pix_bad.sum()
+    # kill decisions: identical except inside the band set by the p difference
+    Ea = np.array([-math.log(1 - orc.uniform(seed, int(c), step0, orc.TAG_HOLD, 0)) for c in idx])
+    Eb = np.array([-math.log(1 - orc.uniform(seed, int(c), step0, orc.TAG_HOLD, 1)) for c in idx])
+    k = k0 / (os_["p"] + eps)
+    gap = np.abs(k * dt * Ea - Eb) / np.maximum(Eb, 1e-30)
+    prel = np.abs(gs["p"] - os_["p"]) / np.maximum(os_["p"], 1e-30)
+    band = 1e-6 + 4 * np.where(match, prel, np.inf)
+    kill_bad = (gs["killed"] != os_["killed"]) & (gap > band)
+    say(f"  kill agreement {(gs['killed'] == os_['killed']).mean():.5f}, outside band {kill_bad.sum()}")
+    assert kill_bad.sum() == 0
+    m = match
+    pscale = max(1e-6, float(os_["p"].mean()))
+    assert np.all(_rel(gs["p"][m], os_["p"][m], 1e-3 * pscale) < 1e-4)
+    assert np.all(np.abs(gs["f_over_p"][:, m] - os_["f_over_p"][:, m]) < 1e-4 * np.maximum(1, np.abs(os_["f_over_p"][:, m])))
+    assert np.all(_rel(gs["weight"][m], os_["w"][m], 1e-30) < 1e-4)
+    if check_score:
+        live = m & (os_["killed"] == 0) & (gs["killed"] == 0) & (os_["p"] > 1e-3 * pscale)
+        go, gg = os_["score"][:, live], gs["score"][:, live].astype(np.float64)
+        err = np.linalg.norm(gg - go, axis=0) / np.maximum(np.linalg.norm(go, axis=0), 1e-6)
+        say(f"  score rel err median {np.median(err):.2e} p99 {np.quantile(err, 0.99):.2e}")
+        assert np.median(err) < 1e-5 and np.quantile(err, 0.99) < 1e-3
+
+
+@pytest.mark.parametrize("mode", [dr.DR_MODE_FUSED, dr.DR_MODE_PLAIN])
+@pytest.mark.parametrize("which,L,N", [("tiny", 4, 1000), ("spheres_small", 8, 1500)])
+def test_one_step_matches_oracle(orc, scenes, which, L, N, mode):
+    say(f"[one step] scene={which} L={L} N={N} mode={mode}")
+    k0 = 300.0
+    st, gs, os_, idx, step0 = _onestep(orc, scenes[which], L, N, mode, seed=21, k0=k0)
+    # the plain form computes the score at the start of the next step
+    _compare_step(orc, scenes[which], L, st, gs, os_, idx, 21, step0, k0, check_score=(mode == dr.DR_MODE_FUSED))
+
+
+def test_one_step_per_chain_sigma_and_rotation(orc, scenes):
+    """Nonreversible drift (gamma = 0.5) with per-chain diagonal Sigma."""
+    sc = scenes["spheres_small"]
+    L, N = 8, 800
+    sigma = inputs.per_chain_sigma(4 * (L - 1), N, seed=4)
+    say(f"[one step sigma] L={L} N={N}")
+    st, gs, os_, idx, step0 = _onestep(orc, sc, L, N, dr.DR_MODE_FUSED, seed=5, k0=200.0, gamma=0.5, sigma=sigma)
+    _compare_step(orc, sc, L, st, gs, os_, idx, 5, step0, 200.0)
+
+
+def test_init_matches_oracle(orc, scenes):
+    sc = scenes["tiny"]
+    L, N, seed = 4, 2048, 13
+    say(f"[init] L={L} N={N}")
+    S = dr.Scene(sc)
+    ch = dr.Chains(S, N, L, seed, k0=0.0)
+    ch.set_record(True)
+    ch.reinit(3)
+    gs = ch.read_state()
+    O = orc.Scene(sc)
+    oc = orc.Chains.scene(O, L, N, seed=seed)
+    oc.init(frame=3, nthreads=16)
+    os_ = oc.state()
+    oa = oc.accum()
+    assert np.array_equal(gs["x"].astype(np.float64), os_["x"])   # regeneration draws are exact in FP32
+    assert gs["step"] == oa["step"] == (3 << 32) + 1
+    assert abs(gs["p_lambda_hat"] / oa["p_lambda_hat"] - 1) < 1e-5
+    assert abs(gs["k0"] / oa["k0"] - 1) < 1e-5
+    agree = (gs["killed"] == os_["killed"]).mean()
+    say(f"  init kill agreement {agree:.5f}")
+    assert agree > 0.999
+    assert (gs["pixel"] == os_["pixel"]).all()
+
+
+def test_fused_and_plain_agree(scenes):
+    sc = scenes["tiny"]
+    L, N, seed = 4, 1024, 17
+    say(f"[fused vs plain] L={L} N={N}")
+    S = dr.Scene(sc)
+    out = []
+    for mode in (dr.DR_MODE_FUSED, dr.DR_MODE_PLAIN):
+        ch = dr.Chains(S, N, L, seed, k0=400.0, mode=mode)
+        ch.step(20)
+        s = ch.read_state()
+        out.append(s)
+    a, b = out
+    agree = (a["killed"] == b["killed"]).mean()
+    close = np.abs(a["x"] - b["x"]).max()
+    say(f"  kill agreement {agree:.5f}, max |dx| {close:.2e}, tours {a['tour_count']} {b['tour_count']}")
+    assert agree > 0.99
+    assert abs(a["tour_count"] - b["tour_count"]) <= 0.01 * a["tour_count"] + 5
+
+
+def test_pt_render_matches_oracle(orc, scenes):
+    sc = scenes["tiny"]
+    L, spp, seed = 4, 64, 3
+    say(f"[pt] L={L} spp={spp}")
+    S = dr.Scene(sc)
+    img = S.pt_render(L, seed, spp).cpu().numpy()
+    ref = orc.Scene(sc).pt_render(L, seed, spp)
+    err = np.abs(img - ref) / np.maximum(np.abs(ref), 1e-2)
+    say(f"  pt per-pixel rel err median {np.median(err):.2e} p99.9 {np.quantile(err, 0.999):.2e}")
+    assert np.median(err) < 1e-5
+    assert (err > 1e-3).mean() < 0.01
+
+
+def test_image_statistics_match_oracle(orc, scenes):
+    """The tiny configuration (256 chains x 1000 steps): device and oracle
+    images over 8 seeds each; their MRSE against a path-traced reference must
+    lie in each other's 95% band, and their means agree within the
+    seed-to-seed spread."""
+    sc = scenes["tiny"]
+    L, N, steps, R = 4, 256, 1000, 8
+    say(f"[image stats] L={L} N={N} steps={steps} R={R}")
+    S = dr.Scene(sc)
+    ref = S.pt_render(L, 12345, 1024).cpu().numpy().astype(np.float64)
+    O = orc.Scene(sc)
+
+    def mrse(img):
+        return float(((img - ref) ** 2 / (ref ** 2 + 1e-2)).mean())
+
+    g_m, o_m, g_means, o_means = [], [], [], []
+    for r in range(R):
+        ch = dr.Chains(S, N, L, 1000 + r)
+        ch.step(steps)
+        img, _ = ch.image_read()
+        g_m.append(mrse(img))
+        g_means.append(img.mean())
+        oc = orc.Chains.scene(O, L, N, seed=1000 + r)
+        oc.init(nthreads=16)
+        oc.step(steps, nthreads=16)
+        oi = oc.resolve()
+        o_m.append(mrse(oi))
+        o_means.append(oi.mean())
+    g_m, o_m = np.array(g_m), np.array(o_m)
+    say(f"  MRSE device {g_m.mean():.4f}+-{g_m.std():.4f}  oracle {o_m.mean():.4f}+-{o_m.std():.4f}")
+    se = math.sqrt(g_m.var(ddof=1) / R + o_m.var(ddof=1) / R)
+    assert abs(g_m.mean() - o_m.mean()) < 2.5 * se + 1e-3
+    sm = math.sqrt(np.var(g_means, ddof=1) / R + np.var(o_means, ddof=1) / R)
+    assert abs(np.mean(g_means) - np.mean(o_means)) < 3 * sm + 1e-4
+
+
+def test_resume_is_bit_identical(scenes):
+    sc = scenes["spheres_small"]
+    L, N, seed = 8, 2048, 23
+    say(f"[resume] L={L} N={N}")
+    S = dr.Scene(sc)
+    a = dr.Chains(S, N, L, seed)
+    a.step(5)
+    snap = a.read_state()
+    a.step(7)
+    ra = a.read_state()
+    b = dr.Chains(S, N, L, seed + 99)   # different seed: state must fully come from the snapshot
+    b.close()
+    b = dr.Chains(S, N, L, seed)
+    b.write_state(x=snap["x"], score=snap["score"], killed=snap["killed"], accum=snap["accum"], step=snap["step"],
+                  tour_count=snap["tour_count"], k0=snap["k0"])
+    b.step(7)
+    rb = b.read_state()
+    assert np.array_equal(ra["x"], rb["x"]) and np.array_equal(ra["killed"], rb["killed"])
+    assert ra["tour_count"] == rb["tour_count"]
+
+
+def test_counters_and_scene_change(scenes):
+    sc = scenes["tiny"]
+    L, N = 4, 512
+    S = dr.Scene(sc)
+    ch = dr.Chains(S, N, L, 1)
+    ch.set_counters(True)
+    ch.reinit(0)
+    ch.step(10)
+    st = ch.stats()
+    say(f"[counters] {st}")
+    assert st["chain_steps"] == N * 11
+    assert st["rays"] > N * 11 and st["node_visits"] >= st["rays"]
+    assert st["tours"] > 0 and st["adjoints"] > 0
+    cam = sc["camera"].copy()
+    cam[0] += 0.05
+    S.set_camera(cam)
+    with pytest.raises(dr.DrError) as e:
+        ch.step(1)
+    assert e.value.status == dr.DR_ERR_BAD_STATE
+    ch.reinit(1)
+    ch.step(1)
