@@ -466,7 +466,9 @@ static void path_eval(const Scene& S, int L, const T* u, PathRec& rec, bool repl
             T cy = -dot(lift<T>(lt.n), wl);
             bool contrib;
             if (!replay) {
-                contrib = val(cx) > 0.0 && val(cy) > 0.0 &&
+                // both cosines must clear 1e-6: a vertex lying in the light's own
+                // plane gives cosines that are rounding noise around zero
+                contrib = val(cx) > 1e-6 && val(cy) > 1e-6 &&
                           !occluded(S, vald(x), vald(wl), S.tmin, (1.0 - 1e-4) * val(r));
                 rec.nee[j - 1] = ((uint32_t)li << 1) | (contrib ? 1u : 0u);
             } else {

@@ -395,7 +395,9 @@ __device__ V3 path_forward(const DevScene& S, int L, const U& u, uint32_t* rec, 
             const V3 wl = w * (1.0f / r);
             const float cx = dot(n, wl);
             const float cy = -dot(xyz(l3), wl);
-            bool contrib = cx > 0.0f && cy > 0.0f;
+            // both cosines must clear 1e-6 (a vertex in the light's own plane
+            // has cosines that are rounding noise around zero)
+            bool contrib = cx > 1e-6f && cy > 1e-6f;
             if (contrib) contrib = !trace_any(S, x, wl, (1.0f - 1e-4f) * r, stk, stride, ctr);
             if (rec) rec[(j - 1) * rs] = ((uint32_t)slot << 8) | ((uint32_t)li << 1) | (contrib ? 1u : 0u);
             if (contrib) {
