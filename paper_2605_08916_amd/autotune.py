@@ -1,0 +1,82 @@
+"""Launch-configuration autotuner for the fused persistent chain-step kernel.
+
+It sweeps the threads per block, the resident blocks per compute unit of the
+persistent grid and the number of chains a lane takes per queue pop, times
+`dr_step(1)` for each candidate with HIP events on the launch stream, and
+caches the fastest configuration in a JSON file keyed by device name, path
+length, chain count and triangle count.  The chain state is saved before and
+restored after the sweep, so tuning does not advance the chains.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+from . import dr
+
+CACHE = os.environ.get("DR_AUTOTUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "drestore_autotune.json"))
+
+BLOCKS = (64, 128, 256)
+BLOCKS_PER_CU = (1, 2, 3, 4, 6, 8)
+GRABS = (1, 2)
+
+
+def _key(ch: "dr.Chains") -> str:
+    import torch
+    name = torch.cuda.get_device_name()
+    return f"{name}|L{ch.L}|N{ch.N}|T{int(ch.scene.sc['indices'].shape[0])}"
+
+
+def _load() -> dict:
+    try:
+        with open(CACHE) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _time(ch: "dr.Chains", reps: int) -> float:
+    import torch
+    s = torch.cuda.current_stream()
+    ch.step(1)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        ch.step(1)
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def tune(ch: "dr.Chains", reps: int = 5, use_cache: bool = True, verbose: bool = False) -> dict:
+    """Pick and apply the fastest launch configuration for this chain set."""
+    key = _key(ch)
+    cache = _load() if use_cache else {}
+    if key in cache:
+        cfg = cache[key]["cfg"]
+        ch.set_launch(**cfg)
+        return cache[key]
+    snap = ch.read_state()
+    results = []
+    for block in BLOCKS:
+        for bpc in BLOCKS_PER_CU:
+            for grab in GRABS:
+                ch.set_launch(block=block, blocks_per_cu=bpc, grab=grab)
+                ms = _time(ch, reps)
+                results.append((ms, dict(block=block, blocks_per_cu=bpc, grab=grab)))
+                if verbose:
+                    print(f"autotune block={block} blocks/CU={bpc} grab={grab}: {ms:.3f} ms")
+    results.sort(key=lambda r: r[0])
+    best_ms, best = results[0]
+    ch.set_launch(**best)
+    ch.write_state(x=snap["x"], score=snap["score"], killed=snap["killed"], accum=snap["accum"], step=snap["step"],
+                   tour_count=snap["tour_count"], k0=snap["k0"])
+    entry = {"cfg": best, "ms": best_ms, "sweep": [(ms, c) for ms, c in results]}
+    cache[key] = entry
+    try:
+        os.makedirs(os.path.dirname(CACHE), exist_ok=True)
+        with open(CACHE, "w") as f:
+            json.dump(cache, f, indent=1)
+    except OSError:
+        pass
+    return entry

@@ -241,31 +241,39 @@ __global__ void __launch_bounds__(256) k_init_accumulate(KParams P, DevScene S, 
 
 // Fused persistent evolve step: every chain advances nsteps steps.
 template <int L>
-__global__ void __launch_bounds__(256) k_step_fused(KParams P, DevScene S, KBufs B, uint64_t s0, uint32_t nsteps) {
+__global__ void __launch_bounds__(256) k_step_fused(KParams P, DevScene S, KBufs B, uint64_t s0, uint32_t nsteps,
+                                                    uint32_t grab) {
     extern __shared__ uint32_t s_stack[];
     uint32_t* stk = s_stack + threadIdx.x;
     const int stride = blockDim.x;
     const int lane = threadIdx.x & 63;
     const float k0 = *B.k0;
-    int c = -1;
+    int c = -1, cend = -1;
     uint32_t k = nsteps;
     Counters ctr = {0, 0, 0};
     uint32_t kills = 0, steps = 0, adj = 0;
     while (true) {
-        // refill lanes whose chain is finished: one queue atomic per wavefront
+        // a lane done with its chain moves to the next of its `grab` chains;
+        // lanes out of chains refill with one queue atomic per wavefront
+        if (k >= nsteps && c + 1 < cend) {
+            ++c;
+            k = 0;
+        }
         const bool need = k >= nsteps;
         const uint64_t mask = __ballot(need);
         if (mask) {
             const int leader = __ffsll((long long)mask) - 1;
             uint32_t base = 0;
-            if (lane == leader) base = atomicAdd(B.queue, (uint32_t)__popcll(mask));
+            if (lane == leader) base = atomicAdd(B.queue, (uint32_t)__popcll(mask) * grab);
             base = __shfl(base, leader);
             if (need) {
-                c = (int)(base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull)));
+                const uint32_t first = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull)) * grab;
+                c = (int)min(first, (uint32_t)P.N);
+                cend = (int)min(first + grab, (uint32_t)P.N);
                 k = 0;
             }
         }
-        const bool active = c < P.N;
+        const bool active = c < cend;
         if (!__any(active)) break;
         if (active) {
             const uint64_t s = s0 + k;
@@ -287,6 +295,7 @@ __global__ void __launch_bounds__(256) k_step_fused(KParams P, DevScene S, KBufs
             ++steps;
         } else {
             k = 0;  // drained lanes stop asking for work
+            cend = c;
         }
     }
     wave_add(&B.ctr[C_TOURS], kills);
@@ -542,8 +551,8 @@ static void launch_init_acc(dim3 g, dim3 b, hipStream_t st, const KParams& P, co
 }
 template <int L>
 static void launch_fused(dim3 g, dim3 b, hipStream_t st, const KParams& P, const DevScene& S, const KBufs& B,
-                         uint64_t s0, uint32_t n) {
-    hipLaunchKernelGGL(k_step_fused<L>, g, b, stack_bytes(b.x), st, P, S, B, s0, n);
+                         uint64_t s0, uint32_t n, uint32_t grab) {
+    hipLaunchKernelGGL(k_step_fused<L>, g, b, stack_bytes(b.x), st, P, S, B, s0, n, grab);
 }
 template <int L>
 static void launch_plain_score(dim3 g, dim3 b, hipStream_t st, const KParams& P, const DevScene& S, const KBufs& B) {
@@ -910,7 +919,8 @@ dr_status dr_step(dr_chains* c, uint32_t n_steps, void* hip_stream) {
         const int blk = (int)c->launch.block;
         int blocks = (int)(c->n_cu * c->launch.blocks_per_cu);
         blocks = std::max(1, std::min(blocks, (N + blk - 1) / blk));
-        DR_DISPATCH_L(P.L, launch_fused, dim3(blocks), dim3(blk), st, P, c->scene->ds, c->kb, c->step, n_steps);
+        DR_DISPATCH_L(P.L, launch_fused, dim3(blocks), dim3(blk), st, P, c->scene->ds, c->kb, c->step, n_steps,
+                      c->launch.grab);
     } else {
         const int blk = 256;
         const dim3 g((N + blk - 1) / blk), b(blk);
@@ -1074,6 +1084,7 @@ dr_status dr_chains_set_launch(dr_chains* c, const dr_launch_cfg* cfg) {
     if (cfg->block && (cfg->block % 64 != 0 || cfg->block > 256))
         return fail(DR_ERR_INVALID_ARG, "dr_chains_set_launch: block must be 64, 128, 192 or 256");
     if (cfg->blocks_per_cu > 64) return fail(DR_ERR_INVALID_ARG, "dr_chains_set_launch: blocks_per_cu must be <= 64");
+    if (cfg->grab > 64) return fail(DR_ERR_INVALID_ARG, "dr_chains_set_launch: grab must be <= 64");
     if (cfg->block) c->launch.block = cfg->block;
     if (cfg->blocks_per_cu) c->launch.blocks_per_cu = cfg->blocks_per_cu;
     if (cfg->grab) c->launch.grab = cfg->grab;
