@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdr.so")
 SOURCES = [os.path.join(CSRC, "dr_lib.hip"), os.path.join(CSRC, "bvh_build.cpp")]
-DEPS = SOURCES + [os.path.join(CSRC, "dr_device.h"), os.path.join(CSRC, "dr_adjoint.h"),
+DEPS = SOURCES + [os.path.join(CSRC, "dr_device.h"), os.path.join(CSRC, "dr_adjoint.h"), os.path.join(CSRC, "dr_chain.h"),
                   os.path.join(ROOT, "include", "dr.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -22,6 +22,7 @@
 
 #include "../../include/dr.h"
 #include "dr_adjoint.h"
+#include "dr_chain.h"
 #include "dr_device.h"
 
 using namespace dr;
@@ -77,61 +78,11 @@ __device__ __forceinline__ void wave_add(unsigned long long* dst, uint32_t v) {
     if ((threadIdx.x & 63) == (uint32_t)(__ffsll((long long)act) - 1) && s) atomicAdd(dst, (unsigned long long)s);
 }
 
-// ---------------------------------------------------------------------------
-// Chain-state pieces (Alg. 4.1, 4.2, 5.1)
-// ---------------------------------------------------------------------------
-// x ~ uniform on the torus.
-__device__ __forceinline__ void regen(const KParams& P, float* x, int c, uint64_t s) {
-    for (int b = 0; b < P.d / 4; ++b) {
-        const uint4 r = rng_block(P.seed, (uint32_t)c, s, TAG_REGEN, (uint32_t)b);
-        x[(size_t)(4 * b + 0) * P.N] = u24(r.x);
-        x[(size_t)(4 * b + 1) * P.N] = u24(r.y);
-        x[(size_t)(4 * b + 2) * P.N] = u24(r.z);
-        x[(size_t)(4 * b + 3) * P.N] = u24(r.w);
-    }
-}
-
-__device__ __forceinline__ float wrap01(float y) {
-    y -= floorf(y);
-    return y >= 1.0f ? 0.0f : y;
-}
-
-// Euler-Maruyama move with rotational drift, per 2-D block (Alg. 5.1):
-// x += (sd^2/2) s + gt (s2, -s1) + sd xi, then wrap to the torus.
-__device__ __forceinline__ void move(const KParams& P, float* x, const float* score, const float* sigma, int c,
-                                     uint64_t s) {
-    for (int b = 0; b < P.d / 4; ++b) {
-        const uint4 r = rng_block(P.seed, (uint32_t)c, s, TAG_GAUSS, (uint32_t)b);
-        const float uu[4] = {u24(r.x), u24(r.y), u24(r.z), u24(r.w)};
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int i0 = 4 * b + 2 * q, i1 = i0 + 1;
-            const float rad = sqrtf(-2.0f * logf(1.0f - uu[2 * q]));
-            float sn, cs;
-            sincosf(2.0f * DR_PI * uu[2 * q + 1], &sn, &cs);
-            const float xi0 = rad * cs, xi1 = rad * sn;
-            const size_t a0 = (size_t)i0 * P.N, a1 = (size_t)i1 * P.N;
-            const float s0 = score[a0], s1 = score[a1];
-            const float sd0 = sigma ? sigma[a0] : P.stddev;
-            const float sd1 = sigma ? sigma[a1] : P.stddev;
-            const float y0 = x[a0] + 0.5f * sd0 * sd0 * s0 + P.gt * s1 + sd0 * xi0;
-            const float y1 = x[a1] + 0.5f * sd1 * sd1 * s1 - P.gt * s0 + sd1 * xi1;
-            x[a0] = wrap01(y0);
-            x[a1] = wrap01(y1);
-        }
-    }
-}
-
 // Hold/kill and splat (Accumulate).  Returns true if the tour survives.
 __device__ __forceinline__ bool hold_kill_splat(const KParams& P, const KBufs& B, const DevScene& S, int c, uint64_t s,
                                                 float k0, V3 f, float p, uint32_t pix) {
-    const uint4 r = rng_block(P.seed, (uint32_t)c, s, TAG_HOLD, 0);
-    const float Ea = -logf(1.0f - u24(r.x));
-    const float Eb = -logf(1.0f - u24(r.y));
-    const float k = k0 / (p + P.eps);
-    const bool alive = (k * P.dt) * Ea < Eb;
-    // splat weight in units of dt: RB 1/(1 + k dt), or the sampled min
-    const float wdt = P.rb ? 1.0f / (1.0f + k * P.dt) : fminf(Ea, Eb / (k * P.dt));
+    float wdt;
+    const bool alive = hold_kill(P.seed, c, s, k0, p, P.eps, P.dt, P.rb, wdt);
     if (p > 0.0f) {
         const float sc = wdt / p;
         const size_t npx = (size_t)S.W * S.H;
@@ -174,7 +125,7 @@ __global__ void __launch_bounds__(256) k_init_eval(KParams P, DevScene S, KBufs 
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     Counters ctr = {0, 0, 0};
     if (c < P.N) {
-        regen(P, B.x + c, c, s0);
+        regen(P.seed, P.d, P.N, B.x + c, c, s0);
         const V3 f = path_forward(S, P.L, SoaU{B.x + c, P.N}, B.rec + c, P.N, s_stack + threadIdx.x, blockDim.x, ctr);
         B.p_tmp[c] = lum(f);
         B.f_tmp[c] = f.x;
@@ -278,8 +229,8 @@ __global__ void __launch_bounds__(256) k_step_fused(KParams P, DevScene S, KBufs
         if (active) {
             const uint64_t s = s0 + k;
             float* xc = B.x + c;
-            if (B.killed[c]) regen(P, xc, c, s);
-            else move(P, xc, B.score + c, B.sigma ? B.sigma + c : nullptr, c, s);
+            if (B.killed[c]) regen(P.seed, P.d, P.N, xc, c, s);
+            else move(P.seed, P.d, P.N, P.stddev, P.gt, xc, B.score + c, B.sigma ? B.sigma + c : nullptr, c, s);
             const SoaU u{xc, P.N};
             const V3 f = path_forward(S, L, u, B.rec + c, P.N, stk, stride, ctr);
             const float p = lum(f);
@@ -332,8 +283,8 @@ __global__ void __launch_bounds__(256) k_plain_score(KParams P, DevScene S, KBuf
 __global__ void __launch_bounds__(256) k_plain_move(KParams P, KBufs B, uint64_t s) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= P.N) return;
-    if (B.killed[c]) regen(P, B.x + c, c, s);
-    else move(P, B.x + c, B.score + c, B.sigma ? B.sigma + c : nullptr, c, s);
+    if (B.killed[c]) regen(P.seed, P.d, P.N, B.x + c, c, s);
+    else move(P.seed, P.d, P.N, P.stddev, P.gt, B.x + c, B.score + c, B.sigma ? B.sigma + c : nullptr, c, s);
 }
 __global__ void __launch_bounds__(256) k_plain_forward(KParams P, DevScene S, KBufs B) {
     extern __shared__ uint32_t s_stack[];
