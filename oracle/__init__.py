@@ -18,6 +18,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# a prebuilt oracle library to load instead (used by the mutation tests, which
+# plant mistakes in a copy of oracle.cpp and check that the pins catch them)
+_LIB_OVERRIDE = os.environ.get("DR_ORACLE_LIB")
 
 # Paper parameter defaults: stddev 5e-3, dt 1e-5, m 64 (Sec. 6, parameter
 # choices); eps 1e-8 (Sec. 5, target penalty); gamma 0.5 (not given in the
@@ -43,8 +46,11 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        build()
-        L = C.CDLL(_LIB)
+        if _LIB_OVERRIDE:
+            L = C.CDLL(_LIB_OVERRIDE)
+        else:
+            build()
+            L = C.CDLL(_LIB)
         P = C.c_void_p
         D = C.POINTER(C.c_double)
         F = C.POINTER(C.c_float)
@@ -68,6 +74,10 @@ def lib():
         L.orc_bsdf_sample.restype = C.c_int
         L.orc_bsdf_eval.argtypes = [F, D, D, D, D]
         L.orc_onb.argtypes = [D, D, D]
+        L.orc_ggx_d.argtypes = [C.c_double, C.c_double]
+        L.orc_ggx_d.restype = C.c_double
+        L.orc_smith_g1.argtypes = [C.c_double, C.c_double]
+        L.orc_smith_g1.restype = C.c_double
         L.orc_bsdf_sample_n.argtypes = [F, D, D, C.c_int, D, D, D, D, I]
         L.orc_bsdf_eval_n.argtypes = [F, D, D, C.c_int, D, D]
         L.orc_chains_new_scene.argtypes = [P, C.c_int, C.c_int, D, C.c_uint64, F]
@@ -232,6 +242,14 @@ def bsdf_eval_n(mat, n, wo, wi):
     lib().orc_bsdf_eval_n(_p(m, C.c_float), _p(n, C.c_double), _p(wo, C.c_double), wi.shape[0], _p(wi, C.c_double),
                           _p(fs, C.c_double))
     return fs
+
+
+def ggx_d(ch: float, alpha: float) -> float:
+    return lib().orc_ggx_d(ch, alpha)
+
+
+def smith_g1(c: float, alpha: float) -> float:
+    return lib().orc_smith_g1(c, alpha)
 
 
 def onb(n):

@@ -335,6 +335,12 @@ template <class T> static T smith_g1(T c, double alpha) {
     return 2.0 / (1.0 + sqrt(1.0 + alpha * alpha * tan2));
 }
 
+// Trowbridge-Reitz (GGX) normal distribution at cos(theta_h) = ch.
+template <class T> static T ggx_d(T ch, double a2) {
+    T den = ch * ch * (a2 - 1.0) + 1.0;
+    return a2 / (M_PI * den * den);
+}
+
 // f_s(wo, wi) * (per channel).  Caller guarantees n.wo > 0 and n.wi > 0.
 template <class T>
 static void bsdf_eval(const Material& m, const V3<double>& n, const V3<T>& wo, const V3<T>& wi, T fs[3]) {
@@ -347,8 +353,7 @@ static void bsdf_eval(const Material& m, const V3<double>& n, const V3<T>& wo, c
     T co = dot(nn, wo), ci = dot(nn, wi);
     V3<T> h = normalize(wo + wi);
     T ch = dot(nn, h);
-    T den = ch * ch * (a2 - 1.0) + 1.0;
-    T D = a2 / (M_PI * den * den);
+    T D = ggx_d(ch, a2);
     T G = smith_g1(co, a) * smith_g1(ci, a);
     T oh = dot(wi, h);
     T one_m = 1.0 - oh;
@@ -918,6 +923,10 @@ void orc_bsdf_sample_n(const float* mat, const double* n, const double* wo, int 
 void orc_bsdf_eval_n(const float* mat, const double* n, const double* wo, int count, const double* wi, double* fs) {
     for (int i = 0; i < count; ++i) orc_bsdf_eval(mat, n, wo, wi + 3 * i, fs + 3 * i);
 }
+// GGX distribution D(cos theta_h) and Smith masking G1(cos theta) for alpha.
+double orc_ggx_d(double ch, double alpha) { return ggx_d<double>(ch, alpha * alpha); }
+double orc_smith_g1(double c, double alpha) { return smith_g1<double>(c, alpha); }
+
 void orc_onb(const double* n, double* t, double* b) {
     V3<double> tt, bb;
     onb({n[0], n[1], n[2]}, tt, bb);

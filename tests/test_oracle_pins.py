@@ -180,6 +180,30 @@ def test_bsdf_sampling_matches_evaluation(orc, mat):
         assert np.allclose((fs * (ct * w)[:, None]).sum(0), mat[1:4], rtol=1e-4)
 
 
+@pytest.mark.parametrize("alpha", [0.1, 0.3, 0.5])
+def test_ggx_normalisation_and_weak_white_furnace(orc, alpha):
+    """Exact identities of a microfacet model: the projected microfacet area
+    integrates to one, int D(h) cos(theta_h) dh = 1, and the weak white
+    furnace, int G1(wo) max(0, wo.h) D(h) dh = cos(theta_o), which holds only
+    for the Smith G1 that matches D."""
+    n = 2000
+    ct = (np.arange(n) + 0.5) / n
+    D = np.array([orc.ggx_d(c, alpha) for c in ct])
+    assert abs((D * ct).sum() / n * 2 * np.pi - 1) < 2e-3
+    # weak furnace for a few outgoing angles (quadrature over h on the hemisphere)
+    nth, nph = 1500, 400
+    cth = (np.arange(nth) + 0.5) / nth
+    ph = 2 * np.pi * (np.arange(nph) + 0.5) / nph
+    CT, PH = np.meshgrid(cth, ph, indexing="ij")
+    ST = np.sqrt(1 - CT ** 2)
+    Dh = np.array([orc.ggx_d(c, alpha) for c in cth])[:, None]
+    for th_o in (0.2, 0.7, 1.2):
+        wo = np.array([math.sin(th_o), 0.0, math.cos(th_o)])
+        dot_oh = ST * np.cos(PH) * wo[0] + CT * wo[2]
+        integral = (orc.smith_g1(wo[2], alpha) * np.maximum(dot_oh, 0) * Dh).sum() * (1 / nth) * (2 * np.pi / nph)
+        assert abs(integral / wo[2] - 1) < 5e-3, (alpha, th_o, integral / wo[2])
+
+
 def test_bsdf_reciprocity_and_energy(orc):
     rng = np.random.default_rng(4)
     n = np.array([0.0, 0.0, 1.0])
