@@ -41,6 +41,10 @@ def parse():
     ap.add_argument("--no-mrse", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--chains", type=int, default=65536)
+    ap.add_argument("--profile-only", action="store_true",
+                    help="only run warmup + steps of the fused form (for hardware-counter runs)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy (calibrates the FETCH_SIZE/WRITE_SIZE counters)")
     return ap.parse_args()
 
 
@@ -115,6 +119,23 @@ def main():
     from paper_2605_08916_amd import dr, inputs
 
     torch.cuda.set_device(0)
+    if a.copy_probe:
+        n = 1 << 28
+        src = torch.ones(n, device="cuda", dtype=torch.float32)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": 4 * n}))
+        return
+    if a.profile_only:
+        sc = inputs.procedural_spheres(seed=1)
+        scene = dr.Scene(sc)
+        ch = dr.Chains(scene, a.chains, 8, 2024, mode=dr.DR_MODE_FUSED)
+        for _ in range(a.warmup + a.steps):
+            ch.step(1)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_only_steps": a.warmup + a.steps}))
+        return
     sc = inputs.procedural_spheres(seed=1)
     L, N = 8, a.chains
     d = 4 * (L - 1)

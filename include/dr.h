@@ -203,10 +203,12 @@ dr_status dr_chains_set_counters(dr_chains* c, int enable);
 dr_status dr_stats(dr_chains* c, dr_counters* out, void* hip_stream);
 
 /* Launch configuration of the fused persistent kernel: threads per block
- * (64..1024, multiple of 64), resident blocks per compute unit, and the number
- * of chains a wavefront takes from the device work queue per pop.  Zeros keep
- * the current value. */
-typedef struct { uint32_t block; uint32_t blocks_per_cu; uint32_t grab; } dr_launch_cfg;
+ * (64, 128, 192 or 256), resident blocks per compute unit of the persistent
+ * grid, the number of consecutive chains a lane (or lane pair) takes per pop
+ * of the device work queue (1..64), and lanes per chain (1, or 2: the two
+ * lanes trace a path's continuation and shadow rays concurrently).  Zeros keep
+ * the current value.  Defaults: 256, 2, 1, 2. */
+typedef struct { uint32_t block; uint32_t blocks_per_cu; uint32_t grab; uint32_t lanes_per_chain; } dr_launch_cfg;
 dr_status dr_chains_set_launch(dr_chains* c, const dr_launch_cfg* cfg);
 dr_status dr_chains_get_launch(dr_chains* c, dr_launch_cfg* cfg);
 

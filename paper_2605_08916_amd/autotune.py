@@ -18,7 +18,8 @@ CACHE = os.environ.get("DR_AUTOTUNE_CACHE", os.path.join(os.path.expanduser("~")
 
 BLOCKS = (64, 128, 256)
 BLOCKS_PER_CU = (1, 2, 3, 4, 6, 8)
-GRABS = (1, 2)
+GRABS = (1,)
+LANES = (1, 2)
 
 
 def _key(ch: "dr.Chains") -> str:
@@ -61,11 +62,13 @@ def tune(ch: "dr.Chains", reps: int = 5, use_cache: bool = True, verbose: bool =
     for block in BLOCKS:
         for bpc in BLOCKS_PER_CU:
             for grab in GRABS:
-                ch.set_launch(block=block, blocks_per_cu=bpc, grab=grab)
-                ms = _time(ch, reps)
-                results.append((ms, dict(block=block, blocks_per_cu=bpc, grab=grab)))
-                if verbose:
-                    print(f"autotune block={block} blocks/CU={bpc} grab={grab}: {ms:.3f} ms")
+                for lanes in LANES:
+                    cfg = dict(block=block, blocks_per_cu=bpc, grab=grab, lanes_per_chain=lanes)
+                    ch.set_launch(**cfg)
+                    ms = _time(ch, reps)
+                    results.append((ms, cfg))
+                    if verbose:
+                        print(f"autotune {cfg}: {ms:.3f} ms")
     results.sort(key=lambda r: r[0])
     best_ms, best = results[0]
     ch.set_launch(**best)

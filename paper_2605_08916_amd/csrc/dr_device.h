@@ -142,11 +142,16 @@ __device__ __forceinline__ DevNode load_node(const DevNode* nodes, int i) {
     return n;
 }
 
-// Closest hit over (tmin, tmax); ties in t go to the lower input triangle
-// index.  Returns the triangle slot (leaf order) or -1.  stk: this lane's LDS
-// stack, entries at stk[k * stride].
-__device__ int trace_closest(const DevScene& S, V3 o, V3 d, float tmax, float& t_hit, uint32_t* stk, int stride,
-                             Counters& ctr) {
+// One ray query over (tmin, tmax): the closest hit (ties in t go to the lower
+// input triangle index) or, with anyhit, the first hit found.  Returns the
+// triangle slot (leaf order) or -1; tmax <= tmin means "no ray" and returns -1
+// at once (used by paired lanes that have nothing to trace).  stk is this
+// lane's LDS stack, entries at stk[k * stride].  A leaf's triangles are fetched
+// four at a time so their loads are in flight together.
+__device__ int trace(const DevScene& S, V3 o, V3 d, float tmax, bool anyhit, float& t_hit, uint32_t* stk, int stride,
+                     Counters& ctr) {
+    t_hit = tmax;
+    if (!(tmax > S.tmin)) return -1;
     const V3 inv = v3(safe_rcp(d.x), safe_rcp(d.y), safe_rcp(d.z));
     float bt = tmax;
     int best = -1;
@@ -160,23 +165,33 @@ __device__ int trace_closest(const DevScene& S, V3 o, V3 d, float tmax, float& t
         float tn0, tn1;
         bool h0 = n.d.z >= 0 && slab(n.a.x, n.a.y, n.a.z, n.a.w, n.b.x, n.b.y, o, inv, S.tmin, bt, tn0);
         bool h1 = n.d.w >= 0 && slab(n.b.z, n.b.w, n.c.x, n.c.y, n.c.z, n.c.w, o, inv, S.tmin, bt, tn1);
-        // leaves are tested on the spot
 #pragma unroll
         for (int side = 0; side < 2; ++side) {
             const bool h = side ? h1 : h0;
             const int cnt = side ? n.d.w : n.d.z;
             const int first = side ? n.d.y : n.d.x;
             if (h && cnt > 0) {
-                for (int k = first; k < first + cnt; ++k) {
-                    const DevTri T = S.tris[k];
-                    ctr.tris++;
-                    float t;
-                    if (tri_test(T, o, d, S.tmin, t)) {
-                        const uint32_t prim = __float_as_uint(T.v0.w);
-                        if (t < bt || (t == bt && prim < best_prim)) {
-                            bt = t;
-                            best = k;
-                            best_prim = prim;
+                for (int k0 = first; k0 < first + cnt; k0 += 4) {
+                    DevTri T[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (k0 + q < first + cnt) T[q] = S.tris[k0 + q];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        if (k0 + q >= first + cnt) break;
+                        ctr.tris++;
+                        float t;
+                        if (tri_test(T[q], o, d, S.tmin, t) && t <= bt) {
+                            const uint32_t prim = __float_as_uint(T[q].v0.w);
+                            if (anyhit && t < tmax) {
+                                t_hit = t;
+                                return k0 + q;
+                            }
+                            if (t < bt || (t == bt && prim < best_prim)) {
+                                bt = t;
+                                best = k0 + q;
+                                best_prim = prim;
+                            }
                         }
                     }
                 }
@@ -198,50 +213,7 @@ __device__ int trace_closest(const DevScene& S, V3 o, V3 d, float tmax, float& t
         }
     }
     t_hit = bt;
-    return best;
-}
-
-// Any hit in the open interval (tmin, tmax).
-__device__ bool trace_any(const DevScene& S, V3 o, V3 d, float tmax, uint32_t* stk, int stride, Counters& ctr) {
-    const V3 inv = v3(safe_rcp(d.x), safe_rcp(d.y), safe_rcp(d.z));
-    int sp = 0;
-    int node = 0;
-    ctr.rays++;
-    while (true) {
-        const DevNode n = load_node(S.nodes, node);
-        ctr.nodes++;
-        float tn0, tn1;
-        bool h0 = n.d.z >= 0 && slab(n.a.x, n.a.y, n.a.z, n.a.w, n.b.x, n.b.y, o, inv, S.tmin, tmax, tn0);
-        bool h1 = n.d.w >= 0 && slab(n.b.z, n.b.w, n.c.x, n.c.y, n.c.z, n.c.w, o, inv, S.tmin, tmax, tn1);
-#pragma unroll
-        for (int side = 0; side < 2; ++side) {
-            const bool h = side ? h1 : h0;
-            const int cnt = side ? n.d.w : n.d.z;
-            const int first = side ? n.d.y : n.d.x;
-            if (h && cnt > 0) {
-                for (int k = first; k < first + cnt; ++k) {
-                    ctr.tris++;
-                    float t;
-                    if (tri_test(S.tris[k], o, d, S.tmin, t) && t < tmax) return true;
-                }
-            }
-        }
-        h0 = h0 && n.d.z == 0;
-        h1 = h1 && n.d.w == 0;
-        if (h0 && h1) {
-            const bool first0 = tn0 <= tn1;
-            if (sp < DR_STACK) stk[(sp++) * stride] = (uint32_t)(first0 ? n.d.y : n.d.x);
-            node = first0 ? n.d.x : n.d.y;
-        } else if (h0) {
-            node = n.d.x;
-        } else if (h1) {
-            node = n.d.y;
-        } else {
-            if (sp == 0) break;
-            node = (int)stk[(--sp) * stride];
-        }
-    }
-    return false;
+    return anyhit ? -1 : best;
 }
 
 // ---------------------------------------------------------------------------
@@ -359,18 +331,54 @@ __device__ __forceinline__ uint32_t pixel_of(const DevScene& S, float u0, float 
 // U is an accessor: float operator()(int i) returns coordinate i of u.
 // rec (nullable): per vertex j = 1..L-1, rec[(j-1) * rs] = slot << 8 |
 // light << 1 | contributed, or DR_NO_VERTEX.
+//
+// PAIR: two adjacent lanes evaluate the same path.  Both run the same control
+// flow on the same data (so they take the same branches and hold the same
+// values); at each vertex the even lane traces the continuation ray and the
+// odd lane the shadow ray, concurrently, and they swap the results with a
+// lane shuffle.  Without PAIR one lane traces both rays in turn.
 // ---------------------------------------------------------------------------
-template <class U>
+template <bool PAIR>
+__device__ __forceinline__ void trace_vertex_rays(const DevScene& S, V3 x, bool shadow, V3 wl, float smax, bool cont,
+                                                  V3 wi, bool& occluded, int& nslot, float& tn, uint32_t* stk,
+                                                  int stride, Counters& ctr) {
+    if (PAIR) {
+        const bool odd = (threadIdx.x & 1) != 0;
+        float tt;
+        const int r = trace(S, x, odd ? wl : wi, odd ? (shadow ? smax : -1.0f) : (cont ? INFINITY : -1.0f), odd, tt,
+                            stk, stride, ctr);
+        const int ro = __shfl_xor(r, 1);
+        const float to = __shfl_xor(tt, 1);
+        occluded = shadow && (odd ? r : ro) >= 0;
+        nslot = cont ? (odd ? ro : r) : -1;
+        tn = odd ? to : tt;
+    } else {
+        float ts;
+        occluded = shadow && trace(S, x, wl, smax, true, ts, stk, stride, ctr) >= 0;
+        nslot = cont ? trace(S, x, wi, INFINITY, false, tn, stk, stride, ctr) : -1;
+    }
+}
+
+template <bool PAIR, class U>
 __device__ V3 path_forward(const DevScene& S, int L, const U& u, uint32_t* rec, int rs, uint32_t* stk, int stride,
                            Counters& ctr) {
     V3 f = v3(0.f, 0.f, 0.f);
     V3 d = camera_dir(S, u(0), u(1));
-    V3 x;
     float t;
-    int slot = trace_closest(S, S.eye, d, INFINITY, t, stk, stride, ctr);
+    int slot;
+    if (PAIR) {
+        const bool odd = (threadIdx.x & 1) != 0;
+        const int r = trace(S, S.eye, d, odd ? -1.0f : INFINITY, false, t, stk, stride, ctr);
+        slot = __shfl_xor(r, 1);
+        const float to = __shfl_xor(t, 1);
+        if (!odd) slot = r;
+        else t = to;
+    } else {
+        slot = trace(S, S.eye, d, INFINITY, false, t, stk, stride, ctr);
+    }
     int j = 1;
     if (slot >= 0) {
-        x = S.eye + d * t;
+        V3 x = S.eye + d * t;
         DevTri T = S.tris[slot];
         {
             const Material m = load_material(S, __float_as_uint(T.e1.w));
@@ -382,7 +390,7 @@ __device__ V3 path_forward(const DevScene& S, int L, const U& u, uint32_t* rec, 
             const Material m = load_material(S, __float_as_uint(T.e1.w));
             const V3 n = facing_normal(T, d);
             const V3 wo = -d;
-            // next-event estimation
+            // next-event estimation candidate
             float ap;
             const float a = u(4 * j - 2), b = u(4 * j - 1);
             const int li = select_light(a, nl, ap);
@@ -397,22 +405,25 @@ __device__ V3 path_forward(const DevScene& S, int L, const U& u, uint32_t* rec, 
             const float cy = -dot(xyz(l3), wl);
             // both cosines must clear 1e-6 (a vertex in the light's own plane
             // has cosines that are rounding noise around zero)
-            bool contrib = cx > 1e-6f && cy > 1e-6f;
-            if (contrib) contrib = !trace_any(S, x, wl, (1.0f - 1e-4f) * r, stk, stride, ctr);
+            const bool shadow = cx > 1e-6f && cy > 1e-6f;
+            // continuation candidate: BSDF sample at vertex j
+            V3 wi = v3(0.f, 0.f, 1.f), wt = v3(0.f, 0.f, 0.f);
+            const bool cont = j < L - 1 && !(beta.x == 0.0f && beta.y == 0.0f && beta.z == 0.0f) &&
+                              bsdf_sample(m, n, wo, u(4 * j), u(4 * j + 1), wi, wt);
+            bool occluded;
+            int ns;
+            float tn;
+            trace_vertex_rays<PAIR>(S, x, shadow, wl, (1.0f - 1e-4f) * r, cont, wi, occluded, ns, tn, stk, stride,
+                                    ctr);
+            const bool contrib = shadow && !occluded;
             if (rec) rec[(j - 1) * rs] = ((uint32_t)slot << 8) | ((uint32_t)li << 1) | (contrib ? 1u : 0u);
             if (contrib) {
                 const V3 fs = bsdf_eval(m, n, wo, wl);
                 const float g = cx * cy / r2 * ((float)nl * l3.w);
                 f = f + mul(mul(beta, fs), xyz(l4)) * g;
             }
-            if (j == L - 1) break;
-            if (beta.x == 0.0f && beta.y == 0.0f && beta.z == 0.0f) break;
-            V3 wi, wt;
-            if (!bsdf_sample(m, n, wo, u(4 * j), u(4 * j + 1), wi, wt)) break;
-            beta = mul(beta, wt);
-            float tn;
-            const int ns = trace_closest(S, x, wi, INFINITY, tn, stk, stride, ctr);
             if (ns < 0) break;
+            beta = mul(beta, wt);
             x = x + wi * tn;
             d = wi;
             slot = ns;

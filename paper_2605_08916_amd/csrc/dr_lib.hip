@@ -80,10 +80,10 @@ __device__ __forceinline__ void wave_add(unsigned long long* dst, uint32_t v) {
 
 // Hold/kill and splat (Accumulate).  Returns true if the tour survives.
 __device__ __forceinline__ bool hold_kill_splat(const KParams& P, const KBufs& B, const DevScene& S, int c, uint64_t s,
-                                                float k0, V3 f, float p, uint32_t pix) {
+                                                float k0, V3 f, float p, uint32_t pix, bool lead = true) {
     float wdt;
     const bool alive = hold_kill(P.seed, c, s, k0, p, P.eps, P.dt, P.rb, wdt);
-    if (p > 0.0f) {
+    if (lead && p > 0.0f) {
         const float sc = wdt / p;
         const size_t npx = (size_t)S.W * S.H;
         atomicAdd(&B.accum[pix], sc * f.x);
@@ -126,7 +126,7 @@ __global__ void __launch_bounds__(256) k_init_eval(KParams P, DevScene S, KBufs 
     Counters ctr = {0, 0, 0};
     if (c < P.N) {
         regen(P.seed, P.d, P.N, B.x + c, c, s0);
-        const V3 f = path_forward(S, P.L, SoaU{B.x + c, P.N}, B.rec + c, P.N, s_stack + threadIdx.x, blockDim.x, ctr);
+        const V3 f = path_forward<false>(S, P.L, SoaU{B.x + c, P.N}, B.rec + c, P.N, s_stack + threadIdx.x, blockDim.x, ctr);
         B.p_tmp[c] = lum(f);
         B.f_tmp[c] = f.x;
         B.f_tmp[(size_t)P.N + c] = f.y;
@@ -190,14 +190,18 @@ __global__ void __launch_bounds__(256) k_init_accumulate(KParams P, DevScene S, 
     }
 }
 
-// Fused persistent evolve step: every chain advances nsteps steps.
-template <int L>
+// Fused persistent evolve step: every chain advances nsteps steps.  With
+// PAIR, two adjacent lanes share a chain: both run its step on the same data,
+// the path's continuation and shadow rays are traced concurrently (one per
+// lane), and only the even lane performs the atomics.
+template <int L, bool PAIR>
 __global__ void __launch_bounds__(256) k_step_fused(KParams P, DevScene S, KBufs B, uint64_t s0, uint32_t nsteps,
                                                     uint32_t grab) {
     extern __shared__ uint32_t s_stack[];
     uint32_t* stk = s_stack + threadIdx.x;
     const int stride = blockDim.x;
     const int lane = threadIdx.x & 63;
+    const bool lead = PAIR ? (lane & 1) == 0 : true;
     const float k0 = *B.k0;
     int c = -1, cend = -1;
     uint32_t k = nsteps;
@@ -205,7 +209,8 @@ __global__ void __launch_bounds__(256) k_step_fused(KParams P, DevScene S, KBufs
     uint32_t kills = 0, steps = 0, adj = 0;
     while (true) {
         // a lane done with its chain moves to the next of its `grab` chains;
-        // lanes out of chains refill with one queue atomic per wavefront
+        // units (lanes or lane pairs) out of chains refill with one queue
+        // atomic per wavefront
         if (k >= nsteps && c + 1 < cend) {
             ++c;
             k = 0;
@@ -213,12 +218,14 @@ __global__ void __launch_bounds__(256) k_step_fused(KParams P, DevScene S, KBufs
         const bool need = k >= nsteps;
         const uint64_t mask = __ballot(need);
         if (mask) {
-            const int leader = __ffsll((long long)mask) - 1;
+            const uint64_t umask = PAIR ? (mask & 0x5555555555555555ull) : mask;
+            const int leader = __ffsll((long long)umask) - 1;
             uint32_t base = 0;
-            if (lane == leader) base = atomicAdd(B.queue, (uint32_t)__popcll(mask) * grab);
+            if (lane == leader) base = atomicAdd(B.queue, (uint32_t)__popcll(umask) * grab);
             base = __shfl(base, leader);
             if (need) {
-                const uint32_t first = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull)) * grab;
+                const int me = PAIR ? (lane & ~1) : lane;
+                const uint32_t first = base + (uint32_t)__popcll(umask & ((1ull << me) - 1ull)) * grab;
                 c = (int)min(first, (uint32_t)P.N);
                 cend = (int)min(first + grab, (uint32_t)P.N);
                 k = 0;
@@ -229,21 +236,22 @@ __global__ void __launch_bounds__(256) k_step_fused(KParams P, DevScene S, KBufs
         if (active) {
             const uint64_t s = s0 + k;
             float* xc = B.x + c;
+            // both lanes of a pair store identical values
             if (B.killed[c]) regen(P.seed, P.d, P.N, xc, c, s);
             else move(P.seed, P.d, P.N, P.stddev, P.gt, xc, B.score + c, B.sigma ? B.sigma + c : nullptr, c, s);
             const SoaU u{xc, P.N};
-            const V3 f = path_forward(S, L, u, B.rec + c, P.N, stk, stride, ctr);
+            const V3 f = path_forward<PAIR>(S, L, u, B.rec + c, P.N, stk, stride, ctr);
             const float p = lum(f);
             const uint32_t pix = pixel_of(S, xc[0], xc[P.N]);
-            const bool alive = hold_kill_splat(P, B, S, c, s, k0, f, p, pix);
+            const bool alive = hold_kill_splat(P, B, S, c, s, k0, f, p, pix, lead);
             B.killed[c] = alive ? 0u : 1u;
-            kills += alive ? 0u : 1u;
+            if (lead) kills += alive ? 0u : 1u;
             if (alive) {
                 score_at<L>(P, B, S, c, p);
-                ++adj;
+                if (lead) ++adj;
             }
             ++k;
-            ++steps;
+            if (lead) ++steps;
         } else {
             k = 0;  // drained lanes stop asking for work
             cend = c;
@@ -269,7 +277,7 @@ __global__ void __launch_bounds__(256) k_plain_score(KParams P, DevScene S, KBuf
     uint32_t adj = 0;
     if (c < P.N && !B.killed[c]) {
         const SoaU u{B.x + c, P.N};
-        const V3 f = path_forward(S, L, u, B.rec + c, P.N, s_stack + threadIdx.x, blockDim.x, ctr);
+        const V3 f = path_forward<false>(S, L, u, B.rec + c, P.N, s_stack + threadIdx.x, blockDim.x, ctr);
         score_at<L>(P, B, S, c, lum(f));
         adj = 1;
     }
@@ -291,7 +299,7 @@ __global__ void __launch_bounds__(256) k_plain_forward(KParams P, DevScene S, KB
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     Counters ctr = {0, 0, 0};
     if (c < P.N) {
-        const V3 f = path_forward(S, P.L, SoaU{B.x + c, P.N}, B.rec + c, P.N, s_stack + threadIdx.x, blockDim.x, ctr);
+        const V3 f = path_forward<false>(S, P.L, SoaU{B.x + c, P.N}, B.rec + c, P.N, s_stack + threadIdx.x, blockDim.x, ctr);
         B.p_tmp[c] = lum(f);
         B.f_tmp[c] = f.x;
         B.f_tmp[(size_t)P.N + c] = f.y;
@@ -342,7 +350,7 @@ __global__ void __launch_bounds__(256) k_eval(DevScene S, const float* u, int n,
     Counters ctr = {0, 0, 0};
     const RowU uu{u + (size_t)i * d};
     uint32_t* rc = rec_scratch + i;
-    const V3 f = path_forward(S, L, uu, rc, n, s_stack + threadIdx.x, blockDim.x, ctr);
+    const V3 f = path_forward<false>(S, L, uu, rc, n, s_stack + threadIdx.x, blockDim.x, ctr);
     const float p = lum(f);
     if (fo) {
         fo[3 * (size_t)i] = f.x;
@@ -383,7 +391,7 @@ __global__ void __launch_bounds__(256) k_pt(DevScene S, int L, uint64_t seed, ui
     V3 acc = v3(0.f, 0.f, 0.f);
     for (uint32_t k = 0; k < spp; ++k) {
         const PtU u{seed, (uint32_t)pix, (uint64_t)k, S.W, S.H, pix % S.W, pix / S.W};
-        acc = acc + path_forward(S, L, u, nullptr, 0, s_stack + threadIdx.x, blockDim.x, ctr);
+        acc = acc + path_forward<false>(S, L, u, nullptr, 0, s_stack + threadIdx.x, blockDim.x, ctr);
     }
     const float inv = 1.0f / (float)spp;
     img[pix] = acc.x * inv;
@@ -468,7 +476,7 @@ struct dr_chains {
     uint64_t seed = 0, step = 0;
     int n_partials = 0;
     int record = 0, count = 0;
-    dr_launch_cfg launch{256, 2, 1};
+    dr_launch_cfg launch{256, 2, 1, 2};
     int n_cu = 256;
 };
 
@@ -502,8 +510,9 @@ static void launch_init_acc(dim3 g, dim3 b, hipStream_t st, const KParams& P, co
 }
 template <int L>
 static void launch_fused(dim3 g, dim3 b, hipStream_t st, const KParams& P, const DevScene& S, const KBufs& B,
-                         uint64_t s0, uint32_t n, uint32_t grab) {
-    hipLaunchKernelGGL(k_step_fused<L>, g, b, stack_bytes(b.x), st, P, S, B, s0, n, grab);
+                         uint64_t s0, uint32_t n, uint32_t grab, bool pair) {
+    if (pair) hipLaunchKernelGGL((k_step_fused<L, true>), g, b, stack_bytes(b.x), st, P, S, B, s0, n, grab);
+    else hipLaunchKernelGGL((k_step_fused<L, false>), g, b, stack_bytes(b.x), st, P, S, B, s0, n, grab);
 }
 template <int L>
 static void launch_plain_score(dim3 g, dim3 b, hipStream_t st, const KParams& P, const DevScene& S, const KBufs& B) {
@@ -868,10 +877,12 @@ dr_status dr_step(dr_chains* c, uint32_t n_steps, void* hip_stream) {
     if (c->P.mode == DR_MODE_FUSED) {
         hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, c->kb.queue, (size_t)1, 0u);
         const int blk = (int)c->launch.block;
+        const bool pair = c->launch.lanes_per_chain == 2;
+        const long lanes = (long)N * (pair ? 2 : 1);
         int blocks = (int)(c->n_cu * c->launch.blocks_per_cu);
-        blocks = std::max(1, std::min(blocks, (N + blk - 1) / blk));
+        blocks = (int)std::max(1L, std::min((long)blocks, (lanes + blk - 1) / blk));
         DR_DISPATCH_L(P.L, launch_fused, dim3(blocks), dim3(blk), st, P, c->scene->ds, c->kb, c->step, n_steps,
-                      c->launch.grab);
+                      c->launch.grab, pair);
     } else {
         const int blk = 256;
         const dim3 g((N + blk - 1) / blk), b(blk);
@@ -1036,9 +1047,11 @@ dr_status dr_chains_set_launch(dr_chains* c, const dr_launch_cfg* cfg) {
         return fail(DR_ERR_INVALID_ARG, "dr_chains_set_launch: block must be 64, 128, 192 or 256");
     if (cfg->blocks_per_cu > 64) return fail(DR_ERR_INVALID_ARG, "dr_chains_set_launch: blocks_per_cu must be <= 64");
     if (cfg->grab > 64) return fail(DR_ERR_INVALID_ARG, "dr_chains_set_launch: grab must be <= 64");
+    if (cfg->lanes_per_chain > 2) return fail(DR_ERR_INVALID_ARG, "dr_chains_set_launch: lanes_per_chain must be 1 or 2");
     if (cfg->block) c->launch.block = cfg->block;
     if (cfg->blocks_per_cu) c->launch.blocks_per_cu = cfg->blocks_per_cu;
     if (cfg->grab) c->launch.grab = cfg->grab;
+    if (cfg->lanes_per_chain) c->launch.lanes_per_chain = cfg->lanes_per_chain;
     g_err.clear();
     return DR_OK;
 }

@@ -85,7 +85,8 @@ class dr_counters(C.Structure):
 
 
 class dr_launch_cfg(C.Structure):
-    _fields_ = [("block", C.c_uint32), ("blocks_per_cu", C.c_uint32), ("grab", C.c_uint32)]
+    _fields_ = [("block", C.c_uint32), ("blocks_per_cu", C.c_uint32), ("grab", C.c_uint32),
+                ("lanes_per_chain", C.c_uint32)]
 
 
 _lib = None
@@ -336,14 +337,14 @@ class Chains:
         _check(lib().dr_stats(self.h, C.byref(c), _stream(stream)))
         return {k: getattr(c, k) for k, _ in dr_counters._fields_}
 
-    def set_launch(self, block=0, blocks_per_cu=0, grab=0):
-        cfg = dr_launch_cfg(block, blocks_per_cu, grab)
+    def set_launch(self, block=0, blocks_per_cu=0, grab=0, lanes_per_chain=0):
+        cfg = dr_launch_cfg(block, blocks_per_cu, grab, lanes_per_chain)
         _check(lib().dr_chains_set_launch(self.h, C.byref(cfg)))
 
     def get_launch(self) -> dict:
         cfg = dr_launch_cfg()
         _check(lib().dr_chains_get_launch(self.h, C.byref(cfg)))
-        return dict(block=cfg.block, blocks_per_cu=cfg.blocks_per_cu, grab=cfg.grab)
+        return dict(block=cfg.block, blocks_per_cu=cfg.blocks_per_cu, grab=cfg.grab, lanes_per_chain=cfg.lanes_per_chain)
 
     def read_state(self, stream=None) -> dict:
         N, d, V = self.N, self.d, self.L - 1

@@ -404,3 +404,22 @@ def test_counters_and_scene_change(scenes):
     assert e.value.status == dr.DR_ERR_BAD_STATE
     ch.reinit(1)
     ch.step(1)
+
+
+@pytest.mark.parametrize("which,L,N", [("tiny", 4, 1000), ("spheres_small", 8, 3000)])
+def test_paired_lanes_match_single_lane(scenes, which, L, N):
+    """Two lanes per chain (continuation and shadow rays traced concurrently)
+    must give exactly the chains one lane per chain gives."""
+    say(f"[pair vs single] scene={which} L={L} N={N}")
+    S = dr.Scene(scenes[which])
+    out = []
+    for lanes in (1, 2):
+        ch = dr.Chains(S, N, L, 31, k0=250.0)
+        ch.set_launch(lanes_per_chain=lanes)
+        ch.step(6)
+        out.append(ch.read_state())
+    a, b = out
+    assert np.array_equal(a["x"], b["x"]) and np.array_equal(a["killed"], b["killed"])
+    assert np.array_equal(a["score"][:, a["killed"] == 0], b["score"][:, b["killed"] == 0])
+    assert a["tour_count"] == b["tour_count"]
+    assert np.allclose(a["accum"], b["accum"], rtol=1e-5, atol=1e-6)
