@@ -207,7 +207,9 @@ dr_status dr_stats(dr_chains* c, dr_counters* out, void* hip_stream);
  * grid, the number of consecutive chains a lane (or lane pair) takes per pop
  * of the device work queue (1..64), and lanes per chain (1, or 2: the two
  * lanes trace a path's continuation and shadow rays concurrently).  Zeros keep
- * the current value.  Defaults: 256, 2, 1, 2. */
+ * the current value.  Defaults: 256 threads, 3 blocks per compute unit, 1
+ * chain per pop, and 2 lanes per chain when n_chains is below two wavefronts
+ * per SIMD (n_cu * 512), else 1. */
 typedef struct { uint32_t block; uint32_t blocks_per_cu; uint32_t grab; uint32_t lanes_per_chain; } dr_launch_cfg;
 dr_status dr_chains_set_launch(dr_chains* c, const dr_launch_cfg* cfg);
 dr_status dr_chains_get_launch(dr_chains* c, dr_launch_cfg* cfg);
