@@ -114,7 +114,9 @@ dr_status dr_bvh_build(const float* vertices, uint32_t n_vertices, const uint32_
 dr_status dr_scene_create(const dr_scene_desc* desc, int device, dr_scene** out);
 
 /* Replace the camera (a scene change: chains built on this scene must be
- * re-initialised with dr_chains_reinit before the next dr_step, Sec. 4.3). */
+ * re-initialised with dr_chains_reinit before the next dr_step, Sec. 4.3).
+ * Waits for the device to finish the work in flight, then updates the camera
+ * in device memory.  The image size cannot change. */
 dr_status dr_scene_set_camera(dr_scene* s, const dr_camera* cam);
 
 void dr_scene_destroy(dr_scene* s);
@@ -213,6 +215,28 @@ dr_status dr_stats(dr_chains* c, dr_counters* out, void* hip_stream);
 typedef struct { uint32_t block; uint32_t blocks_per_cu; uint32_t grab; uint32_t lanes_per_chain; } dr_launch_cfg;
 dr_status dr_chains_set_launch(dr_chains* c, const dr_launch_cfg* cfg);
 dr_status dr_chains_get_launch(dr_chains* c, dr_launch_cfg* cfg);
+
+/* ------------------------------------------------------------------------
+ * Captured frames (the real-time loop of Sec. 4.3 and 6: scene change ->
+ * re-initialise, evolve, resolve once per displayed frame)
+ * ------------------------------------------------------------------------ */
+typedef struct dr_frame dr_frame;
+
+/* Capture one frame as a HIP graph on hip_stream (must not be the default
+ * stream): if reinit, the initialise pass of the next frame (the device frame
+ * counter advances by one per launch, starting after the last dr_chains_init
+ * or dr_chains_reinit frame); then n_steps evolve steps; then the resolve into
+ * image_dev (3*W*H floats, device, borrowed for the frame's lifetime).  Step
+ * and frame counters and the camera are read from device memory, so every
+ * launch continues the chains and sees dr_scene_set_camera updates.  Record
+ * and counter switches are fixed at capture time.  The capture enqueues no
+ * memset and no allocation. */
+dr_status dr_frame_capture(dr_chains* c, uint32_t n_steps, int reinit, float* image_dev, void* hip_stream,
+                           dr_frame** out);
+/* Launch a captured frame (asynchronous).  DR_ERR_BAD_STATE if the scene
+ * changed and the frame does not re-initialise. */
+dr_status dr_frame_launch(dr_frame* f, void* hip_stream);
+dr_status dr_frame_destroy(dr_frame* f);
 
 /* ------------------------------------------------------------------------
  * Path-space evaluation (differentiation surface)

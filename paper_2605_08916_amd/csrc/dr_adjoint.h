@@ -44,11 +44,11 @@ __device__ __forceinline__ float plane_t(const DevTri& T, V3 ng, V3 o, V3 d) {
 }
 
 // Camera vertex (vertex 1) state.
-__device__ __forceinline__ VState camera_state(const DevScene& S, float u0, float u1, const DevTri& T1) {
-    const V3 d = camera_dir(S, u0, u1);
+__device__ __forceinline__ VState camera_state(const Cam& C, float u0, float u1, const DevTri& T1) {
+    const V3 d = camera_dir(C, u0, u1);
     const V3 ng = normalize(cross(xyz(T1.e1), xyz(T1.e2)));
     VState s;
-    s.x = S.eye + d * plane_t(T1, ng, S.eye, d);
+    s.x = C.eye + d * plane_t(T1, ng, C.eye, d);
     s.din = d;
     s.beta = v3(1.f, 1.f, 1.f);
     return s;
@@ -257,6 +257,7 @@ __device__ void path_score(const DevScene& S, const U& u, const uint32_t* rec, i
         return;
     }
     const float inv_pe = 1.0f / (p + eps);
+    const Cam Cm = load_cam(S);
     uint32_t R[V + 1];
 #pragma unroll
     for (int j = 1; j <= V; ++j) R[j] = rec[(j - 1) * rs];
@@ -265,7 +266,7 @@ __device__ void path_score(const DevScene& S, const U& u, const uint32_t* rec, i
     // checkpoints at the first vertex of every segment
     VState cp[NSEG];
     {
-        VState st = camera_state(S, u(0), u(1), S.tris[rec_slot(R[1])]);
+        VState st = camera_state(Cm, u(0), u(1), S.tris[rec_slot(R[1])]);
 #pragma unroll
         for (int j = 1; j <= V; ++j) {
             if ((j - 1) % DR_SEG == 0) cp[(j - 1) / DR_SEG] = st;
@@ -312,17 +313,17 @@ __device__ void path_score(const DevScene& S, const U& u, const uint32_t* rec, i
     // camera: x1 = eye + t1 d, d = D/|D|, D = cw + (2u0-1) cu + (1-2u1) cv
     {
         const float u0 = u(0), u1 = u(1);
-        const V3 D = S.cw + S.cu * (2.0f * u0 - 1.0f) + S.cv * (1.0f - 2.0f * u1);
+        const V3 D = Cm.cw + Cm.cu * (2.0f * u0 - 1.0f) + Cm.cv * (1.0f - 2.0f * u1);
         const float Dl = sqrtf(dot(D, D));
         const V3 d = D * (1.0f / Dl);
         const DevTri T1 = S.tris[rec_slot(R[1])];
         const V3 ng = normalize(cross(xyz(T1.e1), xyz(T1.e2)));
         const float Dn = dot(ng, d);
-        const float t1 = dot(ng, xyz(T1.v0) - S.eye) / Dn;
+        const float t1 = dot(ng, xyz(T1.v0) - Cm.eye) / Dn;
         const float sc = dot(a.gx, d) / Dn;
         const V3 gd = a.gd + (a.gx - ng * sc) * t1;
         const V3 gD = (gd - d * dot(d, gd)) * (1.0f / Dl);
-        float g0 = 2.0f * dot(gD, S.cu) * inv_pe, g1 = -2.0f * dot(gD, S.cv) * inv_pe;
+        float g0 = 2.0f * dot(gD, Cm.cu) * inv_pe, g1 = -2.0f * dot(gD, Cm.cv) * inv_pe;
         if (!isfinite(g0)) g0 = 0.0f;
         if (!isfinite(g1)) g1 = 0.0f;
         out[0] = g0;

@@ -85,11 +85,23 @@ struct DevScene {
     const DevTri* tris;
     const float4* mats;
     const float4* lights;
+    const float4* cam;   // camera in device memory (so captured graphs see updates):
+                         // eye, cu, cv, cw; ray direction = cw + (2u0-1) cu + (1-2u1) cv
     int n_lights;
     float tmin;
-    V3 eye, cu, cv, cw;  // camera ray direction = cw + (2u0-1) cu + (1-2u1) cv
     int W, H;
 };
+struct Cam {
+    V3 eye, cu, cv, cw;
+};
+__device__ __forceinline__ Cam load_cam(const DevScene& S) {
+    Cam c;
+    c.eye = v3(S.cam[0].x, S.cam[0].y, S.cam[0].z);
+    c.cu = v3(S.cam[1].x, S.cam[1].y, S.cam[1].z);
+    c.cv = v3(S.cam[2].x, S.cam[2].y, S.cam[2].z);
+    c.cw = v3(S.cam[3].x, S.cam[3].y, S.cam[3].z);
+    return c;
+}
 
 struct Counters {
     uint32_t rays, nodes, tris;
@@ -314,8 +326,8 @@ __device__ __forceinline__ int select_light(float a, int nl, float& ap) {
 }
 
 // Camera ray direction for the film block.
-__device__ __forceinline__ V3 camera_dir(const DevScene& S, float u0, float u1) {
-    return normalize(S.cw + S.cu * (2.0f * u0 - 1.0f) + S.cv * (1.0f - 2.0f * u1));
+__device__ __forceinline__ V3 camera_dir(const Cam& C, float u0, float u1) {
+    return normalize(C.cw + C.cu * (2.0f * u0 - 1.0f) + C.cv * (1.0f - 2.0f * u1));
 }
 
 // Pixel of the film block, in FP32: px = min(floor(u0 W), W-1), row 0 at top.
@@ -363,22 +375,23 @@ template <bool PAIR, class U>
 __device__ V3 path_forward(const DevScene& S, int L, const U& u, uint32_t* rec, int rs, uint32_t* stk, int stride,
                            Counters& ctr) {
     V3 f = v3(0.f, 0.f, 0.f);
-    V3 d = camera_dir(S, u(0), u(1));
+    const Cam C = load_cam(S);
+    V3 d = camera_dir(C, u(0), u(1));
     float t;
     int slot;
     if (PAIR) {
         const bool odd = (threadIdx.x & 1) != 0;
-        const int r = trace(S, S.eye, d, odd ? -1.0f : INFINITY, false, t, stk, stride, ctr);
+        const int r = trace(S, C.eye, d, odd ? -1.0f : INFINITY, false, t, stk, stride, ctr);
         slot = __shfl_xor(r, 1);
         const float to = __shfl_xor(t, 1);
         if (!odd) slot = r;
         else t = to;
     } else {
-        slot = trace(S, S.eye, d, INFINITY, false, t, stk, stride, ctr);
+        slot = trace(S, C.eye, d, INFINITY, false, t, stk, stride, ctr);
     }
     int j = 1;
     if (slot >= 0) {
-        V3 x = S.eye + d * t;
+        V3 x = C.eye + d * t;
         DevTri T = S.tris[slot];
         {
             const Material m = load_material(S, __float_as_uint(T.e1.w));

@@ -60,6 +60,9 @@ struct KBufs {
     float* r_w;          // N (record)
     double* partial;     // reduction partials
     float* img;          // 3 x W*H resolved image (dr_image_read)
+    // step counters in device memory so captured graphs replay correctly:
+    // [0] next step index, [1] first step index of the current launch, [2] frame
+    unsigned long long* steps;
 };
 
 enum { C_TOURS = 0, C_STEPS = 1, C_RAYS = 2, C_NODES = 3, C_TRIS = 4, C_ADJ = 5, C_N = 8 };
@@ -119,10 +122,30 @@ __global__ void k_fill_u64(unsigned long long* a, int n) {
     if (threadIdx.x < (unsigned)n) a[threadIdx.x] = 0ull;
 }
 
+// Start of an evolve launch of n steps: reset the work queue and advance the
+// device step counter (one thread).
+__global__ void k_begin_launch(KBufs B, uint32_t n) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    *B.queue = 0u;
+    B.steps[1] = B.steps[0];
+    B.steps[0] += n;
+}
+// Start of an initialise pass: frame index `frame`, or the device frame
+// counter plus one when from_device (a captured frame advances it each replay);
+// the pass uses step frame << 32 and the next step is that plus one.
+__global__ void k_begin_init(KBufs B, uint32_t frame, int from_device) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const unsigned long long f = from_device ? B.steps[2] + 1ull : (unsigned long long)frame;
+    B.steps[2] = f;
+    B.steps[1] = f << 32;
+    B.steps[0] = (f << 32) + 1ull;
+}
+
 // Initialise, phase 1: x ~ mu and f(x) for every chain (Alg. 4.1).
-__global__ void __launch_bounds__(256) k_init_eval(KParams P, DevScene S, KBufs B, uint64_t s0) {
+__global__ void __launch_bounds__(256) k_init_eval(KParams P, DevScene S, KBufs B) {
     extern __shared__ uint32_t s_stack[];
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t s0 = B.steps[1];
     Counters ctr = {0, 0, 0};
     if (c < P.N) {
         regen(P.seed, P.d, P.N, B.x + c, c, s0);
@@ -169,8 +192,9 @@ __global__ void k_finish_k0(KParams P, KBufs B, int nparts, double k0_given, dou
 
 // Initialise, phase 2: hold/kill/splat with the final k0, then scores.
 template <int L>
-__global__ void __launch_bounds__(256) k_init_accumulate(KParams P, DevScene S, KBufs B, uint64_t s0, int with_score) {
+__global__ void __launch_bounds__(256) k_init_accumulate(KParams P, DevScene S, KBufs B, int with_score) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t s0 = B.steps[1];
     uint32_t kill = 0, adj = 0;
     if (c < P.N) {
         const float p = B.p_tmp[c];
@@ -195,14 +219,14 @@ __global__ void __launch_bounds__(256) k_init_accumulate(KParams P, DevScene S, 
 // the path's continuation and shadow rays are traced concurrently (one per
 // lane), and only the even lane performs the atomics.
 template <int L, bool PAIR>
-__global__ void __launch_bounds__(256) k_step_fused(KParams P, DevScene S, KBufs B, uint64_t s0, uint32_t nsteps,
-                                                    uint32_t grab) {
+__global__ void __launch_bounds__(256) k_step_fused(KParams P, DevScene S, KBufs B, uint32_t nsteps, uint32_t grab) {
     extern __shared__ uint32_t s_stack[];
     uint32_t* stk = s_stack + threadIdx.x;
     const int stride = blockDim.x;
     const int lane = threadIdx.x & 63;
     const bool lead = PAIR ? (lane & 1) == 0 : true;
     const float k0 = *B.k0;
+    const uint64_t s0 = B.steps[1];
     int c = -1, cend = -1;
     uint32_t k = nsteps;
     Counters ctr = {0, 0, 0};
@@ -288,9 +312,10 @@ __global__ void __launch_bounds__(256) k_plain_score(KParams P, DevScene S, KBuf
         wave_add(&B.ctr[C_TRIS], ctr.tris);
     }
 }
-__global__ void __launch_bounds__(256) k_plain_move(KParams P, KBufs B, uint64_t s) {
+__global__ void __launch_bounds__(256) k_plain_move(KParams P, KBufs B) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= P.N) return;
+    const uint64_t s = B.steps[1];
     if (B.killed[c]) regen(P.seed, P.d, P.N, B.x + c, c, s);
     else move(P.seed, P.d, P.N, P.stddev, P.gt, B.x + c, B.score + c, B.sigma ? B.sigma + c : nullptr, c, s);
 }
@@ -312,8 +337,9 @@ __global__ void __launch_bounds__(256) k_plain_forward(KParams P, DevScene S, KB
         wave_add(&B.ctr[C_TRIS], ctr.tris);
     }
 }
-__global__ void __launch_bounds__(256) k_plain_accumulate(KParams P, DevScene S, KBufs B, uint64_t s) {
+__global__ void __launch_bounds__(256) k_plain_accumulate(KParams P, DevScene S, KBufs B) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t s = B.steps[1];
     uint32_t kill = 0;
     if (c < P.N) {
         const float p = B.p_tmp[c];
@@ -429,7 +455,7 @@ struct DevAlloc {
     }
 };
 
-void camera_basis(const dr_camera& c, DevScene& S) {
+void camera_basis(const dr_camera& c, float4 out[4]) {
     double eye[3] = {c.eye[0], c.eye[1], c.eye[2]}, at[3] = {c.at[0], c.at[1], c.at[2]}, up[3] = {c.up[0], c.up[1], c.up[2]};
     double w[3] = {eye[0] - at[0], eye[1] - at[1], eye[2] - at[2]};
     double wl = std::sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
@@ -440,12 +466,10 @@ void camera_basis(const dr_camera& c, DevScene& S) {
     double v[3] = {w[1] * u[2] - w[2] * u[1], w[2] * u[0] - w[0] * u[2], w[0] * u[1] - w[1] * u[0]};
     const double th = std::tan(0.5 * (double)c.vfov_deg * M_PI / 180.0);
     const double aspect = (double)c.width / (double)c.height;
-    S.eye = v3(c.eye[0], c.eye[1], c.eye[2]);
-    S.cu = v3((float)(u[0] * th * aspect), (float)(u[1] * th * aspect), (float)(u[2] * th * aspect));
-    S.cv = v3((float)(v[0] * th), (float)(v[1] * th), (float)(v[2] * th));
-    S.cw = v3((float)-w[0], (float)-w[1], (float)-w[2]);
-    S.W = (int)c.width;
-    S.H = (int)c.height;
+    out[0] = make_float4(c.eye[0], c.eye[1], c.eye[2], 0.f);
+    out[1] = make_float4((float)(u[0] * th * aspect), (float)(u[1] * th * aspect), (float)(u[2] * th * aspect), 0.f);
+    out[2] = make_float4((float)(v[0] * th), (float)(v[1] * th), (float)(v[2] * th), 0.f);
+    out[3] = make_float4((float)-w[0], (float)-w[1], (float)-w[2], 0.f);
 }
 
 int g_num_cu(int dev) {
@@ -473,7 +497,7 @@ struct dr_chains {
     KParams kp{};
     KBufs kb{};
     DevAlloc mem;
-    uint64_t seed = 0, step = 0;
+    uint64_t seed = 0;
     int n_partials = 0;
     int record = 0, count = 0;
     dr_launch_cfg launch{256, 2, 1, 2};
@@ -505,14 +529,14 @@ static size_t stack_bytes(int block) { return (size_t)DR_STACK * block * sizeof(
 
 template <int L>
 static void launch_init_acc(dim3 g, dim3 b, hipStream_t st, const KParams& P, const DevScene& S, const KBufs& B,
-                            uint64_t s0, int with_score) {
-    hipLaunchKernelGGL(k_init_accumulate<L>, g, b, 0, st, P, S, B, s0, with_score);
+                            int with_score) {
+    hipLaunchKernelGGL(k_init_accumulate<L>, g, b, 0, st, P, S, B, with_score);
 }
 template <int L>
 static void launch_fused(dim3 g, dim3 b, hipStream_t st, const KParams& P, const DevScene& S, const KBufs& B,
-                         uint64_t s0, uint32_t n, uint32_t grab, bool pair) {
-    if (pair) hipLaunchKernelGGL((k_step_fused<L, true>), g, b, stack_bytes(b.x), st, P, S, B, s0, n, grab);
-    else hipLaunchKernelGGL((k_step_fused<L, false>), g, b, stack_bytes(b.x), st, P, S, B, s0, n, grab);
+                         uint32_t n, uint32_t grab, bool pair) {
+    if (pair) hipLaunchKernelGGL((k_step_fused<L, true>), g, b, stack_bytes(b.x), st, P, S, B, n, grab);
+    else hipLaunchKernelGGL((k_step_fused<L, false>), g, b, stack_bytes(b.x), st, P, S, B, n, grab);
 }
 template <int L>
 static void launch_plain_score(dim3 g, dim3 b, hipStream_t st, const KParams& P, const DevScene& S, const KBufs& B) {
@@ -524,27 +548,73 @@ static void launch_eval(dim3 g, dim3 b, hipStream_t st, const DevScene& S, const
     hipLaunchKernelGGL(k_eval<L>, g, b, stack_bytes(b.x), st, S, u, n, eps, fo, logp, grad, rs, ro);
 }
 
-static dr_status run_init(dr_chains* c, uint32_t frame, hipStream_t st) {
+// Enqueue the initialise pass (Alg. 4.1).  from_device: take the frame index
+// from the device frame counter plus one (used inside captured frames).
+static void enqueue_init(dr_chains* c, uint32_t frame, int from_device, hipStream_t st) {
     const int N = c->kp.N;
     const int blk = 256;
     const dim3 g((N + blk - 1) / blk), b(blk);
-    const uint64_t s0 = (uint64_t)frame << 32;
     const size_t npx = (size_t)c->scene->ds.W * c->scene->ds.H;
     KParams P = c->kp;
     P.record = c->record;
     P.count = c->count;
+    hipLaunchKernelGGL(k_begin_init, dim3(1), dim3(64), 0, st, c->kb, frame, from_device);
     hipLaunchKernelGGL(k_fill_f32, dim3(1024), dim3(256), 0, st, c->kb.accum, 3 * npx);
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, c->kb.ctr, (int)C_N);
-    hipLaunchKernelGGL(k_init_eval, g, b, stack_bytes(blk), st, P, c->scene->ds, c->kb, s0);
+    hipLaunchKernelGGL(k_init_eval, g, b, stack_bytes(blk), st, P, c->scene->ds, c->kb);
     hipLaunchKernelGGL(k_reduce_p, dim3(c->n_partials), dim3(256), 0, st, P, c->kb);
     hipLaunchKernelGGL(k_finish_k0, dim3(1), dim3(64), 0, st, P, c->kb, c->n_partials, (double)c->P.k0, (double)c->P.m);
     const int with_score = c->P.mode == DR_MODE_FUSED ? 1 : 0;
-    DR_DISPATCH_L(c->kp.L, launch_init_acc, g, b, st, P, c->scene->ds, c->kb, s0, with_score);
+    DR_DISPATCH_L(c->kp.L, launch_init_acc, g, b, st, P, c->scene->ds, c->kb, with_score);
+}
+
+// Enqueue n_steps evolve steps (Alg. 4.2) in the chain set's form.
+static void enqueue_steps(dr_chains* c, uint32_t n_steps, hipStream_t st) {
+    KParams P = c->kp;
+    P.record = c->record;
+    P.count = c->count;
+    const int N = P.N;
+    if (c->P.mode == DR_MODE_FUSED) {
+        hipLaunchKernelGGL(k_begin_launch, dim3(1), dim3(64), 0, st, c->kb, n_steps);
+        const int blk = (int)c->launch.block;
+        const bool pair = c->launch.lanes_per_chain == 2;
+        const long lanes = (long)N * (pair ? 2 : 1);
+        int blocks = (int)(c->n_cu * c->launch.blocks_per_cu);
+        blocks = (int)std::max(1L, std::min((long)blocks, (lanes + blk - 1) / blk));
+        DR_DISPATCH_L(P.L, launch_fused, dim3(blocks), dim3(blk), st, P, c->scene->ds, c->kb, n_steps,
+                      c->launch.grab, pair);
+    } else {
+        const int blk = 256;
+        const dim3 g((N + blk - 1) / blk), b(blk);
+        for (uint32_t k = 0; k < n_steps; ++k) {
+            hipLaunchKernelGGL(k_begin_launch, dim3(1), dim3(64), 0, st, c->kb, 1u);
+            DR_DISPATCH_L(P.L, launch_plain_score, g, b, st, P, c->scene->ds, c->kb);
+            hipLaunchKernelGGL(k_plain_move, g, b, 0, st, P, c->kb);
+            hipLaunchKernelGGL(k_plain_forward, g, b, stack_bytes(blk), st, P, c->scene->ds, c->kb);
+            hipLaunchKernelGGL(k_plain_accumulate, g, b, 0, st, P, c->scene->ds, c->kb);
+        }
+    }
+}
+
+static void enqueue_resolve(dr_chains* c, float* image_dev, hipStream_t st) {
+    const size_t npx = (size_t)c->scene->ds.W * c->scene->ds.H;
+    hipLaunchKernelGGL(k_resolve, dim3(std::min<size_t>(4096, (3 * npx + 255) / 256)), dim3(256), 0, st, c->kb.accum,
+                       image_dev, npx, c->kb.k0d, c->kb.ctr, (double)c->P.dt);
+}
+
+static dr_status run_init(dr_chains* c, uint32_t frame, hipStream_t st) {
+    enqueue_init(c, frame, 0, st);
     HIP_TRY(hipGetLastError());
-    c->step = s0 + 1;
     c->cam_version = c->scene->cam_version;
     return DR_OK;
 }
+
+struct dr_frame {
+    dr_chains* c = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int reinit = 0;
+};
 
 extern "C" {
 
@@ -737,8 +807,11 @@ dr_status dr_scene_create(const dr_scene_desc* desc, int device, dr_scene** out)
     HIP_TRY(hipSetDevice(device));
     auto* S = new dr_scene();
     S->device = device;
-    void *dnodes, *dtris, *dmats, *dlights;
-    if (S->mem.get(&dnodes, dn.size() * sizeof(DevNode)) != hipSuccess ||
+    void *dnodes, *dtris, *dmats, *dlights, *dcam;
+    float4 cam4[4];
+    camera_basis(desc->camera, cam4);
+    if (S->mem.get(&dcam, sizeof(cam4)) != hipSuccess ||
+        S->mem.get(&dnodes, dn.size() * sizeof(DevNode)) != hipSuccess ||
         S->mem.get(&dtris, tris.size() * sizeof(DevTri)) != hipSuccess ||
         S->mem.get(&dmats, mats.size() * sizeof(float4)) != hipSuccess ||
         S->mem.get(&dlights, lights.size() * sizeof(float4)) != hipSuccess) {
@@ -746,7 +819,8 @@ dr_status dr_scene_create(const dr_scene_desc* desc, int device, dr_scene** out)
         delete S;
         return fail(DR_ERR_OUT_OF_MEMORY, "dr_scene_create: device allocation failed");
     }
-    if (hipMemcpy(dnodes, dn.data(), dn.size() * sizeof(DevNode), hipMemcpyHostToDevice) != hipSuccess ||
+    if (hipMemcpy(dcam, cam4, sizeof(cam4), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(dnodes, dn.data(), dn.size() * sizeof(DevNode), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(dtris, tris.data(), tris.size() * sizeof(DevTri), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(dmats, mats.data(), mats.size() * sizeof(float4), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(dlights, lights.data(), lights.size() * sizeof(float4), hipMemcpyHostToDevice) != hipSuccess) {
@@ -760,7 +834,9 @@ dr_status dr_scene_create(const dr_scene_desc* desc, int device, dr_scene** out)
     S->ds.lights = (const float4*)dlights;
     S->ds.n_lights = (int)desc->n_lights;
     S->ds.tmin = (float)(1e-4 * diag);
-    camera_basis(desc->camera, S->ds);
+    S->ds.cam = (const float4*)dcam;
+    S->ds.W = (int)desc->camera.width;
+    S->ds.H = (int)desc->camera.height;
     S->cam = desc->camera;
     S->slot_to_prim = std::move(slot_to_prim);
     S->n_tris = T;
@@ -773,8 +849,13 @@ dr_status dr_scene_set_camera(dr_scene* s, const dr_camera* cam) {
     if (!s || !cam) return fail(DR_ERR_INVALID_ARG, "dr_scene_set_camera: null argument");
     if (cam->width != s->cam.width || cam->height != s->cam.height)
         return fail(DR_ERR_INVALID_ARG, "dr_scene_set_camera: image size cannot change");
+    float4 cam4[4];
+    camera_basis(*cam, cam4);
+    HIP_TRY(hipSetDevice(s->device));
+    // work in flight may still read the camera: wait for it, then update
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy((void*)s->ds.cam, cam4, sizeof(cam4), hipMemcpyHostToDevice));
     s->cam = *cam;
-    camera_basis(*cam, s->ds);
     s->cam_version++;
     g_err.clear();
     return DR_OK;
@@ -836,6 +917,7 @@ dr_status dr_chains_init(dr_scene* s, const dr_params* p, uint64_t seed, uint32_
     get(&q, sizeof(float) * N); B.r_w = (float*)q;
     get(&q, sizeof(double) * c->n_partials); B.partial = (double*)q;
     get(&q, sizeof(float) * 3 * npx); B.img = (float*)q;
+    get(&q, 64); B.steps = (unsigned long long*)q;
     B.sigma = p->sigma_diag;
     if (!ok) {
         c->mem.release();
@@ -873,33 +955,8 @@ dr_status dr_step(dr_chains* c, uint32_t n_steps, void* hip_stream) {
         return fail(DR_ERR_BAD_STATE, "dr_step: the scene changed since init; call dr_chains_reinit");
     if (n_steps == 0) { g_err.clear(); return DR_OK; }
     HIP_TRY(hipSetDevice(c->scene->device));
-    hipStream_t st = (hipStream_t)hip_stream;
-    KParams P = c->kp;
-    P.record = c->record;
-    P.count = c->count;
-    const int N = P.N;
-    if (c->P.mode == DR_MODE_FUSED) {
-        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, c->kb.queue, (size_t)1, 0u);
-        const int blk = (int)c->launch.block;
-        const bool pair = c->launch.lanes_per_chain == 2;
-        const long lanes = (long)N * (pair ? 2 : 1);
-        int blocks = (int)(c->n_cu * c->launch.blocks_per_cu);
-        blocks = (int)std::max(1L, std::min((long)blocks, (lanes + blk - 1) / blk));
-        DR_DISPATCH_L(P.L, launch_fused, dim3(blocks), dim3(blk), st, P, c->scene->ds, c->kb, c->step, n_steps,
-                      c->launch.grab, pair);
-    } else {
-        const int blk = 256;
-        const dim3 g((N + blk - 1) / blk), b(blk);
-        for (uint32_t k = 0; k < n_steps; ++k) {
-            const uint64_t s = c->step + k;
-            DR_DISPATCH_L(P.L, launch_plain_score, g, b, st, P, c->scene->ds, c->kb);
-            hipLaunchKernelGGL(k_plain_move, g, b, 0, st, P, c->kb, s);
-            hipLaunchKernelGGL(k_plain_forward, g, b, stack_bytes(blk), st, P, c->scene->ds, c->kb);
-            hipLaunchKernelGGL(k_plain_accumulate, g, b, 0, st, P, c->scene->ds, c->kb, s);
-        }
-    }
+    enqueue_steps(c, n_steps, (hipStream_t)hip_stream);
     HIP_TRY(hipGetLastError());
-    c->step += n_steps;
     g_err.clear();
     return DR_OK;
 }
@@ -907,9 +964,7 @@ dr_status dr_step(dr_chains* c, uint32_t n_steps, void* hip_stream) {
 dr_status dr_resolve(dr_chains* c, float* image_dev, void* hip_stream) {
     if (!c || !image_dev) return fail(DR_ERR_INVALID_ARG, "dr_resolve: null argument");
     HIP_TRY(hipSetDevice(c->scene->device));
-    const size_t npx = (size_t)c->scene->ds.W * c->scene->ds.H;
-    hipLaunchKernelGGL(k_resolve, dim3(std::min<size_t>(4096, (3 * npx + 255) / 256)), dim3(256), 0,
-                       (hipStream_t)hip_stream, c->kb.accum, image_dev, npx, c->kb.k0d, c->kb.ctr, (double)c->P.dt);
+    enqueue_resolve(c, image_dev, (hipStream_t)hip_stream);
     HIP_TRY(hipGetLastError());
     g_err.clear();
     return DR_OK;
@@ -973,7 +1028,9 @@ dr_status dr_chains_read_state(dr_chains* c, dr_state* o, void* hip_stream) {
     double k0 = 0, pl = 0;
     HIP_TRY(hipMemcpy(&k0, B.k0d, sizeof(double), hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(&pl, B.plam, sizeof(double), hipMemcpyDeviceToHost));
-    o->step = c->step;
+    unsigned long long steps[3];
+    HIP_TRY(hipMemcpy(steps, B.steps, sizeof(steps), hipMemcpyDeviceToHost));
+    o->step = steps[0];
     o->tour_count = ctr[C_TOURS];
     o->k0 = k0;
     o->p_lambda_hat = pl;
@@ -1007,7 +1064,12 @@ dr_status dr_chains_write_state(dr_chains* c, const dr_state* in, void* hip_stre
         HIP_TRY(hipMemcpy(B.k0d, &k0, sizeof(double), hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(B.k0, &k0f, sizeof(float), hipMemcpyHostToDevice));
     }
-    c->step = in->step;
+    {
+        unsigned long long steps[3];
+        HIP_TRY(hipMemcpy(steps, B.steps, sizeof(steps), hipMemcpyDeviceToHost));
+        steps[0] = in->step;
+        HIP_TRY(hipMemcpy(B.steps, steps, sizeof(steps), hipMemcpyHostToDevice));
+    }
     g_err.clear();
     return DR_OK;
 }
@@ -1096,6 +1158,57 @@ dr_status dr_pt_render(dr_scene* s, uint32_t L, uint64_t seed, uint32_t spp, flo
     hipLaunchKernelGGL(k_pt, dim3((npx + blk - 1) / blk), dim3(blk), stack_bytes(blk), (hipStream_t)hip_stream, s->ds,
                        (int)L, seed, spp, img_dev);
     HIP_TRY(hipGetLastError());
+    g_err.clear();
+    return DR_OK;
+}
+
+dr_status dr_frame_capture(dr_chains* c, uint32_t n_steps, int reinit, float* image_dev, void* hip_stream,
+                           dr_frame** out) {
+    if (!c || !image_dev || !out) return fail(DR_ERR_INVALID_ARG, "dr_frame_capture: null argument");
+    if (!hip_stream) return fail(DR_ERR_INVALID_ARG, "dr_frame_capture: needs a non-default stream to capture on");
+    HIP_TRY(hipSetDevice(c->scene->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    if (reinit) enqueue_init(c, 0, 1, st);
+    if (n_steps) enqueue_steps(c, n_steps, st);
+    enqueue_resolve(c, image_dev, st);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(st, &g);
+    if (e != hipSuccess) return fail(DR_ERR_DEVICE, std::string("dr_frame_capture: ") + hipGetErrorString(e));
+    hipGraphExec_t ge = nullptr;
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(DR_ERR_DEVICE, std::string("dr_frame_capture: instantiate: ") + hipGetErrorString(e));
+    }
+    auto* f = new dr_frame();
+    f->c = c;
+    f->graph = g;
+    f->exec = ge;
+    f->reinit = reinit ? 1 : 0;
+    *out = f;
+    g_err.clear();
+    return DR_OK;
+}
+
+dr_status dr_frame_launch(dr_frame* f, void* hip_stream) {
+    if (!f) return fail(DR_ERR_INVALID_ARG, "dr_frame_launch: null handle");
+    dr_chains* c = f->c;
+    if (!f->reinit && c->cam_version != c->scene->cam_version)
+        return fail(DR_ERR_BAD_STATE, "dr_frame_launch: the scene changed and this frame does not re-initialise");
+    HIP_TRY(hipSetDevice(c->scene->device));
+    HIP_TRY(hipGraphLaunch(f->exec, (hipStream_t)hip_stream));
+    if (f->reinit) c->cam_version = c->scene->cam_version;
+    g_err.clear();
+    return DR_OK;
+}
+
+dr_status dr_frame_destroy(dr_frame* f) {
+    if (!f) return DR_OK;
+    (void)hipSetDevice(f->c->scene->device);
+    if (f->exec) (void)hipGraphExecDestroy(f->exec);
+    if (f->graph) (void)hipGraphDestroy(f->graph);
+    delete f;
     g_err.clear();
     return DR_OK;
 }

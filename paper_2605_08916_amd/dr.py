@@ -25,6 +25,7 @@ EXPORTED = [
     "dr_chains_init", "dr_chains_reinit", "dr_step", "dr_resolve", "dr_image_read", "dr_chains_destroy",
     "dr_chains_read_state", "dr_chains_write_state", "dr_chains_set_record", "dr_chains_set_counters", "dr_stats",
     "dr_chains_set_launch", "dr_chains_get_launch", "dr_eval_logp_grad", "dr_pt_render",
+    "dr_frame_capture", "dr_frame_launch", "dr_frame_destroy",
 ]
 
 
@@ -126,6 +127,9 @@ def lib():
         "dr_chains_get_launch": ([P, C.POINTER(dr_launch_cfg)], st),
         "dr_eval_logp_grad": ([P, C.c_uint32, P, C.c_uint32, C.c_float, P, P, P, P, P], st),
         "dr_pt_render": ([P, C.c_uint32, C.c_uint64, C.c_uint32, P, P], st),
+        "dr_frame_capture": ([P, C.c_uint32, C.c_int, P, P, pp], st),
+        "dr_frame_launch": ([P, P], st),
+        "dr_frame_destroy": ([P], st),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -246,7 +250,10 @@ class Scene:
             self.h = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:
+            pass
 
     def eval_logp_grad(self, L: int, u, eps: float = 1e-8, grad: bool = True, rec: bool = False, stream=None):
         """u: CUDA float32 tensor (n, d).  Returns (f, logp, grad or None,
@@ -305,7 +312,10 @@ class Chains:
             self.h = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:
+            pass
 
     def reinit(self, frame: int, stream=None):
         _check(lib().dr_chains_reinit(self.h, frame, _stream(stream)))
@@ -361,6 +371,14 @@ class Chains:
         out.update(step=s.step, tour_count=s.tour_count, k0=s.k0, p_lambda_hat=s.p_lambda_hat)
         return out
 
+    def capture_frame(self, n_steps: int, reinit: bool, image, stream) -> "Frame":
+        """Capture re-init (optional) + n_steps + resolve into `image` (CUDA
+        float32 (3, W*H)) as a HIP graph on `stream` (a torch.cuda.Stream)."""
+        h = C.c_void_p()
+        _check(lib().dr_frame_capture(self.h, n_steps, 1 if reinit else 0, _dev_ptr(image),
+                                      C.c_void_p(stream.cuda_stream), C.byref(h)))
+        return Frame(h, self, image)
+
     def write_state(self, x=None, score=None, killed=None, accum=None, step=None, tour_count=0, k0=0.0, stream=None):
         s = dr_state()
         keep = []
@@ -374,3 +392,24 @@ class Chains:
         s.tour_count = tour_count
         s.k0 = k0
         _check(lib().dr_chains_write_state(self.h, C.byref(s), _stream(stream)))
+
+
+class Frame:
+    """A captured frame (dr_frame_capture / dr_frame_launch / dr_frame_destroy)."""
+
+    def __init__(self, h, chains, image):
+        self.h, self.chains, self.image = h, chains, image
+
+    def launch(self, stream):
+        _check(lib().dr_frame_launch(self.h, C.c_void_p(stream.cuda_stream)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().dr_frame_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

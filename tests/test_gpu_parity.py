@@ -423,3 +423,39 @@ def test_paired_lanes_match_single_lane(scenes, which, L, N):
     assert np.array_equal(a["score"][:, a["killed"] == 0], b["score"][:, b["killed"] == 0])
     assert a["tour_count"] == b["tour_count"]
     assert np.allclose(a["accum"], b["accum"], rtol=1e-5, atol=1e-6)
+
+
+def test_captured_frames_replay_like_eager(scenes):
+    """A captured frame (re-init + n steps + resolve) replayed several times,
+    with a camera change between replays and eager work in between, gives the
+    chains and image the same calls give eagerly."""
+    sc = scenes["spheres_small"]
+    L, N, n = 8, 4096, 5
+    say(f"[frame graph] L={L} N={N} steps/frame={n}")
+    S1, S2 = dr.Scene(sc), dr.Scene(sc)
+    a = dr.Chains(S1, N, L, 41, frame=3)
+    b = dr.Chains(S2, N, L, 41, frame=3)
+    stream = torch.cuda.Stream()
+    img_a = torch.zeros((3, S1.W * S1.H), device="cuda")
+    with torch.cuda.stream(stream):
+        frame = a.capture_frame(n, True, img_a, stream)
+    for k in range(3):
+        cam = sc["camera"].copy()
+        cam[0] += 0.03 * k
+        S1.set_camera(cam)
+        S2.set_camera(cam)
+        frame.launch(stream)
+        stream.synchronize()
+        b.reinit(4 + k)
+        b.step(n)
+        img_b = b.resolve()
+        torch.cuda.synchronize()
+        sa, sb = a.read_state(), b.read_state()
+        assert sa["step"] == sb["step"] == ((4 + k) << 32) + 1 + n
+        assert np.array_equal(sa["x"], sb["x"]) and np.array_equal(sa["killed"], sb["killed"])
+        assert sa["tour_count"] == sb["tour_count"]
+        ia, ib = img_a.cpu().numpy(), img_b.cpu().numpy()
+        assert np.allclose(ia, ib, rtol=1e-4, atol=1e-6), np.abs(ia - ib).max()
+        a.step(1)   # eager work between replays on the captured chain set
+        b.step(1)
+    frame.close()
