@@ -459,3 +459,60 @@ def test_captured_frames_replay_like_eager(scenes):
         a.step(1)   # eager work between replays on the captured chain set
         b.step(1)
     frame.close()
+
+
+@pytest.mark.parametrize("name", ["instances", "spheres_1080p_L16", "interior"])
+def test_large_configs_sampled_parity(orc, name):
+    """The larger configurations at their real shapes: ~1M triangles with
+    path length 12 and 1M chains; path length 16 with per-chain diagonal
+    Sigma at 1920x1080 and 2M chains; ~2M triangles at 1920x1080 with 4M
+    chains.  One fused step on every chain, 512 sampled chains against the
+    oracle."""
+    factory, L, N = inputs.CONFIGS[name]
+    sc = factory()
+    d = 4 * (L - 1)
+    sigma = inputs.per_chain_sigma(d, N, seed=4) if name == "spheres_1080p_L16" else None
+    sample = np.sort(np.random.default_rng(1).choice(N, 512, replace=False))
+    say(f"[large] {name}: {sc['indices'].shape[0]} triangles, {sc['width']}x{sc['height']}, L={L}, N={N}")
+    st, gs, os_, idx, step0 = _onestep(orc, sc, L, N, dr.DR_MODE_FUSED, seed=91, k0=100.0, sigma=sigma,
+                                      sample=sample)
+    _compare_step(orc, sc, L, st, gs, os_, idx, 91, step0, 100.0)
+
+
+def test_adjoint_long_paths_with_segment_recompute(orc):
+    """Path length 16 (d = 60): the adjoint keeps one checkpoint per 8-vertex
+    segment and recomputes each segment in the reverse sweep.  Checked against
+    the oracle's forward-mode score and central differences (h = 1e-3) on the
+    device."""
+    sc = inputs.procedural_interior(n_inst=40, subdiv=3, width=320, height=180)
+    L, n, h = 16, 1024, 1e-3
+    d = 4 * (L - 1)
+    say(f"[adjoint L16] {sc['indices'].shape[0]} triangles, n={n}")
+    u, (f, logp, g), (fo, po, go), match = _eval_both(orc, sc, L, n, seed=12)
+    say(f"  path-signature match {match.mean():.5f}")
+    assert match.mean() > 0.99
+    live = match & (po > 1e-3 * po.mean())
+    err = np.linalg.norm(g[live] - go[live], axis=1) / np.maximum(np.linalg.norm(go[live], axis=1), 1e-6)
+    say(f"  score rel err median {np.median(err):.2e} p99 {np.quantile(err, 0.99):.2e}")
+    assert np.median(err) < 1e-5 and np.quantile(err, 0.99) < 1e-3
+    S = dr.Scene(sc)
+    ut = torch.from_numpy(u).cuda()
+    _, lp0, _, r0 = S.eval_logp_grad(L, ut, grad=False, rec=True)
+    # long paths: some samples reach the second 8-vertex segment
+    nverts = (r0 != -1).sum(1).cpu().numpy()
+    say(f"  samples with more than 8 vertices: {(nverts > 8).sum()}")
+    assert (nverts > 8).sum() > 20
+    checked = bad = 0
+    for i in range(d):
+        e = torch.zeros_like(ut)
+        e[:, i] = h
+        _, lpp, _, rp = S.eval_logp_grad(L, (ut + e).clamp(0, 1 - 2 ** -24), grad=False, rec=True)
+        _, lpm, _, rm = S.eval_logp_grad(L, (ut - e).clamp(0, 1 - 2 ** -24), grad=False, rec=True)
+        same = (rp == r0).all(1).cpu().numpy() & (rm == r0).all(1).cpu().numpy() & live
+        same &= (u[:, i] > h) & (u[:, i] < 1 - h)
+        fd = (lpp - lpm).cpu().numpy() / (2 * h)
+        tol = 0.05 * np.abs(go[:, i]) + 0.05 * np.abs(fd) + 2e-4 / h * np.maximum(1.0, np.abs(lp0.cpu().numpy()))
+        checked += same.sum()
+        bad += (same & (np.abs(fd - g[:, i]) > tol)).sum()
+    say(f"  FD checked {checked}, outside tolerance {bad}")
+    assert checked > 5000 and bad <= 0.01 * checked
