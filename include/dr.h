@@ -109,7 +109,9 @@ dr_status dr_bvh_build(const float* vertices, uint32_t n_vertices, const uint32_
 /* Validate and deep-copy a scene to device `device` (the caller's arrays may be
  * freed on return).  Converts the host BVH to the device node layout.
  * Errors: DR_ERR_INVALID_ARG (index/material/node out of range, no lights,
- * more than 2^24-1 triangles or 127 lights, BVH deeper than 40),
+ * more than 2^24-1 triangles or 127 lights, BVH deeper than 64),
+ * DR_ERR_UNSUPPORTED (a tree whose traversal could need more than 64 stack
+ * entries),
  * DR_ERR_OUT_OF_MEMORY, DR_ERR_DEVICE.  Synchronous. */
 dr_status dr_scene_create(const dr_scene_desc* desc, int device, dr_scene** out);
 

@@ -10,7 +10,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#define DR_STACK 40       // traversal stack entries per lane (tree depth limit)
+#define DR_STACK 64       // traversal stack entries per lane (checked against the tree on the host)
 #define DR_NO_VERTEX 0xFFFFFFFFu
 #define DR_PI 3.14159265358979323846f
 
@@ -65,13 +65,14 @@ __device__ __forceinline__ float u24(uint32_t w) { return (float)(w >> 8) * (1.0
 // ---------------------------------------------------------------------------
 // Scene layout in HBM
 // ---------------------------------------------------------------------------
-// BVH node holding the boxes of its two children (64 B, one fetch per visit):
-//   box0 lo = a.xyz, hi = (a.w, b.x, b.y);  box1 lo = (b.z, b.w, c.x), hi = c.yzw
-//   d = (child0, child1, count0, count1): count > 0 leaf of `count` triangles
-//   starting at slot child; count == 0 inner node index child; count < 0 empty.
-struct alignas(64) DevNode {
-    float4 a, b, c;
-    int4 d;
+// 4-wide BVH node (128 B, two cache lines fetched together per visit): the
+// boxes of its four children in SOA form (lo/hi per axis for children 0..3),
+// then per child: index and count.  count > 0: leaf of `count` triangles
+// starting at slot `child`; count == 0: inner node index `child`; count < 0:
+// empty slot.
+struct alignas(128) DevNode {
+    float4 lox, loy, loz, hix, hiy, hiz;
+    int4 child, count;
 };
 // Triangle in leaf order (48 B): v0 | prim id bits, e1 = v1 - v0 | material
 // bits, e2 = v2 - v0 | 0.
@@ -147,12 +148,19 @@ __device__ __forceinline__ bool tri_test(const DevTri& T, V3 o, V3 d, float tmin
 __device__ __forceinline__ DevNode load_node(const DevNode* nodes, int i) {
     const float4* p = reinterpret_cast<const float4*>(nodes + i);
     DevNode n;
-    n.a = p[0];
-    n.b = p[1];
-    n.c = p[2];
-    n.d = reinterpret_cast<const int4*>(p)[3];
+    n.lox = p[0];
+    n.loy = p[1];
+    n.loz = p[2];
+    n.hix = p[3];
+    n.hiy = p[4];
+    n.hiz = p[5];
+    n.child = reinterpret_cast<const int4*>(p)[6];
+    n.count = reinterpret_cast<const int4*>(p)[7];
     return n;
 }
+
+__device__ __forceinline__ float f4(const float4& v, int q) { return q == 0 ? v.x : (q == 1 ? v.y : (q == 2 ? v.z : v.w)); }
+__device__ __forceinline__ int i4(const int4& v, int q) { return q == 0 ? v.x : (q == 1 ? v.y : (q == 2 ? v.z : v.w)); }
 
 // One ray query over (tmin, tmax): the closest hit (ties in t go to the lower
 // input triangle index) or, with anyhit, the first hit found.  Returns the
@@ -174,34 +182,37 @@ __device__ int trace(const DevScene& S, V3 o, V3 d, float tmax, bool anyhit, flo
     while (true) {
         const DevNode n = load_node(S.nodes, node);
         ctr.nodes++;
-        float tn0, tn1;
-        bool h0 = n.d.z >= 0 && slab(n.a.x, n.a.y, n.a.z, n.a.w, n.b.x, n.b.y, o, inv, S.tmin, bt, tn0);
-        bool h1 = n.d.w >= 0 && slab(n.b.z, n.b.w, n.c.x, n.c.y, n.c.z, n.c.w, o, inv, S.tmin, bt, tn1);
+        float tn[4];
+        bool hit[4];
 #pragma unroll
-        for (int side = 0; side < 2; ++side) {
-            const bool h = side ? h1 : h0;
-            const int cnt = side ? n.d.w : n.d.z;
-            const int first = side ? n.d.y : n.d.x;
-            if (h && cnt > 0) {
+        for (int q = 0; q < 4; ++q)
+            hit[q] = i4(n.count, q) >= 0 && slab(f4(n.lox, q), f4(n.loy, q), f4(n.loz, q), f4(n.hix, q), f4(n.hiy, q),
+                                                  f4(n.hiz, q), o, inv, S.tmin, bt, tn[q]);
+        // leaves are tested on the spot, four triangles' loads in flight at once
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int cnt = i4(n.count, q);
+            const int first = i4(n.child, q);
+            if (hit[q] && cnt > 0) {
                 for (int k0 = first; k0 < first + cnt; k0 += 4) {
                     DevTri T[4];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        if (k0 + q < first + cnt) T[q] = S.tris[k0 + q];
+                    for (int e = 0; e < 4; ++e)
+                        if (k0 + e < first + cnt) T[e] = S.tris[k0 + e];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        if (k0 + q >= first + cnt) break;
+                    for (int e = 0; e < 4; ++e) {
+                        if (k0 + e >= first + cnt) break;
                         ctr.tris++;
                         float t;
-                        if (tri_test(T[q], o, d, S.tmin, t) && t <= bt) {
-                            const uint32_t prim = __float_as_uint(T[q].v0.w);
+                        if (tri_test(T[e], o, d, S.tmin, t) && t <= bt) {
+                            const uint32_t prim = __float_as_uint(T[e].v0.w);
                             if (anyhit && t < tmax) {
                                 t_hit = t;
-                                return k0 + q;
+                                return k0 + e;
                             }
                             if (t < bt || (t == bt && prim < best_prim)) {
                                 bt = t;
-                                best = k0 + q;
+                                best = k0 + e;
                                 best_prim = prim;
                             }
                         }
@@ -209,19 +220,35 @@ __device__ int trace(const DevScene& S, V3 o, V3 d, float tmax, bool anyhit, flo
                 }
             }
         }
-        h0 = h0 && n.d.z == 0;
-        h1 = h1 && n.d.w == 0;
-        if (h0 && h1) {
-            const bool first0 = tn0 <= tn1;
-            if (sp < DR_STACK) stk[(sp++) * stride] = (uint32_t)(first0 ? n.d.y : n.d.x);
-            node = first0 ? n.d.x : n.d.y;
-        } else if (h0) {
-            node = n.d.x;
-        } else if (h1) {
-            node = n.d.y;
-        } else {
+        // inner children hit: visit the nearest next, push the others
+        // far-first (a fixed sorting network keeps every index static)
+        float kt[4];
+        int kc[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const bool inner = hit[q] && i4(n.count, q) == 0;
+            kt[q] = inner ? tn[q] : INFINITY;
+            kc[q] = inner ? i4(n.child, q) : -1;
+        }
+#define DR_CSWAP(i, j)                                  \
+    if (kt[j] < kt[i]) {                                \
+        const float tt_ = kt[i]; kt[i] = kt[j]; kt[j] = tt_; \
+        const int cc_ = kc[i]; kc[i] = kc[j]; kc[j] = cc_;   \
+    }
+        DR_CSWAP(0, 1)
+        DR_CSWAP(2, 3)
+        DR_CSWAP(0, 2)
+        DR_CSWAP(1, 3)
+        DR_CSWAP(1, 2)
+#undef DR_CSWAP
+        if (kc[0] < 0) {
             if (sp == 0) break;
             node = (int)stk[(--sp) * stride];
+        } else {
+            if (kc[3] >= 0 && sp < DR_STACK) stk[(sp++) * stride] = (uint32_t)kc[3];
+            if (kc[2] >= 0 && sp < DR_STACK) stk[(sp++) * stride] = (uint32_t)kc[2];
+            if (kc[1] >= 0 && sp < DR_STACK) stk[(sp++) * stride] = (uint32_t)kc[1];
+            node = kc[0];
         }
     }
     t_hit = bt;

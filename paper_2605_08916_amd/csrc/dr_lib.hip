@@ -670,8 +670,7 @@ dr_status dr_scene_create(const dr_scene_desc* desc, int device, dr_scene** out)
         if (s != DR_OK) return s;
         nodes.resize(nn);
     }
-    // Validate the tree, recompute exact f32 bounds bottom-up, and convert to
-    // the device layout (one DevNode per inner node, leaves embedded).
+    // Validate the tree and recompute exact f32 bounds bottom-up.
     const size_t NN = nodes.size();
     std::vector<int> depth(NN, -1), parent(NN, -1);
     std::vector<int> stack = {0};
@@ -693,7 +692,7 @@ dr_status dr_scene_create(const dr_scene_desc* desc, int device, dr_scene** out)
                 if (ch <= 0 || (size_t)ch >= NN || depth[ch] != -1)
                     return fail(DR_ERR_INVALID_ARG, "dr_scene_create: bad BVH child index");
                 depth[ch] = depth[i] + 1;
-                if (depth[ch] > DR_STACK) return fail(DR_ERR_INVALID_ARG, "dr_scene_create: BVH deeper than 40");
+                if (depth[ch] > 64) return fail(DR_ERR_INVALID_ARG, "dr_scene_create: BVH deeper than 64");
                 parent[ch] = i;
                 stack.push_back(ch);
             }
@@ -722,41 +721,100 @@ dr_status dr_scene_create(const dr_scene_desc* desc, int device, dr_scene** out)
             }
         }
     }
-    std::vector<DevNode> dn;
-    std::vector<int> dev_index(NN, -1);
-    auto child_slot = [&](int ch, float* box, int& idx, int& cnt) {
-        for (int a = 0; a < 3; ++a) { box[a] = blo[3 * ch + a]; box[3 + a] = bhi[3 * ch + a]; }
-        const dr_bvh_node& n = nodes[ch];
-        if (n.a < 0) { idx = ~n.a; cnt = n.b; }
-        else { idx = dev_index[ch]; cnt = 0; }
+    // Collapse the binary tree into 4-wide nodes: a node takes its two
+    // children and keeps replacing the inner child of largest surface area by
+    // that child's two children until it has four.  Device nodes are created
+    // in depth-first order; leaves stay embedded in their parent.
+    auto area = [&](int i) {
+        const float dx = bhi[3 * i] - blo[3 * i], dy = bhi[3 * i + 1] - blo[3 * i + 1], dz = bhi[3 * i + 2] - blo[3 * i + 2];
+        return dx * dy + dy * dz + dz * dx;
     };
-    // assign device indices to inner nodes in topo (pre-)order
-    for (int i : topo)
-        if (nodes[i].a >= 0) { dev_index[i] = (int)dn.size(); dn.emplace_back(); }
-    if (nodes[0].a < 0) {  // whole scene in one leaf: a root with one leaf child
-        DevNode r{};
-        float box[6];
-        int idx, cnt;
-        child_slot(0, box, idx, cnt);
-        r.a = make_float4(box[0], box[1], box[2], box[3]);
-        r.b = make_float4(box[4], box[5], 1.f, 1.f);
-        r.c = make_float4(1.f, 0.f, 0.f, 0.f);
-        r.d = make_int4(idx, 0, cnt, -1);
-        dn.push_back(r);
-    } else {
-        for (int i : topo) {
-            const dr_bvh_node& n = nodes[i];
-            if (n.a < 0) continue;
-            float b0[6], b1[6];
-            int i0, c0, i1, c1;
-            child_slot(n.a, b0, i0, c0);
-            child_slot(n.b, b1, i1, c1);
-            DevNode& r = dn[dev_index[i]];
-            r.a = make_float4(b0[0], b0[1], b0[2], b0[3]);
-            r.b = make_float4(b0[4], b0[5], b1[0], b1[1]);
-            r.c = make_float4(b1[2], b1[3], b1[4], b1[5]);
-            r.d = make_int4(i0, i1, c0, c1);
+    auto gather = [&](int i, int out[4]) {
+        int k = 0;
+        out[k++] = nodes[i].a;
+        out[k++] = nodes[i].b;
+        while (k < 4) {
+            int best = -1;
+            float ba = -1.f;
+            for (int q = 0; q < k; ++q)
+                if (nodes[out[q]].a >= 0 && area(out[q]) > ba) { ba = area(out[q]); best = q; }
+            if (best < 0) break;
+            const int c = out[best];
+            out[best] = nodes[c].a;
+            out[k++] = nodes[c].b;
         }
+        return k;
+    };
+    std::vector<DevNode> dn;
+    std::vector<int> need;  // worst-case traversal stack entries below each device node
+    {
+        struct Item { int bin; int dev; };
+        std::vector<Item> work;
+        std::vector<std::vector<int>> kids;  // device children (inner) per device node
+        auto fill_leafroot = [&]() {
+            DevNode r{};
+            r.lox = make_float4(blo[0], 1.f, 1.f, 1.f); r.loy = make_float4(blo[1], 1.f, 1.f, 1.f);
+            r.loz = make_float4(blo[2], 1.f, 1.f, 1.f); r.hix = make_float4(bhi[0], 0.f, 0.f, 0.f);
+            r.hiy = make_float4(bhi[1], 0.f, 0.f, 0.f); r.hiz = make_float4(bhi[2], 0.f, 0.f, 0.f);
+            r.child = make_int4(~nodes[0].a, 0, 0, 0);
+            r.count = make_int4(nodes[0].b, -1, -1, -1);
+            dn.push_back(r);
+            kids.emplace_back();
+        };
+        if (nodes[0].a < 0) {
+            fill_leafroot();
+        } else {
+            dn.emplace_back();
+            kids.emplace_back();
+            work.push_back({0, 0});
+            while (!work.empty()) {
+                const Item it = work.back();
+                work.pop_back();
+                int ch[4];
+                const int k = gather(it.bin, ch);
+                float lo[3][4], hi[3][4];
+                int cidx[4], ccnt[4];
+                for (int q = 0; q < 4; ++q) {
+                    if (q >= k) {
+                        for (int a2 = 0; a2 < 3; ++a2) { lo[a2][q] = 1.f; hi[a2][q] = 0.f; }
+                        cidx[q] = 0;
+                        ccnt[q] = -1;
+                        continue;
+                    }
+                    const int c = ch[q];
+                    for (int a2 = 0; a2 < 3; ++a2) { lo[a2][q] = blo[3 * c + a2]; hi[a2][q] = bhi[3 * c + a2]; }
+                    if (nodes[c].a < 0) {
+                        cidx[q] = ~nodes[c].a;
+                        ccnt[q] = nodes[c].b;
+                    } else {
+                        cidx[q] = (int)dn.size();
+                        ccnt[q] = 0;
+                        dn.emplace_back();
+                        kids.emplace_back();
+                        kids[it.dev].push_back(cidx[q]);
+                        work.push_back({c, cidx[q]});
+                    }
+                }
+                DevNode& r = dn[it.dev];
+                r.lox = make_float4(lo[0][0], lo[0][1], lo[0][2], lo[0][3]);
+                r.loy = make_float4(lo[1][0], lo[1][1], lo[1][2], lo[1][3]);
+                r.loz = make_float4(lo[2][0], lo[2][1], lo[2][2], lo[2][3]);
+                r.hix = make_float4(hi[0][0], hi[0][1], hi[0][2], hi[0][3]);
+                r.hiy = make_float4(hi[1][0], hi[1][1], hi[1][2], hi[1][3]);
+                r.hiz = make_float4(hi[2][0], hi[2][1], hi[2][2], hi[2][3]);
+                r.child = make_int4(cidx[0], cidx[1], cidx[2], cidx[3]);
+                r.count = make_int4(ccnt[0], ccnt[1], ccnt[2], ccnt[3]);
+            }
+        }
+        // a visit pushes (inner children hit - 1) entries: the stack never
+        // holds more than the largest sum of that along a root-to-leaf path
+        need.assign(dn.size(), 0);
+        for (int i = (int)dn.size() - 1; i >= 0; --i) {  // children have larger indices
+            int m = 0;
+            for (int c : kids[i]) m = std::max(m, need[c]);
+            need[i] = (kids[i].empty() ? 0 : (int)kids[i].size() - 1) + m;
+        }
+        if (need[0] > DR_STACK) return fail(DR_ERR_UNSUPPORTED, "dr_scene_create: BVH needs a deeper traversal stack than 64");
     }
     // triangles in leaf order
     std::vector<DevTri> tris(T);
