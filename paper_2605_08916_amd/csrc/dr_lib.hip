@@ -473,9 +473,12 @@ void camera_basis(const dr_camera& c, float4 out[4]) {
 }
 
 int g_num_cu(int dev) {
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 256;
-    return prop.multiProcessorCount;
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) {
+        (void)hipGetLastError();
+        return 256;
+    }
+    return n;
 }
 
 }  // namespace
@@ -551,6 +554,7 @@ static void launch_eval(dim3 g, dim3 b, hipStream_t st, const DevScene& S, const
 // Enqueue the initialise pass (Alg. 4.1).  from_device: take the frame index
 // from the device frame counter plus one (used inside captured frames).
 static void enqueue_init(dr_chains* c, uint32_t frame, int from_device, hipStream_t st) {
+    (void)hipGetLastError();  // drop a stale error left by an earlier, unrelated call
     const int N = c->kp.N;
     const int blk = 256;
     const dim3 g((N + blk - 1) / blk), b(blk);
@@ -570,6 +574,7 @@ static void enqueue_init(dr_chains* c, uint32_t frame, int from_device, hipStrea
 
 // Enqueue n_steps evolve steps (Alg. 4.2) in the chain set's form.
 static void enqueue_steps(dr_chains* c, uint32_t n_steps, hipStream_t st) {
+    (void)hipGetLastError();  // drop a stale error left by an earlier, unrelated call
     KParams P = c->kp;
     P.record = c->record;
     P.count = c->count;
@@ -597,6 +602,7 @@ static void enqueue_steps(dr_chains* c, uint32_t n_steps, hipStream_t st) {
 }
 
 static void enqueue_resolve(dr_chains* c, float* image_dev, hipStream_t st) {
+    (void)hipGetLastError();  // drop a stale error left by an earlier, unrelated call
     const size_t npx = (size_t)c->scene->ds.W * c->scene->ds.H;
     hipLaunchKernelGGL(k_resolve, dim3(std::min<size_t>(4096, (3 * npx + 255) / 256)), dim3(256), 0, st, c->kb.accum,
                        image_dev, npx, c->kb.k0d, c->kb.ctr, (double)c->P.dt);
@@ -604,7 +610,8 @@ static void enqueue_resolve(dr_chains* c, float* image_dev, hipStream_t st) {
 
 static dr_status run_init(dr_chains* c, uint32_t frame, hipStream_t st) {
     enqueue_init(c, frame, 0, st);
-    HIP_TRY(hipGetLastError());
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(DR_ERR_DEVICE, std::string("initialise pass launch: ") + hipGetErrorString(e));
     c->cam_version = c->scene->cam_version;
     return DR_OK;
 }
@@ -1194,6 +1201,7 @@ dr_status dr_eval_logp_grad(dr_scene* s, uint32_t L, const float* u_dev, uint32_
     if (!(eps > 0)) return fail(DR_ERR_INVALID_ARG, "dr_eval_logp_grad: eps must be > 0");
     if (n == 0) { g_err.clear(); return DR_OK; }
     HIP_TRY(hipSetDevice(s->device));
+    (void)hipGetLastError();  // drop a stale error left by an earlier, unrelated call
     hipStream_t st = (hipStream_t)hip_stream;
     void* rs = nullptr;
     HIP_TRY(hipMallocAsync(&rs, sizeof(uint32_t) * (L - 1) * (size_t)n, st));
@@ -1211,6 +1219,7 @@ dr_status dr_pt_render(dr_scene* s, uint32_t L, uint64_t seed, uint32_t spp, flo
     if (!s || !img_dev) return fail(DR_ERR_INVALID_ARG, "dr_pt_render: null argument");
     if (L < 2 || L > 16 || spp == 0) return fail(DR_ERR_INVALID_ARG, "dr_pt_render: L must be 2..16 and spp >= 1");
     HIP_TRY(hipSetDevice(s->device));
+    (void)hipGetLastError();  // drop a stale error left by an earlier, unrelated call
     const int npx = s->ds.W * s->ds.H;
     const int blk = 128;
     hipLaunchKernelGGL(k_pt, dim3((npx + blk - 1) / blk), dim3(blk), stack_bytes(blk), (hipStream_t)hip_stream, s->ds,
