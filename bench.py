@@ -49,7 +49,100 @@ def parse():
                     help="only run warmup + steps of the fused form (for hardware-counter runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates the FETCH_SIZE/WRITE_SIZE counters)")
+    ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="no GPU: write the HBM traffic summary of the fused kernel from four rocprofv3 --pmc "
+                         "output folders (FETCH_SIZE and WRITE_SIZE of --profile-only, then of --copy-probe)")
     return ap.parse_args()
+
+
+# ---- HBM traffic of the fused kernel, from hardware counters.  The summary
+# records a digest of the kernel sources; a bench run whose sources differ
+# reports traffic as null.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_fused_spheres53k_traffic.txt")
+KERNEL_SOURCES = ["paper_2605_08916_amd/csrc/dr_lib.hip", "paper_2605_08916_amd/csrc/dr_device.h",
+                  "paper_2605_08916_amd/csrc/dr_adjoint.h", "paper_2605_08916_amd/csrc/dr_chain.h",
+                  "paper_2605_08916_amd/build.py"]
+
+
+def sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(rel.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def _pmc_rows(folder, counter):
+    import csv
+    import glob
+    rows = []
+    for path in glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True):
+        with open(path, newline="") as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] == counter:
+                    rows.append((r["Kernel_Name"], float(r["Counter_Value"])))
+    if not rows:
+        raise SystemExit(f"no {counter} rows under {folder}")
+    return rows
+
+
+def write_traffic_summary(dirs, chains, per_launch):
+    fetch_dir, write_dir, cfetch_dir, cwrite_dir = dirs
+
+    def fused_mean(folder, counter):
+        v = [x for k, x in _pmc_rows(folder, counter) if "k_step_fused" in k]
+        if not v:
+            raise SystemExit(f"no k_step_fused dispatch with {counter} under {folder}")
+        return sum(v) / len(v), len(v)
+
+    def copy_kib(folder, counter):
+        return max(x for k, x in _pmc_rows(folder, counter) if "copyBuffer" in k)
+
+    fk, nf = fused_mean(fetch_dir, "FETCH_SIZE")
+    wk, nw = fused_mean(write_dir, "WRITE_SIZE")
+    copy_bytes = 4 * (1 << 28)
+    fs = copy_bytes / (copy_kib(cfetch_dir, "FETCH_SIZE") * 1024.0)
+    ws = copy_bytes / (copy_kib(cwrite_dir, "WRITE_SIZE") * 1024.0)
+    rd, wr = fk * 1024.0 * fs, wk * 1024.0 * ws
+    cmd = f"python3 bench.py --profile-only --steps 8 --warmup 2 --chains {chains} --steps-per-frame {per_launch}"
+    lines = [
+        "# HBM traffic of k_step_fused<8, true>: procedural spheres 53k triangles, 512x512, L = 8",
+        f"# counters: rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) -d <out> -- {cmd}",
+        "# calibration: rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) -d <out> -- python3 bench.py --copy-probe",
+        f"# written by: python3 bench.py --traffic-summary <fetch> <write> <copy_fetch> <copy_write>",
+        f"sources_digest: {sources_digest()}",
+        f"chains: {chains}",
+        f"steps_per_launch: {per_launch}",
+        f"dispatches_fetch: {nf}",
+        f"dispatches_write: {nw}",
+        f"fetch_kib_per_dispatch: {fk:.1f}",
+        f"write_kib_per_dispatch: {wk:.1f}",
+        f"copy_fetch_scale: {fs:.4f}",
+        f"copy_write_scale: {ws:.4f}",
+        f"hbm_read_bytes_per_launch: {rd:.0f}",
+        f"hbm_write_bytes_per_launch: {wr:.0f}",
+        f"hbm_bytes_per_launch: {rd + wr:.0f}",
+        f"hbm_bytes_per_chain_step: {(rd + wr) / (chains * per_launch):.1f}",
+    ]
+    with open(TRAFFIC_FILE, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def read_traffic(chains, per_launch):
+    """HBM bytes per launch from the committed counter summary, or None when
+    the summary is missing, was taken on another launch shape, or the kernel
+    sources changed since."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            kv = dict(l.split(": ", 1) for l in f.read().splitlines() if l and not l.startswith("#"))
+    except OSError:
+        return None
+    if (kv.get("sources_digest") != sources_digest() or int(kv.get("chains", -1)) != chains
+            or int(kv.get("steps_per_launch", -1)) != per_launch):
+        return None
+    return float(kv["hbm_bytes_per_launch"])
 
 
 def lum(img):
@@ -117,6 +210,9 @@ def cpu_baseline(sc, L, seconds, k0):
 
 def main():
     a = parse()
+    if a.traffic_summary:
+        write_traffic_summary(a.traffic_summary, a.chains, max(1, a.steps_per_frame))
+        return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the chain step has no multi-GPU path in this "
               "build", file=sys.stderr)
@@ -138,10 +234,11 @@ def main():
         sc = inputs.procedural_spheres(seed=1)
         scene = dr.Scene(sc)
         ch = dr.Chains(scene, a.chains, 8, 2024, mode=dr.DR_MODE_FUSED)
+        F = max(1, a.steps_per_frame)
         for _ in range(a.warmup + a.steps):
-            ch.step(1)
+            ch.step(F)
         torch.cuda.synchronize()
-        print(json.dumps({"profile_only_steps": a.warmup + a.steps}))
+        print(json.dumps({"profile_only_launches": a.warmup + a.steps, "steps_per_launch": F}))
         return
     sc = inputs.procedural_spheres(seed=1)
     L, N = 8, a.chains
@@ -189,6 +286,7 @@ def main():
     b_splat = 24
     bytes_step = b_state + b_trav + b_shade + b_splat
     achieved = bytes_step * N * F / (ms_launch * 1e-3) / 1e9
+    traffic = read_traffic(N, F)
 
     res = {
         "metric": "chain-steps/s (f+∇log f) and MRSE at 33 ms/frame, fused vs plain",
@@ -212,7 +310,8 @@ def main():
         "per_chain_step": {"rays": rays, "node_visits": nodes, "tri_tests": tris, "adjoint_fraction": adj,
                            "alg_bytes": bytes_step},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch", "alg_bytes_per_launch": bytes_step * N * F,
                      "kernel": f"k_step_fused<{L},{'true' if launch_cfg['lanes_per_chain'] == 2 else 'false'}>",
                      "launch_ms": ms_launch, "steps_per_launch": F},
     }

@@ -121,6 +121,19 @@ dr_status dr_scene_create(const dr_scene_desc* desc, int device, dr_scene** out)
  * in device memory.  The image size cannot change. */
 dr_status dr_scene_set_camera(dr_scene* s, const dr_camera* cam);
 
+/* Device layout of a created scene: triangles, 4-wide BVH nodes (128 B
+ * each), and the traversal stack a lane needs (the exact worst case over the
+ * tree's root-to-leaf paths, at most 64 entries of 4 bytes).  Kernels that
+ * trace rays reserve that many LDS bytes per lane, which bounds how many
+ * wavefronts a compute unit can hold. */
+typedef struct {
+    uint32_t n_triangles;
+    uint32_t n_nodes;
+    uint32_t stack_entries;
+    uint32_t stack_bytes_per_lane;
+} dr_scene_stats;
+dr_status dr_scene_get_stats(const dr_scene* s, dr_scene_stats* out);
+
 void dr_scene_destroy(dr_scene* s);
 
 /* ------------------------------------------------------------------------
@@ -209,12 +222,22 @@ dr_status dr_stats(dr_chains* c, dr_counters* out, void* hip_stream);
 /* Launch configuration of the fused persistent kernel: threads per block
  * (64, 128, 192 or 256), resident blocks per compute unit of the persistent
  * grid, the number of consecutive chains a lane (or lane pair) takes per pop
- * of the device work queue (1..64), and lanes per chain (1, or 2: the two
- * lanes trace a path's continuation and shadow rays concurrently).  Zeros keep
- * the current value.  Defaults: 256 threads, 3 blocks per compute unit, 1
- * chain per pop, and 2 lanes per chain when n_chains is below two wavefronts
- * per SIMD (n_cu * 512), else 1. */
-typedef struct { uint32_t block; uint32_t blocks_per_cu; uint32_t grab; uint32_t lanes_per_chain; } dr_launch_cfg;
+ * of the device work queue (1..64), lanes per chain (1, or 2: the two lanes
+ * trace a path's continuation and shadow rays concurrently), and
+ * sort_by_length (1: before each launch, order the chains by the number of
+ * path vertices of their last step so the chains of a wavefront finish
+ * together; 2: off).  Zeros keep the current value.  Defaults: 256 threads,
+ * 3 blocks per compute unit, 1 chain per pop, 2 lanes per chain when n_chains
+ * is below two wavefronts per SIMD (n_cu * 512) else 1, sorting off (it pays
+ * only when chains outnumber the resident lanes several times over).  The
+ * order in which chains are processed never changes their results. */
+typedef struct {
+    uint32_t block;
+    uint32_t blocks_per_cu;
+    uint32_t grab;
+    uint32_t lanes_per_chain;
+    uint32_t sort_by_length;
+} dr_launch_cfg;
 dr_status dr_chains_set_launch(dr_chains* c, const dr_launch_cfg* cfg);
 dr_status dr_chains_get_launch(dr_chains* c, dr_launch_cfg* cfg);
 

@@ -1,8 +1,10 @@
 """Launch-configuration autotuner for the fused persistent chain-step kernel.
 
 It sweeps the threads per block, the resident blocks per compute unit of the
-persistent grid and the number of chains a lane takes per queue pop, times
-`dr_step(1)` for each candidate with HIP events on the launch stream, and
+persistent grid, the number of chains a lane takes per queue pop, lanes per
+chain and the path-length ordering of chains, times `dr_step(n)` (n steps per
+launch, as the caller will issue them) for each candidate with HIP events on
+the launch stream, and
 caches the fastest configuration in a JSON file keyed by device name, path
 length, chain count and triangle count.  The chain state is saved before and
 restored after the sweep, so tuning does not advance the chains.
@@ -20,6 +22,7 @@ BLOCKS = (64, 128, 256)
 BLOCKS_PER_CU = (1, 2, 3, 4, 6, 8)
 GRABS = (1,)
 LANES = (1, 2)
+SORTS = (2, 1)  # path-length ordering off, on
 
 
 def _key(ch: "dr.Chains") -> str:
@@ -36,22 +39,23 @@ def _load() -> dict:
         return {}
 
 
-def _time(ch: "dr.Chains", reps: int) -> float:
+def _time(ch: "dr.Chains", reps: int, per_launch: int) -> float:
     import torch
     s = torch.cuda.current_stream()
-    ch.step(1)
+    ch.step(per_launch)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(s)
     for _ in range(reps):
-        ch.step(1)
+        ch.step(per_launch)
     e1.record(s)
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / reps
+    return e0.elapsed_time(e1) / (reps * per_launch)
 
 
-def tune(ch: "dr.Chains", reps: int = 5, use_cache: bool = True, verbose: bool = False) -> dict:
-    """Pick and apply the fastest launch configuration for this chain set."""
-    key = _key(ch)
+def tune(ch: "dr.Chains", reps: int = 3, use_cache: bool = True, verbose: bool = False, per_launch: int = 8) -> dict:
+    """Pick and apply the fastest launch configuration for this chain set
+    (time per chain-step with `per_launch` steps per launch)."""
+    key = _key(ch) + f"|F{per_launch}"
     cache = _load() if use_cache else {}
     if key in cache:
         cfg = cache[key]["cfg"]
@@ -63,12 +67,14 @@ def tune(ch: "dr.Chains", reps: int = 5, use_cache: bool = True, verbose: bool =
         for bpc in BLOCKS_PER_CU:
             for grab in GRABS:
                 for lanes in LANES:
-                    cfg = dict(block=block, blocks_per_cu=bpc, grab=grab, lanes_per_chain=lanes)
-                    ch.set_launch(**cfg)
-                    ms = _time(ch, reps)
-                    results.append((ms, cfg))
-                    if verbose:
-                        print(f"autotune {cfg}: {ms:.3f} ms")
+                    for sort in SORTS:
+                        cfg = dict(block=block, blocks_per_cu=bpc, grab=grab, lanes_per_chain=lanes,
+                                   sort_by_length=sort)
+                        ch.set_launch(**cfg)
+                        ms = _time(ch, reps, per_launch)
+                        results.append((ms, cfg))
+                        if verbose:
+                            print(f"autotune {cfg}: {ms:.3f} ms/step")
     results.sort(key=lambda r: r[0])
     best_ms, best = results[0]
     ch.set_launch(**best)

@@ -91,6 +91,7 @@ struct DevScene {
     int n_lights;
     float tmin;
     int W, H;
+    int stack_cap;  // traversal stack entries per lane (the tree's exact worst case, <= DR_STACK)
 };
 struct Cam {
     V3 eye, cu, cv, cw;
@@ -162,12 +163,98 @@ __device__ __forceinline__ DevNode load_node(const DevNode* nodes, int i) {
 __device__ __forceinline__ float f4(const float4& v, int q) { return q == 0 ? v.x : (q == 1 ? v.y : (q == 2 ? v.z : v.w)); }
 __device__ __forceinline__ int i4(const int4& v, int q) { return q == 0 ? v.x : (q == 1 ? v.y : (q == 2 ? v.z : v.w)); }
 
+// One node visit of a ray query: tests the node's four child boxes, tests the
+// triangles of every hit leaf child (the lanes of a wavefront loop over their
+// own hit leaves, lowest child first, four triangles' loads in flight at
+// once), and returns the hit inner children sorted near to far in kc (-1 =
+// none; a fixed sorting network keeps every index static).  Returns true when
+// an any-hit query has found its hit (slot in best).
+__device__ __forceinline__ bool visit_node(const DevScene& S, int node, V3 o, V3 d, V3 inv, float tmax, bool anyhit,
+                                           float& bt, int& best, uint32_t& best_prim, int (&kc)[4], Counters& ctr) {
+    const DevNode n = load_node(S.nodes, node);
+    ctr.nodes++;
+    float tn[4];
+    bool hit[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        hit[q] = i4(n.count, q) >= 0 && slab(f4(n.lox, q), f4(n.loy, q), f4(n.loz, q), f4(n.hix, q), f4(n.hiy, q),
+                                              f4(n.hiz, q), o, inv, S.tmin, bt, tn[q]);
+    uint32_t leaves = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if (hit[q] && i4(n.count, q) > 0) leaves |= 1u << q;
+    while (leaves) {
+        const int q = __ffs(leaves) - 1;
+        leaves &= leaves - 1u;
+        const int cnt = i4(n.count, q);
+        const int first = i4(n.child, q);
+        for (int k0 = first; k0 < first + cnt; k0 += 4) {
+            DevTri T[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (k0 + e < first + cnt) T[e] = S.tris[k0 + e];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                if (k0 + e >= first + cnt) break;
+                ctr.tris++;
+                float t;
+                if (tri_test(T[e], o, d, S.tmin, t) && t <= bt) {
+                    const uint32_t prim = __float_as_uint(T[e].v0.w);
+                    if (anyhit && t < tmax) {
+                        best = k0 + e;
+                        return true;
+                    }
+                    if (t < bt || (t == bt && prim < best_prim)) {
+                        bt = t;
+                        best = k0 + e;
+                        best_prim = prim;
+                    }
+                }
+            }
+        }
+    }
+    float kt[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const bool inner = hit[q] && i4(n.count, q) == 0;
+        kt[q] = inner ? tn[q] : INFINITY;
+        kc[q] = inner ? i4(n.child, q) : -1;
+    }
+#define DR_CSWAP(i, j)                                       \
+    if (kt[j] < kt[i]) {                                     \
+        const float tt_ = kt[i]; kt[i] = kt[j]; kt[j] = tt_; \
+        const int cc_ = kc[i]; kc[i] = kc[j]; kc[j] = cc_;   \
+    }
+    DR_CSWAP(0, 1)
+    DR_CSWAP(2, 3)
+    DR_CSWAP(0, 2)
+    DR_CSWAP(1, 3)
+    DR_CSWAP(1, 2)
+#undef DR_CSWAP
+    return false;
+}
+
+// Stack step after a visit: descend into the nearest hit child and push the
+// others far-first, or pop.  Returns false when the traversal is over.
+__device__ __forceinline__ bool next_node(const int (&kc)[4], int& node, int& sp, uint32_t* stk, int stride,
+                                          int cap) {
+    if (kc[0] < 0) {
+        if (sp == 0) return false;
+        node = (int)stk[(--sp) * stride];
+    } else {
+        if (kc[3] >= 0 && sp < cap) stk[(sp++) * stride] = (uint32_t)kc[3];
+        if (kc[2] >= 0 && sp < cap) stk[(sp++) * stride] = (uint32_t)kc[2];
+        if (kc[1] >= 0 && sp < cap) stk[(sp++) * stride] = (uint32_t)kc[1];
+        node = kc[0];
+    }
+    return true;
+}
+
 // One ray query over (tmin, tmax): the closest hit (ties in t go to the lower
 // input triangle index) or, with anyhit, the first hit found.  Returns the
 // triangle slot (leaf order) or -1; tmax <= tmin means "no ray" and returns -1
 // at once (used by paired lanes that have nothing to trace).  stk is this
-// lane's LDS stack, entries at stk[k * stride].  A leaf's triangles are fetched
-// four at a time so their loads are in flight together.
+// lane's LDS stack, entries at stk[k * stride].
 __device__ int trace(const DevScene& S, V3 o, V3 d, float tmax, bool anyhit, float& t_hit, uint32_t* stk, int stride,
                      Counters& ctr) {
     t_hit = tmax;
@@ -180,76 +267,12 @@ __device__ int trace(const DevScene& S, V3 o, V3 d, float tmax, bool anyhit, flo
     int node = 0;
     ctr.rays++;
     while (true) {
-        const DevNode n = load_node(S.nodes, node);
-        ctr.nodes++;
-        float tn[4];
-        bool hit[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            hit[q] = i4(n.count, q) >= 0 && slab(f4(n.lox, q), f4(n.loy, q), f4(n.loz, q), f4(n.hix, q), f4(n.hiy, q),
-                                                  f4(n.hiz, q), o, inv, S.tmin, bt, tn[q]);
-        // leaves are tested on the spot, four triangles' loads in flight at once
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int cnt = i4(n.count, q);
-            const int first = i4(n.child, q);
-            if (hit[q] && cnt > 0) {
-                for (int k0 = first; k0 < first + cnt; k0 += 4) {
-                    DevTri T[4];
-#pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        if (k0 + e < first + cnt) T[e] = S.tris[k0 + e];
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        if (k0 + e >= first + cnt) break;
-                        ctr.tris++;
-                        float t;
-                        if (tri_test(T[e], o, d, S.tmin, t) && t <= bt) {
-                            const uint32_t prim = __float_as_uint(T[e].v0.w);
-                            if (anyhit && t < tmax) {
-                                t_hit = t;
-                                return k0 + e;
-                            }
-                            if (t < bt || (t == bt && prim < best_prim)) {
-                                bt = t;
-                                best = k0 + e;
-                                best_prim = prim;
-                            }
-                        }
-                    }
-                }
-            }
-        }
-        // inner children hit: visit the nearest next, push the others
-        // far-first (a fixed sorting network keeps every index static)
-        float kt[4];
         int kc[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const bool inner = hit[q] && i4(n.count, q) == 0;
-            kt[q] = inner ? tn[q] : INFINITY;
-            kc[q] = inner ? i4(n.child, q) : -1;
+        if (visit_node(S, node, o, d, inv, tmax, anyhit, bt, best, best_prim, kc, ctr)) {
+            t_hit = bt;
+            return best;
         }
-#define DR_CSWAP(i, j)                                  \
-    if (kt[j] < kt[i]) {                                \
-        const float tt_ = kt[i]; kt[i] = kt[j]; kt[j] = tt_; \
-        const int cc_ = kc[i]; kc[i] = kc[j]; kc[j] = cc_;   \
-    }
-        DR_CSWAP(0, 1)
-        DR_CSWAP(2, 3)
-        DR_CSWAP(0, 2)
-        DR_CSWAP(1, 3)
-        DR_CSWAP(1, 2)
-#undef DR_CSWAP
-        if (kc[0] < 0) {
-            if (sp == 0) break;
-            node = (int)stk[(--sp) * stride];
-        } else {
-            if (kc[3] >= 0 && sp < DR_STACK) stk[(sp++) * stride] = (uint32_t)kc[3];
-            if (kc[2] >= 0 && sp < DR_STACK) stk[(sp++) * stride] = (uint32_t)kc[2];
-            if (kc[1] >= 0 && sp < DR_STACK) stk[(sp++) * stride] = (uint32_t)kc[1];
-            node = kc[0];
-        }
+        if (!next_node(kc, node, sp, stk, stride, S.stack_cap)) break;
     }
     t_hit = bt;
     return anyhit ? -1 : best;
@@ -400,7 +423,7 @@ __device__ __forceinline__ void trace_vertex_rays(const DevScene& S, V3 x, bool 
 
 template <bool PAIR, class U>
 __device__ V3 path_forward(const DevScene& S, int L, const U& u, uint32_t* rec, int rs, uint32_t* stk, int stride,
-                           Counters& ctr) {
+                           Counters& ctr, int* nverts = nullptr) {
     V3 f = v3(0.f, 0.f, 0.f);
     const Cam C = load_cam(S);
     V3 d = camera_dir(C, u(0), u(1));
@@ -471,6 +494,7 @@ __device__ V3 path_forward(const DevScene& S, int L, const U& u, uint32_t* rec, 
         }
         ++j;
     }
+    if (nverts) *nverts = j - 1;
     if (rec)
         for (; j <= L - 1; ++j) rec[(j - 1) * rs] = DR_NO_VERTEX;
     return f;

@@ -23,6 +23,7 @@
 #include "../../include/dr.h"
 #include "dr_adjoint.h"
 #include "dr_chain.h"
+#include "dr_machine.h"
 #include "dr_device.h"
 
 using namespace dr;
@@ -63,7 +64,21 @@ struct KBufs {
     // step counters in device memory so captured graphs replay correctly:
     // [0] next step index, [1] first step index of the current launch, [2] frame
     unsigned long long* steps;
+    // Chain state sits in slots; ids[slot] is the chain occupying it (its RNG
+    // streams and its row of a per-chain Sigma).  The fused form may move
+    // chains between slots so chains with equal last path length share a
+    // wavefront: key per slot (vertex count, or DR_NBIN-1 for a killed chain),
+    // order = source slot of each destination slot, bins = counting-sort
+    // counts and offsets, alt = staging rows for the move.
+    uint32_t* ids;
+    uint32_t* key;
+    uint32_t* order;
+    uint32_t* bins;
+    uint32_t* state;  // rows: x[d], score[d], rec[L-1], killed, ids, then the record rows p, w, pix, f[3]
+    uint32_t* alt;    // same shape as state
 };
+
+#define DR_NBIN 9
 
 enum { C_TOURS = 0, C_STEPS = 1, C_RAYS = 2, C_NODES = 3, C_TRIS = 4, C_ADJ = 5, C_N = 8 };
 
@@ -82,10 +97,11 @@ __device__ __forceinline__ void wave_add(unsigned long long* dst, uint32_t v) {
 }
 
 // Hold/kill and splat (Accumulate).  Returns true if the tour survives.
-__device__ __forceinline__ bool hold_kill_splat(const KParams& P, const KBufs& B, const DevScene& S, int c, uint64_t s,
-                                                float k0, V3 f, float p, uint32_t pix, bool lead = true) {
+// c: slot of the chain, id: the chain (RNG streams).
+__device__ __forceinline__ bool hold_kill_splat(const KParams& P, const KBufs& B, const DevScene& S, int c, int id,
+                                                uint64_t s, float k0, V3 f, float p, uint32_t pix, bool lead = true) {
     float wdt;
-    const bool alive = hold_kill(P.seed, c, s, k0, p, P.eps, P.dt, P.rb, wdt);
+    const bool alive = hold_kill(P.seed, id, s, k0, p, P.eps, P.dt, P.rb, wdt);
     if (lead && p > 0.0f) {
         const float sc = wdt / p;
         const size_t npx = (size_t)S.W * S.H;
@@ -149,12 +165,16 @@ __global__ void __launch_bounds__(256) k_init_eval(KParams P, DevScene S, KBufs 
     Counters ctr = {0, 0, 0};
     if (c < P.N) {
         regen(P.seed, P.d, P.N, B.x + c, c, s0);
-        const V3 f = path_forward<false>(S, P.L, SoaU{B.x + c, P.N}, B.rec + c, P.N, s_stack + threadIdx.x, blockDim.x, ctr);
+        int nv;
+        const V3 f = path_forward<false>(S, P.L, SoaU{B.x + c, P.N}, B.rec + c, P.N, s_stack + threadIdx.x, blockDim.x,
+                                         ctr, &nv);
         B.p_tmp[c] = lum(f);
         B.f_tmp[c] = f.x;
         B.f_tmp[(size_t)P.N + c] = f.y;
         B.f_tmp[(size_t)2 * P.N + c] = f.z;
         B.pix_tmp[c] = pixel_of(S, B.x[c], B.x[(size_t)P.N + c]);
+        B.key[c] = (uint32_t)nv;
+        B.ids[c] = (uint32_t)c;
     }
     if (P.count) {
         wave_add(&B.ctr[C_RAYS], ctr.rays);
@@ -199,8 +219,9 @@ __global__ void __launch_bounds__(256) k_init_accumulate(KParams P, DevScene S, 
     if (c < P.N) {
         const float p = B.p_tmp[c];
         const V3 f = v3(B.f_tmp[c], B.f_tmp[(size_t)P.N + c], B.f_tmp[(size_t)2 * P.N + c]);
-        const bool alive = hold_kill_splat(P, B, S, c, s0, *B.k0, f, p, B.pix_tmp[c]);
+        const bool alive = hold_kill_splat(P, B, S, c, c, s0, *B.k0, f, p, B.pix_tmp[c]);
         B.killed[c] = alive ? 0u : 1u;
+        if (!alive) B.key[c] = DR_NBIN - 1;
         kill = alive ? 0u : 1u;
         if (alive && with_score) {
             score_at<L>(P, B, S, c, p);
@@ -214,12 +235,67 @@ __global__ void __launch_bounds__(256) k_init_accumulate(KParams P, DevScene S, 
     }
 }
 
+// ---- grouping chains by their last path length (a counting sort over
+// DR_NBIN keys, block-aggregated so each block issues one global atomic per
+// key).  bins[0..15] counts, bins[16..31] running positions.
+__global__ void __launch_bounds__(256) k_sort_hist(const uint32_t* key, int N, uint32_t* bins) {
+    __shared__ uint32_t h[DR_NBIN];
+    if (threadIdx.x < DR_NBIN) h[threadIdx.x] = 0;
+    __syncthreads();
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < N) atomicAdd(&h[min(key[c], (uint32_t)(DR_NBIN - 1))], 1u);
+    __syncthreads();
+    if (threadIdx.x < DR_NBIN && h[threadIdx.x]) atomicAdd(&bins[threadIdx.x], h[threadIdx.x]);
+}
+__global__ void k_sort_prefix(uint32_t* bins) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    uint32_t run = 0;
+    for (int b = 0; b < DR_NBIN; ++b) {
+        bins[16 + b] = run;
+        run += bins[b];
+    }
+}
+__global__ void __launch_bounds__(256) k_sort_scatter(const uint32_t* key, int N, uint32_t* bins, uint32_t* order) {
+    __shared__ uint32_t h[DR_NBIN], base[DR_NBIN];
+    if (threadIdx.x < DR_NBIN) h[threadIdx.x] = 0;
+    __syncthreads();
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t k = 0, r = 0;
+    if (c < N) {
+        k = min(key[c], (uint32_t)(DR_NBIN - 1));
+        r = atomicAdd(&h[k], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < DR_NBIN && h[threadIdx.x]) base[threadIdx.x] = atomicAdd(&bins[16 + threadIdx.x], h[threadIdx.x]);
+    __syncthreads();
+    if (c < N) order[base[k] + r] = (uint32_t)c;
+}
+// alt[row][q] = state[row][order[q]]: chains move to the slots the sort gave them
+__global__ void __launch_bounds__(256) k_slots_gather(const uint32_t* state, uint32_t* alt, const uint32_t* order,
+                                                      int N) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t row = (size_t)blockIdx.y * N;
+    if (q < N) alt[row + q] = state[row + order[q]];
+}
+// alt[row][ids[q]] = state[row][q]: every chain back to the slot of its id
+__global__ void __launch_bounds__(256) k_slots_restore(const uint32_t* state, uint32_t* alt, const uint32_t* ids,
+                                                       int N) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t row = (size_t)blockIdx.y * N;
+    if (q < N) alt[row + ids[q]] = state[row + q];
+}
+__global__ void __launch_bounds__(256) k_copy_u32(const uint32_t* src, uint32_t* dst, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
 // Fused persistent evolve step: every chain advances nsteps steps.  With
 // PAIR, two adjacent lanes share a chain: both run its step on the same data,
 // the path's continuation and shadow rays are traced concurrently (one per
 // lane), and only the even lane performs the atomics.
 template <int L, bool PAIR>
-__global__ void __launch_bounds__(256) k_step_fused(KParams P, DevScene S, KBufs B, uint32_t nsteps, uint32_t grab) {
+__global__ void __launch_bounds__(256) k_step_fused(KParams P, DevScene S, KBufs B, uint32_t nsteps, uint32_t grab,
+                                                    int sorted) {
     extern __shared__ uint32_t s_stack[];
     uint32_t* stk = s_stack + threadIdx.x;
     const int stride = blockDim.x;
@@ -259,16 +335,19 @@ __global__ void __launch_bounds__(256) k_step_fused(KParams P, DevScene S, KBufs
         if (!__any(active)) break;
         if (active) {
             const uint64_t s = s0 + k;
+            const int id = (int)B.ids[c];  // the chain in slot c
             float* xc = B.x + c;
             // both lanes of a pair store identical values
-            if (B.killed[c]) regen(P.seed, P.d, P.N, xc, c, s);
-            else move(P.seed, P.d, P.N, P.stddev, P.gt, xc, B.score + c, B.sigma ? B.sigma + c : nullptr, c, s);
+            if (B.killed[c]) regen(P.seed, P.d, P.N, xc, id, s);
+            else move(P.seed, P.d, P.N, P.stddev, P.gt, xc, B.score + c, B.sigma ? B.sigma + id : nullptr, id, s);
             const SoaU u{xc, P.N};
-            const V3 f = path_forward<PAIR>(S, L, u, B.rec + c, P.N, stk, stride, ctr);
+            int nv;
+            const V3 f = path_forward<PAIR>(S, L, u, B.rec + c, P.N, stk, stride, ctr, &nv);
             const float p = lum(f);
             const uint32_t pix = pixel_of(S, xc[0], xc[P.N]);
-            const bool alive = hold_kill_splat(P, B, S, c, s, k0, f, p, pix, lead);
+            const bool alive = hold_kill_splat(P, B, S, c, id, s, k0, f, p, pix, lead);
             B.killed[c] = alive ? 0u : 1u;
+            if (sorted) B.key[c] = alive ? (uint32_t)nv : (uint32_t)(DR_NBIN - 1);
             if (lead) kills += alive ? 0u : 1u;
             if (alive) {
                 score_at<L>(P, B, S, c, p);
@@ -344,7 +423,7 @@ __global__ void __launch_bounds__(256) k_plain_accumulate(KParams P, DevScene S,
     if (c < P.N) {
         const float p = B.p_tmp[c];
         const V3 f = v3(B.f_tmp[c], B.f_tmp[(size_t)P.N + c], B.f_tmp[(size_t)2 * P.N + c]);
-        const bool alive = hold_kill_splat(P, B, S, c, s, *B.k0, f, p, B.pix_tmp[c]);
+        const bool alive = hold_kill_splat(P, B, S, c, c, s, *B.k0, f, p, B.pix_tmp[c]);
         B.killed[c] = alive ? 0u : 1u;
         kill = alive ? 0u : 1u;
     }
@@ -391,6 +470,80 @@ __global__ void __launch_bounds__(256) k_eval(DevScene S, const float* u, int n,
             rec_out[(size_t)i * (L - 1) + j] =
                 r == DR_NO_VERTEX ? r : ((__float_as_uint(S.tris[r >> 8].v0.w) << 8) | (r & 0xFFu));
         }
+}
+
+// Outputs of the state-machine evaluator for point i.
+template <int L>
+struct EvalRec {
+    const DevTri* tris;
+    uint32_t* rec_out;
+    float* fo;
+    float* logp;
+    float eps;
+    int i;
+    __device__ __forceinline__ void vertex(int j, uint32_t r) const {
+        if (rec_out)
+            rec_out[(size_t)i * (L - 1) + (j - 1)] = (__float_as_uint(tris[r >> 8].v0.w) << 8) | (r & 0xFFu);
+    }
+    __device__ __forceinline__ void finish(V3 f, int nv) const {
+        if (rec_out)
+            for (int j = nv + 1; j <= L - 1; ++j) rec_out[(size_t)i * (L - 1) + (j - 1)] = DR_NO_VERTEX;
+        if (fo) {
+            fo[3 * (size_t)i] = f.x;
+            fo[3 * (size_t)i + 1] = f.y;
+            fo[3 * (size_t)i + 2] = f.z;
+        }
+        if (logp) logp[i] = logf(lum(f) + eps);
+    }
+};
+
+// Forward evaluation of n points with the ray-refill state machine
+// (persistent; points are taken from a device counter).  thresh: events run
+// once at least thresh percent of the busy lanes wait for one.
+template <int L>
+__global__ void __launch_bounds__(256) k_eval_sm(DevScene S, const float* u, int n, float eps, float* fo, float* logp,
+                                                 uint32_t* rec_out, uint32_t* queue, int thresh) {
+    extern __shared__ uint32_t s_stack[];
+    uint32_t* stk = s_stack + threadIdx.x;
+    const int stride = blockDim.x;
+    const int lane = threadIdx.x & 63;
+    constexpr int d = 4 * (L - 1);
+    const Cam C = load_cam(S);
+    Counters ctr = {0, 0, 0};
+    RayQ q;
+    PathSM P;
+    P.phase = PH_NEW;
+    int item = -1;
+    bool tracing = false, drained = false;
+    while (true) {
+        const bool need = !drained && item < 0;
+        const uint64_t nm = __ballot(need);
+        if (nm) {
+            const int leader = __ffsll((long long)nm) - 1;
+            uint32_t base = 0;
+            if (lane == leader) base = atomicAdd(queue, (uint32_t)__popcll(nm));
+            base = __shfl(base, leader);
+            if (need) {
+                const uint32_t it = base + (uint32_t)__popcll(nm & ((1ull << lane) - 1ull));
+                if (it < (uint32_t)n) item = (int)it;
+                else drained = true;
+            }
+        }
+        const bool ev = !drained && !tracing;
+        const uint64_t em = __ballot(ev), tm = __ballot(tracing);
+        if (!em && !tm) break;
+        const int nev = __popcll(em), ntr = __popcll(tm);
+        if (nev && (!ntr || 100 * nev >= thresh * (nev + ntr))) {
+            if (ev) {
+                const RowU uu{u + (size_t)item * d};
+                const EvalRec<L> R{S.tris, rec_out, fo, logp, eps, item};
+                tracing = sm_event<L>(S, C, uu, P, q, R, ctr);
+                if (!tracing) item = -1;
+            }
+        } else if (tracing) {
+            if (ray_step(S, q, stk, stride, ctr)) tracing = false;
+        }
+    }
 }
 
 // Independent path tracing, one thread per pixel.
@@ -491,6 +644,7 @@ struct dr_scene {
     dr_camera cam{};
     uint32_t cam_version = 0;
     uint32_t n_tris = 0;
+    uint32_t n_nodes = 0;
 };
 
 struct dr_chains {
@@ -503,12 +657,14 @@ struct dr_chains {
     uint64_t seed = 0;
     int n_partials = 0;
     int record = 0, count = 0;
-    dr_launch_cfg launch{256, 2, 1, 2};
+    dr_launch_cfg launch{256, 2, 1, 2, 0};
     int n_cu = 256;
+    int rows_move = 0, rows_all = 0;  // state rows moved per sorted launch / restored before host access
+    bool permuted = false;            // chains may sit outside the slot of their id
 };
 
 // ---------------------------------------------------------------------------
-static size_t stack_bytes(int block) { return (size_t)DR_STACK * block * sizeof(uint32_t); }
+static size_t stack_bytes(const DevScene& S, int block) { return (size_t)S.stack_cap * block * sizeof(uint32_t); }
 
 #define DR_DISPATCH_L(L, FN, ...)          \
     switch (L) {                           \
@@ -537,18 +693,23 @@ static void launch_init_acc(dim3 g, dim3 b, hipStream_t st, const KParams& P, co
 }
 template <int L>
 static void launch_fused(dim3 g, dim3 b, hipStream_t st, const KParams& P, const DevScene& S, const KBufs& B,
-                         uint32_t n, uint32_t grab, bool pair) {
-    if (pair) hipLaunchKernelGGL((k_step_fused<L, true>), g, b, stack_bytes(b.x), st, P, S, B, n, grab);
-    else hipLaunchKernelGGL((k_step_fused<L, false>), g, b, stack_bytes(b.x), st, P, S, B, n, grab);
+                         uint32_t n, uint32_t grab, bool pair, int sorted) {
+    if (pair) hipLaunchKernelGGL((k_step_fused<L, true>), g, b, stack_bytes(S, b.x), st, P, S, B, n, grab, sorted);
+    else hipLaunchKernelGGL((k_step_fused<L, false>), g, b, stack_bytes(S, b.x), st, P, S, B, n, grab, sorted);
 }
 template <int L>
 static void launch_plain_score(dim3 g, dim3 b, hipStream_t st, const KParams& P, const DevScene& S, const KBufs& B) {
-    hipLaunchKernelGGL(k_plain_score<L>, g, b, stack_bytes(b.x), st, P, S, B);
+    hipLaunchKernelGGL(k_plain_score<L>, g, b, stack_bytes(S, b.x), st, P, S, B);
+}
+template <int L>
+static void launch_eval_sm(dim3 g, dim3 b, hipStream_t st, const DevScene& S, const float* u, int n, float eps,
+                           float* fo, float* logp, uint32_t* ro, uint32_t* queue, int thresh) {
+    hipLaunchKernelGGL(k_eval_sm<L>, g, b, stack_bytes(S, b.x), st, S, u, n, eps, fo, logp, ro, queue, thresh);
 }
 template <int L>
 static void launch_eval(dim3 g, dim3 b, hipStream_t st, const DevScene& S, const float* u, int n, float eps, float* fo,
                         float* logp, float* grad, uint32_t* rs, uint32_t* ro) {
-    hipLaunchKernelGGL(k_eval<L>, g, b, stack_bytes(b.x), st, S, u, n, eps, fo, logp, grad, rs, ro);
+    hipLaunchKernelGGL(k_eval<L>, g, b, stack_bytes(S, b.x), st, S, u, n, eps, fo, logp, grad, rs, ro);
 }
 
 // Enqueue the initialise pass (Alg. 4.1).  from_device: take the frame index
@@ -565,7 +726,7 @@ static void enqueue_init(dr_chains* c, uint32_t frame, int from_device, hipStrea
     hipLaunchKernelGGL(k_begin_init, dim3(1), dim3(64), 0, st, c->kb, frame, from_device);
     hipLaunchKernelGGL(k_fill_f32, dim3(1024), dim3(256), 0, st, c->kb.accum, 3 * npx);
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, c->kb.ctr, (int)C_N);
-    hipLaunchKernelGGL(k_init_eval, g, b, stack_bytes(blk), st, P, c->scene->ds, c->kb);
+    hipLaunchKernelGGL(k_init_eval, g, b, stack_bytes(c->scene->ds, blk), st, P, c->scene->ds, c->kb);
     hipLaunchKernelGGL(k_reduce_p, dim3(c->n_partials), dim3(256), 0, st, P, c->kb);
     hipLaunchKernelGGL(k_finish_k0, dim3(1), dim3(64), 0, st, P, c->kb, c->n_partials, (double)c->P.k0, (double)c->P.m);
     const int with_score = c->P.mode == DR_MODE_FUSED ? 1 : 0;
@@ -580,6 +741,19 @@ static void enqueue_steps(dr_chains* c, uint32_t n_steps, hipStream_t st) {
     P.count = c->count;
     const int N = P.N;
     if (c->P.mode == DR_MODE_FUSED) {
+        const int sorted = c->launch.sort_by_length ? 1 : 0;
+        if (sorted) {
+            const dim3 gs((N + 255) / 256), bs(256);
+            hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, c->kb.bins, (size_t)32, 0u);
+            hipLaunchKernelGGL(k_sort_hist, gs, bs, 0, st, c->kb.key, N, c->kb.bins);
+            hipLaunchKernelGGL(k_sort_prefix, dim3(1), dim3(64), 0, st, c->kb.bins);
+            hipLaunchKernelGGL(k_sort_scatter, gs, bs, 0, st, c->kb.key, N, c->kb.bins, c->kb.order);
+            hipLaunchKernelGGL(k_slots_gather, dim3(gs.x, c->rows_move), bs, 0, st, c->kb.state, c->kb.alt,
+                               c->kb.order, N);
+            hipLaunchKernelGGL(k_copy_u32, dim3(2048), bs, 0, st, c->kb.alt, c->kb.state,
+                               (size_t)c->rows_move * N);
+            c->permuted = true;
+        }
         hipLaunchKernelGGL(k_begin_launch, dim3(1), dim3(64), 0, st, c->kb, n_steps);
         const int blk = (int)c->launch.block;
         const bool pair = c->launch.lanes_per_chain == 2;
@@ -587,7 +761,7 @@ static void enqueue_steps(dr_chains* c, uint32_t n_steps, hipStream_t st) {
         int blocks = (int)(c->n_cu * c->launch.blocks_per_cu);
         blocks = (int)std::max(1L, std::min((long)blocks, (lanes + blk - 1) / blk));
         DR_DISPATCH_L(P.L, launch_fused, dim3(blocks), dim3(blk), st, P, c->scene->ds, c->kb, n_steps,
-                      c->launch.grab, pair);
+                      c->launch.grab, pair, sorted);
     } else {
         const int blk = 256;
         const dim3 g((N + blk - 1) / blk), b(blk);
@@ -595,7 +769,7 @@ static void enqueue_steps(dr_chains* c, uint32_t n_steps, hipStream_t st) {
             hipLaunchKernelGGL(k_begin_launch, dim3(1), dim3(64), 0, st, c->kb, 1u);
             DR_DISPATCH_L(P.L, launch_plain_score, g, b, st, P, c->scene->ds, c->kb);
             hipLaunchKernelGGL(k_plain_move, g, b, 0, st, P, c->kb);
-            hipLaunchKernelGGL(k_plain_forward, g, b, stack_bytes(blk), st, P, c->scene->ds, c->kb);
+            hipLaunchKernelGGL(k_plain_forward, g, b, stack_bytes(c->scene->ds, blk), st, P, c->scene->ds, c->kb);
             hipLaunchKernelGGL(k_plain_accumulate, g, b, 0, st, P, c->scene->ds, c->kb);
         }
     }
@@ -608,7 +782,23 @@ static void enqueue_resolve(dr_chains* c, float* image_dev, hipStream_t st) {
                        image_dev, npx, c->kb.k0d, c->kb.ctr, (double)c->P.dt);
 }
 
+// Put every chain back into the slot of its id (before the host reads or
+// writes per-chain state).
+static dr_status restore_slots(dr_chains* c, hipStream_t st) {
+    if (!c->permuted) return DR_OK;
+    (void)hipGetLastError();
+    const int N = c->kp.N;
+    hipLaunchKernelGGL(k_slots_restore, dim3((N + 255) / 256, c->rows_all), dim3(256), 0, st, c->kb.state, c->kb.alt,
+                       c->kb.ids, N);
+    hipLaunchKernelGGL(k_copy_u32, dim3(2048), dim3(256), 0, st, c->kb.alt, c->kb.state, (size_t)c->rows_all * N);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(DR_ERR_DEVICE, std::string("slot restore launch: ") + hipGetErrorString(e));
+    c->permuted = false;
+    return DR_OK;
+}
+
 static dr_status run_init(dr_chains* c, uint32_t frame, hipStream_t st) {
+    c->permuted = false;  // the initialise pass puts chain c in slot c
     enqueue_init(c, frame, 0, st);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(DR_ERR_DEVICE, std::string("initialise pass launch: ") + hipGetErrorString(e));
@@ -902,6 +1092,8 @@ dr_status dr_scene_create(const dr_scene_desc* desc, int device, dr_scene** out)
     S->ds.cam = (const float4*)dcam;
     S->ds.W = (int)desc->camera.width;
     S->ds.H = (int)desc->camera.height;
+    S->ds.stack_cap = std::max(1, need.empty() ? 1 : need[0]);
+    S->n_nodes = (uint32_t)dn.size();
     S->cam = desc->camera;
     S->slot_to_prim = std::move(slot_to_prim);
     S->n_tris = T;
@@ -922,6 +1114,16 @@ dr_status dr_scene_set_camera(dr_scene* s, const dr_camera* cam) {
     HIP_TRY(hipMemcpy((void*)s->ds.cam, cam4, sizeof(cam4), hipMemcpyHostToDevice));
     s->cam = *cam;
     s->cam_version++;
+    g_err.clear();
+    return DR_OK;
+}
+
+dr_status dr_scene_get_stats(const dr_scene* s, dr_scene_stats* out) {
+    if (!s || !out) return fail(DR_ERR_INVALID_ARG, "dr_scene_get_stats: null argument");
+    out->n_triangles = s->n_tris;
+    out->n_nodes = s->n_nodes;
+    out->stack_entries = (uint32_t)s->ds.stack_cap;
+    out->stack_bytes_per_lane = (uint32_t)(s->ds.stack_cap * sizeof(uint32_t));
     g_err.clear();
     return DR_OK;
 }
@@ -968,21 +1170,32 @@ dr_status dr_chains_init(dr_scene* s, const dr_params* p, uint64_t seed, uint32_
     void* q;
     bool ok = true;
     auto get = [&](void** ptr, size_t bytes) { if (ok && c->mem.get(ptr, bytes) != hipSuccess) ok = false; };
-    get(&q, sizeof(float) * d * (size_t)N); B.x = (float*)q;
-    get(&q, sizeof(float) * d * (size_t)N); B.score = (float*)q;
-    get(&q, sizeof(uint32_t) * N); B.killed = (uint32_t*)q;
-    get(&q, sizeof(uint32_t) * (L - 1) * (size_t)N); B.rec = (uint32_t*)q;
+    c->rows_move = 2 * d + (L - 1) + 2;
+    c->rows_all = c->rows_move + 6;
+    get(&q, sizeof(uint32_t) * c->rows_all * (size_t)N); B.state = (uint32_t*)q;
+    get(&q, sizeof(uint32_t) * c->rows_all * (size_t)N); B.alt = (uint32_t*)q;
+    if (ok) {
+        uint32_t* r = B.state;
+        B.x = (float*)r; r += (size_t)d * N;
+        B.score = (float*)r; r += (size_t)d * N;
+        B.rec = r; r += (size_t)(L - 1) * N;
+        B.killed = r; r += N;
+        B.ids = r; r += N;
+        B.p_tmp = (float*)r; r += N;
+        B.r_w = (float*)r; r += N;
+        B.pix_tmp = r; r += N;
+        B.f_tmp = (float*)r;
+    }
     get(&q, sizeof(float) * 3 * npx); B.accum = (float*)q;
     get(&q, sizeof(unsigned long long) * C_N); B.ctr = (unsigned long long*)q;
     get(&q, 64); B.k0 = (float*)q; B.k0d = (double*)((char*)q + 16); B.plam = (double*)((char*)q + 32);
     get(&q, 64); B.queue = (uint32_t*)q;
-    get(&q, sizeof(float) * N); B.p_tmp = (float*)q;
-    get(&q, sizeof(float) * 3 * (size_t)N); B.f_tmp = (float*)q;
-    get(&q, sizeof(uint32_t) * N); B.pix_tmp = (uint32_t*)q;
-    get(&q, sizeof(float) * N); B.r_w = (float*)q;
     get(&q, sizeof(double) * c->n_partials); B.partial = (double*)q;
     get(&q, sizeof(float) * 3 * npx); B.img = (float*)q;
     get(&q, 64); B.steps = (unsigned long long*)q;
+    get(&q, sizeof(uint32_t) * N); B.key = (uint32_t*)q;
+    get(&q, sizeof(uint32_t) * N); B.order = (uint32_t*)q;
+    get(&q, sizeof(uint32_t) * 32); B.bins = (uint32_t*)q;
     B.sigma = p->sigma_diag;
     if (!ok) {
         c->mem.release();
@@ -1068,6 +1281,7 @@ dr_status dr_chains_read_state(dr_chains* c, dr_state* o, void* hip_stream) {
     if (!c || !o) return fail(DR_ERR_INVALID_ARG, "dr_chains_read_state: null argument");
     HIP_TRY(hipSetDevice(c->scene->device));
     hipStream_t st = (hipStream_t)hip_stream;
+    if (restore_slots(c, st) != DR_OK) return DR_ERR_DEVICE;
     HIP_TRY(hipStreamSynchronize(st));
     const size_t N = c->kp.N, d = c->kp.d, V = c->kp.L - 1;
     const size_t npx = (size_t)c->scene->ds.W * c->scene->ds.H;
@@ -1106,6 +1320,7 @@ dr_status dr_chains_read_state(dr_chains* c, dr_state* o, void* hip_stream) {
 dr_status dr_chains_write_state(dr_chains* c, const dr_state* in, void* hip_stream) {
     if (!c || !in) return fail(DR_ERR_INVALID_ARG, "dr_chains_write_state: null argument");
     HIP_TRY(hipSetDevice(c->scene->device));
+    if (restore_slots(c, (hipStream_t)hip_stream) != DR_OK) return DR_ERR_DEVICE;
     HIP_TRY(hipStreamSynchronize((hipStream_t)hip_stream));
     const size_t N = c->kp.N, d = c->kp.d;
     const size_t npx = (size_t)c->scene->ds.W * c->scene->ds.H;
@@ -1179,10 +1394,12 @@ dr_status dr_chains_set_launch(dr_chains* c, const dr_launch_cfg* cfg) {
     if (cfg->blocks_per_cu > 64) return fail(DR_ERR_INVALID_ARG, "dr_chains_set_launch: blocks_per_cu must be <= 64");
     if (cfg->grab > 64) return fail(DR_ERR_INVALID_ARG, "dr_chains_set_launch: grab must be <= 64");
     if (cfg->lanes_per_chain > 2) return fail(DR_ERR_INVALID_ARG, "dr_chains_set_launch: lanes_per_chain must be 1 or 2");
+    if (cfg->sort_by_length > 2) return fail(DR_ERR_INVALID_ARG, "dr_chains_set_launch: sort_by_length must be 0, 1 or 2");
     if (cfg->block) c->launch.block = cfg->block;
     if (cfg->blocks_per_cu) c->launch.blocks_per_cu = cfg->blocks_per_cu;
     if (cfg->grab) c->launch.grab = cfg->grab;
     if (cfg->lanes_per_chain) c->launch.lanes_per_chain = cfg->lanes_per_chain;
+    if (cfg->sort_by_length) c->launch.sort_by_length = cfg->sort_by_length == 1 ? 1u : 0u;
     g_err.clear();
     return DR_OK;
 }
@@ -1222,7 +1439,7 @@ dr_status dr_pt_render(dr_scene* s, uint32_t L, uint64_t seed, uint32_t spp, flo
     (void)hipGetLastError();  // drop a stale error left by an earlier, unrelated call
     const int npx = s->ds.W * s->ds.H;
     const int blk = 128;
-    hipLaunchKernelGGL(k_pt, dim3((npx + blk - 1) / blk), dim3(blk), stack_bytes(blk), (hipStream_t)hip_stream, s->ds,
+    hipLaunchKernelGGL(k_pt, dim3((npx + blk - 1) / blk), dim3(blk), stack_bytes(s->ds, blk), (hipStream_t)hip_stream, s->ds,
                        (int)L, seed, spp, img_dev);
     HIP_TRY(hipGetLastError());
     g_err.clear();

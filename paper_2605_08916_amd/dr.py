@@ -21,7 +21,8 @@ DR_MODE_FUSED, DR_MODE_PLAIN = 0, 1
 NO_VERTEX = 0xFFFFFFFF
 
 EXPORTED = [
-    "dr_last_error", "dr_version", "dr_bvh_build", "dr_scene_create", "dr_scene_set_camera", "dr_scene_destroy",
+    "dr_last_error", "dr_version", "dr_bvh_build", "dr_scene_create", "dr_scene_set_camera", "dr_scene_get_stats",
+    "dr_scene_destroy",
     "dr_chains_init", "dr_chains_reinit", "dr_step", "dr_resolve", "dr_image_read", "dr_chains_destroy",
     "dr_chains_read_state", "dr_chains_write_state", "dr_chains_set_record", "dr_chains_set_counters", "dr_stats",
     "dr_chains_set_launch", "dr_chains_get_launch", "dr_eval_logp_grad", "dr_pt_render",
@@ -56,6 +57,11 @@ class dr_camera(C.Structure):
                 ("width", C.c_uint32), ("height", C.c_uint32)]
 
 
+class dr_scene_stats(C.Structure):
+    _fields_ = [("n_triangles", C.c_uint32), ("n_nodes", C.c_uint32), ("stack_entries", C.c_uint32),
+                ("stack_bytes_per_lane", C.c_uint32)]
+
+
 class dr_scene_desc(C.Structure):
     _fields_ = [("vertices", C.POINTER(C.c_float)), ("n_vertices", C.c_uint32),
                 ("indices", C.POINTER(C.c_uint32)), ("n_triangles", C.c_uint32),
@@ -87,7 +93,7 @@ class dr_counters(C.Structure):
 
 class dr_launch_cfg(C.Structure):
     _fields_ = [("block", C.c_uint32), ("blocks_per_cu", C.c_uint32), ("grab", C.c_uint32),
-                ("lanes_per_chain", C.c_uint32)]
+                ("lanes_per_chain", C.c_uint32), ("sort_by_length", C.c_uint32)]
 
 
 _lib = None
@@ -112,6 +118,7 @@ def lib():
         "dr_scene_create": ([C.POINTER(dr_scene_desc), C.c_int, pp], st),
         "dr_scene_set_camera": ([P, C.POINTER(dr_camera)], st),
         "dr_scene_destroy": ([P], None),
+        "dr_scene_get_stats": ([P, C.POINTER(dr_scene_stats)], st),
         "dr_chains_init": ([P, C.POINTER(dr_params), C.c_uint64, C.c_uint32, P, pp], st),
         "dr_chains_reinit": ([P, C.c_uint32, P], st),
         "dr_step": ([P, C.c_uint32, P], st),
@@ -244,6 +251,11 @@ class Scene:
         c = _camera(np.asarray(cam, np.float32), self.W, self.H)
         _check(lib().dr_scene_set_camera(self.h, C.byref(c)))
 
+    def stats(self) -> dict:
+        o = dr_scene_stats()
+        _check(lib().dr_scene_get_stats(self.h, C.byref(o)))
+        return {k: getattr(o, k) for k, _ in dr_scene_stats._fields_}
+
     def close(self):
         if getattr(self, "h", None):
             lib().dr_scene_destroy(self.h)
@@ -347,14 +359,16 @@ class Chains:
         _check(lib().dr_stats(self.h, C.byref(c), _stream(stream)))
         return {k: getattr(c, k) for k, _ in dr_counters._fields_}
 
-    def set_launch(self, block=0, blocks_per_cu=0, grab=0, lanes_per_chain=0):
-        cfg = dr_launch_cfg(block, blocks_per_cu, grab, lanes_per_chain)
+    def set_launch(self, block=0, blocks_per_cu=0, grab=0, lanes_per_chain=0, sort_by_length=0):
+        """Zero keeps a field; sort_by_length: 1 on, 2 off."""
+        cfg = dr_launch_cfg(block, blocks_per_cu, grab, lanes_per_chain, sort_by_length)
         _check(lib().dr_chains_set_launch(self.h, C.byref(cfg)))
 
     def get_launch(self) -> dict:
         cfg = dr_launch_cfg()
         _check(lib().dr_chains_get_launch(self.h, C.byref(cfg)))
-        return dict(block=cfg.block, blocks_per_cu=cfg.blocks_per_cu, grab=cfg.grab, lanes_per_chain=cfg.lanes_per_chain)
+        return dict(block=cfg.block, blocks_per_cu=cfg.blocks_per_cu, grab=cfg.grab, lanes_per_chain=cfg.lanes_per_chain,
+                    sort_by_length=cfg.sort_by_length)
 
     def read_state(self, stream=None) -> dict:
         N, d, V = self.N, self.d, self.L - 1

@@ -406,6 +406,19 @@ def test_counters_and_scene_change(scenes):
     ch.step(1)
 
 
+def test_scene_stats(scenes):
+    """The device scene reports its size and the exact traversal stack bound
+    its kernels reserve in LDS."""
+    for which in ("tiny", "spheres_small"):
+        sc = scenes[which]
+        st = dr.Scene(sc).stats()
+        say(f"[scene stats] {which}: {st}")
+        assert st["n_triangles"] == sc["indices"].shape[0]
+        assert st["n_nodes"] >= 1
+        assert 1 <= st["stack_entries"] <= 64
+        assert st["stack_bytes_per_lane"] == 4 * st["stack_entries"]
+
+
 @pytest.mark.parametrize("which,L,N", [("tiny", 4, 1000), ("spheres_small", 8, 3000)])
 def test_paired_lanes_match_single_lane(scenes, which, L, N):
     """Two lanes per chain (continuation and shadow rays traced concurrently)
@@ -421,6 +434,31 @@ def test_paired_lanes_match_single_lane(scenes, which, L, N):
     a, b = out
     assert np.array_equal(a["x"], b["x"]) and np.array_equal(a["killed"], b["killed"])
     assert np.array_equal(a["score"][:, a["killed"] == 0], b["score"][:, b["killed"] == 0])
+    assert a["tour_count"] == b["tour_count"]
+    assert np.allclose(a["accum"], b["accum"], rtol=1e-5, atol=1e-6)
+
+
+@pytest.mark.parametrize("lanes", [1, 2])
+def test_length_ordering_matches_identity_order(scenes, lanes):
+    """Processing chains grouped by their last path length (a counting sort
+    before each launch) gives exactly the chains of the identity order; only
+    the order of the splat additions differs."""
+    N, L = 5000, 8
+    say(f"[sorted vs identity] scene=spheres_small L={L} N={N} lanes={lanes}")
+    S = dr.Scene(scenes["spheres_small"])
+    out = []
+    for sort in (2, 1):
+        ch = dr.Chains(S, N, L, 57, k0=250.0)
+        ch.set_launch(lanes_per_chain=lanes, sort_by_length=sort)
+        assert ch.get_launch()["sort_by_length"] == (1 if sort == 1 else 0)
+        for _ in range(3):
+            ch.step(1)
+        ch.step(4)
+        out.append(ch.read_state())
+    a, b = out
+    assert np.array_equal(a["x"], b["x"]) and np.array_equal(a["killed"], b["killed"])
+    assert np.array_equal(a["score"][:, a["killed"] == 0], b["score"][:, b["killed"] == 0])
+    assert np.array_equal(a["path_rec"], b["path_rec"])
     assert a["tour_count"] == b["tour_count"]
     assert np.allclose(a["accum"], b["accum"], rtol=1e-5, atol=1e-6)
 
@@ -516,3 +554,34 @@ def test_adjoint_long_paths_with_segment_recompute(orc):
         bad += (same & (np.abs(fd - g[:, i]) > tol)).sum()
     say(f"  FD checked {checked}, outside tolerance {bad}")
     assert checked > 5000 and bad <= 0.01 * checked
+
+
+def test_autotune_restores_chains(scenes, tmp_path, monkeypatch):
+    """The launch autotuner sweeps configurations on the live chain set, then
+    puts the chains back: tuning followed by n steps gives the chains n steps
+    give without tuning."""
+    from paper_2605_08916_amd import autotune
+    monkeypatch.setattr(autotune, "CACHE", str(tmp_path / "tune.json"))
+    monkeypatch.setattr(autotune, "BLOCKS", (128, 256))
+    monkeypatch.setattr(autotune, "BLOCKS_PER_CU", (2, 3))
+    say("[autotune] scene=spheres_small L=8 N=3000")
+    S = dr.Scene(scenes["spheres_small"])
+    a = dr.Chains(S, 3000, 8, 77, k0=250.0)
+    b = dr.Chains(S, 3000, 8, 77, k0=250.0)
+    a.step(2)
+    b.step(2)
+    entry = autotune.tune(a, reps=1, use_cache=True, per_launch=2)
+    applied = dict(entry["cfg"], sort_by_length=1 if entry["cfg"]["sort_by_length"] == 1 else 0)
+    assert a.get_launch() == applied
+    assert len(entry["sweep"]) == 2 * 2 * len(autotune.GRABS) * len(autotune.LANES) * len(autotune.SORTS)
+    a.step(3)
+    b.step(3)
+    sa, sb = a.read_state(), b.read_state()
+    assert sa["step"] == sb["step"]
+    assert np.array_equal(sa["x"], sb["x"]) and np.array_equal(sa["killed"], sb["killed"])
+    assert sa["tour_count"] == sb["tour_count"]
+    assert np.allclose(sa["accum"], sb["accum"], rtol=1e-5, atol=1e-6)
+    # a second chain set with the same key takes the cached configuration
+    c = dr.Chains(S, 3000, 8, 78, k0=250.0)
+    assert autotune.tune(c, reps=1, per_launch=2)["cfg"] == entry["cfg"]
+    assert c.get_launch() == a.get_launch()

@@ -152,5 +152,6 @@ def test_null_handles_rejected(L):
     assert L.dr_step(None, 1, None) == dr.DR_ERR_INVALID_ARG
     assert L.dr_chains_reinit(None, 0, None) == dr.DR_ERR_INVALID_ARG
     assert L.dr_resolve(None, None, None) == dr.DR_ERR_INVALID_ARG
+    assert L.dr_scene_get_stats(None, None) == dr.DR_ERR_INVALID_ARG
     assert L.dr_chains_destroy(None) == dr.DR_OK
     assert b"null" in L.dr_last_error() or L.dr_last_error() == b""
