@@ -226,17 +226,28 @@ dr_status dr_stats(dr_chains* c, dr_counters* out, void* hip_stream);
  * trace a path's continuation and shadow rays concurrently), and
  * sort_by_length (1: before each launch, order the chains by the number of
  * path vertices of their last step so the chains of a wavefront finish
- * together; 2: off).  Zeros keep the current value.  Defaults: 256 threads,
- * 3 blocks per compute unit, 1 chain per pop, 2 lanes per chain when n_chains
- * is below two wavefronts per SIMD (n_cu * 512) else 1, sorting off (it pays
- * only when chains outnumber the resident lanes several times over).  The
- * order in which chains are processed never changes their results. */
+ * together; 2: off), and refill (1: the ray-refill form of the fused kernel,
+ * one lane per chain, where a lane whose ray query finishes shades and issues
+ * its next ray, or finishes its step and starts the next, while the other
+ * lanes of its wavefront keep traversing; 2: off) with its two thresholds:
+ * a wavefront runs the shading events once refill_event_pct percent of its
+ * lanes with rays wait for one, and the step-finishing code once
+ * refill_advance_pct percent of its busy lanes do (1..100).  grab and
+ * lanes_per_chain do not apply to the refill form.  Zeros keep the current
+ * value.  Defaults: 256 threads, 3 blocks per compute unit, 1 chain per pop,
+ * 2 lanes per chain when n_chains is below two wavefronts per SIMD
+ * (n_cu * 512) else 1, sorting off (it pays only when chains outnumber the
+ * resident lanes several times over), refill off, thresholds 50 and 50.  The
+ * form and the order in which chains are processed never change results. */
 typedef struct {
     uint32_t block;
     uint32_t blocks_per_cu;
     uint32_t grab;
     uint32_t lanes_per_chain;
     uint32_t sort_by_length;
+    uint32_t refill;
+    uint32_t refill_event_pct;
+    uint32_t refill_advance_pct;
 } dr_launch_cfg;
 dr_status dr_chains_set_launch(dr_chains* c, const dr_launch_cfg* cfg);
 dr_status dr_chains_get_launch(dr_chains* c, dr_launch_cfg* cfg);

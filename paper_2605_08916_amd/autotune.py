@@ -1,8 +1,9 @@
 """Launch-configuration autotuner for the fused persistent chain-step kernel.
 
-It sweeps the threads per block, the resident blocks per compute unit of the
-persistent grid, the number of chains a lane takes per queue pop, lanes per
-chain and the path-length ordering of chains, times `dr_step(n)` (n steps per
+It sweeps the kernel form (straight-line or ray-refill), the threads per
+block, the resident blocks per compute unit of the persistent grid, the number
+of chains a lane takes per queue pop, lanes per chain, the path-length
+ordering of chains and the refill thresholds, times `dr_step(n)` (n steps per
 launch, as the caller will issue them) for each candidate with HIP events on
 the launch stream, and
 caches the fastest configuration in a JSON file keyed by device name, path
@@ -23,6 +24,26 @@ BLOCKS_PER_CU = (1, 2, 3, 4, 6, 8)
 GRABS = (1,)
 LANES = (1, 2)
 SORTS = (2, 1)  # path-length ordering off, on
+REFILL_PCTS = ((50, 50),)  # (event, advance) thresholds of the ray-refill form
+
+
+def candidates():
+    """Every launch configuration the sweep times: the straight-line form
+    over block x blocks-per-CU x grab x lanes x ordering, and the ray-refill
+    form (one lane per chain) over block x blocks-per-CU x ordering x
+    thresholds."""
+    out = []
+    for block in BLOCKS:
+        for bpc in BLOCKS_PER_CU:
+            for sort in SORTS:
+                for grab in GRABS:
+                    for lanes in LANES:
+                        out.append(dict(block=block, blocks_per_cu=bpc, grab=grab, lanes_per_chain=lanes,
+                                        sort_by_length=sort, refill=2))
+                for ev, adv in REFILL_PCTS:
+                    out.append(dict(block=block, blocks_per_cu=bpc, sort_by_length=sort, refill=1,
+                                    refill_event_pct=ev, refill_advance_pct=adv))
+    return out
 
 
 def _key(ch: "dr.Chains") -> str:
@@ -63,18 +84,12 @@ def tune(ch: "dr.Chains", reps: int = 3, use_cache: bool = True, verbose: bool =
         return cache[key]
     snap = ch.read_state()
     results = []
-    for block in BLOCKS:
-        for bpc in BLOCKS_PER_CU:
-            for grab in GRABS:
-                for lanes in LANES:
-                    for sort in SORTS:
-                        cfg = dict(block=block, blocks_per_cu=bpc, grab=grab, lanes_per_chain=lanes,
-                                   sort_by_length=sort)
-                        ch.set_launch(**cfg)
-                        ms = _time(ch, reps, per_launch)
-                        results.append((ms, cfg))
-                        if verbose:
-                            print(f"autotune {cfg}: {ms:.3f} ms/step")
+    for cfg in candidates():
+        ch.set_launch(**cfg)
+        ms = _time(ch, reps, per_launch)
+        results.append((ms, cfg))
+        if verbose:
+            print(f"autotune {cfg}: {ms:.3f} ms/step")
     results.sort(key=lambda r: r[0])
     best_ms, best = results[0]
     ch.set_launch(**best)

@@ -18,6 +18,10 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-munsafe-fp-atomics",
+    # fuse multiply-add only within one source expression: the same arithmetic
+    # then compiles to the same operations wherever it is inlined, so the
+    # kernels that evaluate a path in different ways agree bit for bit
+    "-ffp-contract=on",
     # keep private arrays out of LDS: the traversal stack owns the dynamic LDS
     "-mllvm", "-disable-promote-alloca-to-lds",
     # packed FP32 instructions stay off (they are not needed and some forms

@@ -370,6 +370,131 @@ __global__ void __launch_bounds__(256) k_step_fused(KParams P, DevScene S, KBufs
     }
 }
 
+// Path records of the chain in slot c, written as the state machine reaches
+// each vertex.
+template <int L>
+struct StepRec {
+    uint32_t* rec;
+    int N, c;
+    __device__ __forceinline__ void vertex(int j, uint32_t r) const { rec[(size_t)(j - 1) * N + c] = r; }
+    __device__ __forceinline__ void finish(V3, int nv) const {
+        for (int j = nv + 1; j <= L - 1; ++j) rec[(size_t)(j - 1) * N + c] = DR_NO_VERTEX;
+    }
+};
+
+enum { LS_POP = 0, LS_ADVANCE = 1, LS_EVENT = 2, LS_TRACE = 3, LS_DONE = 4 };
+
+// Fused persistent evolve step with ray-level refill: one lane per chain,
+// every chain advances nsteps steps (the same arithmetic and random streams as
+// k_step_fused).  A lane is in one of four states:
+//   POP      out of chains: takes the next one from the work queue;
+//   ADVANCE  finishes its chain's last step (hold/kill, splat, adjoint) and
+//            starts the next (move or regenerate, camera ray);
+//   EVENT    its ray query finished: shade, issue the next ray or end the path;
+//   TRACE    a ray query in flight.
+// Each iteration the wavefront runs one of ADVANCE, EVENT or one node visit
+// of TRACE: ADVANCE once adv_pct percent of the busy lanes wait for it, EVENT
+// once ev_pct percent of the lanes tracing or waiting for an event do, and the
+// traversal otherwise.  So traversal keeps most lanes busy, and the long
+// ADVANCE code runs for many chains at once.
+template <int L>
+__global__ void __launch_bounds__(256) k_step_sm(KParams P, DevScene S, KBufs B, uint32_t nsteps, int sorted,
+                                                 int ev_pct, int adv_pct) {
+    extern __shared__ uint32_t s_stack[];
+    uint32_t* stk = s_stack + threadIdx.x;
+    const int stride = blockDim.x;
+    const int lane = threadIdx.x & 63;
+    const float k0 = *B.k0;
+    const uint64_t s0 = B.steps[1];
+    const Cam C = load_cam(S);
+    Counters ctr = {0, 0, 0};
+    uint32_t kills = 0, steps = 0, adj = 0;
+    RayQ q;
+    PathSM ps;
+    int state = LS_POP;
+    int c = 0, id = 0;
+    uint32_t k = 0;
+    bool has_path = false;  // a finished path waits for its hold/kill, splat and adjoint
+    while (true) {
+        const bool need = state == LS_POP;
+        const uint64_t nm = __ballot(need);
+        if (nm) {
+            const int leader = __ffsll((long long)nm) - 1;
+            uint32_t base = 0;
+            if (lane == leader) base = atomicAdd(B.queue, (uint32_t)__popcll(nm));
+            base = __shfl(base, leader);
+            if (need) {
+                const uint32_t it = base + (uint32_t)__popcll(nm & ((1ull << lane) - 1ull));
+                if (it < (uint32_t)P.N) {
+                    c = (int)it;
+                    id = (int)B.ids[c];
+                    k = 0;
+                    has_path = false;
+                    state = LS_ADVANCE;
+                } else {
+                    state = LS_DONE;
+                }
+            }
+        }
+        const uint64_t mt = __ballot(state == LS_TRACE), me = __ballot(state == LS_EVENT),
+                       ma = __ballot(state == LS_ADVANCE);
+        if (!(mt | me | ma)) break;
+        const int nt = __popcll(mt), ne = __popcll(me), na = __popcll(ma);
+        if (na && (nt + ne == 0 || 100 * na >= adv_pct * (nt + ne + na))) {
+            if (state == LS_ADVANCE) {
+                if (has_path) {
+                    const uint64_t s = s0 + k;
+                    const float p = lum(ps.f);
+                    const uint32_t pix = pixel_of(S, B.x[c], B.x[(size_t)P.N + c]);
+                    const bool alive = hold_kill_splat(P, B, S, c, id, s, k0, ps.f, p, pix);
+                    B.killed[c] = alive ? 0u : 1u;
+                    if (sorted) B.key[c] = alive ? (uint32_t)ps.nv : (uint32_t)(DR_NBIN - 1);
+                    kills += alive ? 0u : 1u;
+                    if (alive) {
+                        score_at<L>(P, B, S, c, p);
+                        ++adj;
+                    }
+                    ++steps;
+                    ++k;
+                    has_path = false;
+                }
+                if (k < nsteps) {
+                    const uint64_t s = s0 + k;
+                    float* xc = B.x + c;
+                    if (B.killed[c]) regen(P.seed, P.d, P.N, xc, id, s);
+                    else
+                        move(P.seed, P.d, P.N, P.stddev, P.gt, xc, B.score + c, B.sigma ? B.sigma + id : nullptr, id,
+                             s);
+                    ps.phase = PH_NEW;
+                    sm_event<L>(S, C, SoaU{xc, P.N}, ps, q, StepRec<L>{B.rec, P.N, c}, ctr);
+                    state = LS_TRACE;
+                } else {
+                    state = LS_POP;
+                }
+            }
+        } else if (ne && (nt == 0 || 100 * ne >= ev_pct * (nt + ne))) {
+            if (state == LS_EVENT) {
+                if (sm_event<L>(S, C, SoaU{B.x + c, P.N}, ps, q, StepRec<L>{B.rec, P.N, c}, ctr)) {
+                    state = LS_TRACE;
+                } else {
+                    state = LS_ADVANCE;
+                    has_path = true;
+                }
+            }
+        } else if (state == LS_TRACE) {
+            if (ray_step(S, q, stk, stride, ctr)) state = LS_EVENT;
+        }
+    }
+    wave_add(&B.ctr[C_TOURS], kills);
+    if (P.count) {
+        wave_add(&B.ctr[C_STEPS], steps);
+        wave_add(&B.ctr[C_ADJ], adj);
+        wave_add(&B.ctr[C_RAYS], ctr.rays);
+        wave_add(&B.ctr[C_NODES], ctr.nodes);
+        wave_add(&B.ctr[C_TRIS], ctr.tris);
+    }
+}
+
 // ---- plain multi-kernel form -------------------------------------------------
 // score = grad ln(p + eps) at the current state of every live chain.
 template <int L>
@@ -657,7 +782,7 @@ struct dr_chains {
     uint64_t seed = 0;
     int n_partials = 0;
     int record = 0, count = 0;
-    dr_launch_cfg launch{256, 2, 1, 2, 0};
+    dr_launch_cfg launch{256, 2, 1, 2, 0, 0, 50, 50};
     int n_cu = 256;
     int rows_move = 0, rows_all = 0;  // state rows moved per sorted launch / restored before host access
     bool permuted = false;            // chains may sit outside the slot of their id
@@ -696,6 +821,11 @@ static void launch_fused(dim3 g, dim3 b, hipStream_t st, const KParams& P, const
                          uint32_t n, uint32_t grab, bool pair, int sorted) {
     if (pair) hipLaunchKernelGGL((k_step_fused<L, true>), g, b, stack_bytes(S, b.x), st, P, S, B, n, grab, sorted);
     else hipLaunchKernelGGL((k_step_fused<L, false>), g, b, stack_bytes(S, b.x), st, P, S, B, n, grab, sorted);
+}
+template <int L>
+static void launch_sm(dim3 g, dim3 b, hipStream_t st, const KParams& P, const DevScene& S, const KBufs& B, uint32_t n,
+                      int sorted, int ev_pct, int adv_pct) {
+    hipLaunchKernelGGL(k_step_sm<L>, g, b, stack_bytes(S, b.x), st, P, S, B, n, sorted, ev_pct, adv_pct);
 }
 template <int L>
 static void launch_plain_score(dim3 g, dim3 b, hipStream_t st, const KParams& P, const DevScene& S, const KBufs& B) {
@@ -756,6 +886,13 @@ static void enqueue_steps(dr_chains* c, uint32_t n_steps, hipStream_t st) {
         }
         hipLaunchKernelGGL(k_begin_launch, dim3(1), dim3(64), 0, st, c->kb, n_steps);
         const int blk = (int)c->launch.block;
+        if (c->launch.refill) {
+            int blocks = (int)(c->n_cu * c->launch.blocks_per_cu);
+            blocks = (int)std::max(1L, std::min((long)blocks, ((long)N + blk - 1) / blk));
+            DR_DISPATCH_L(P.L, launch_sm, dim3(blocks), dim3(blk), st, P, c->scene->ds, c->kb, n_steps, sorted,
+                          (int)c->launch.refill_event_pct, (int)c->launch.refill_advance_pct);
+            return;
+        }
         const bool pair = c->launch.lanes_per_chain == 2;
         const long lanes = (long)N * (pair ? 2 : 1);
         int blocks = (int)(c->n_cu * c->launch.blocks_per_cu);
@@ -1395,11 +1532,17 @@ dr_status dr_chains_set_launch(dr_chains* c, const dr_launch_cfg* cfg) {
     if (cfg->grab > 64) return fail(DR_ERR_INVALID_ARG, "dr_chains_set_launch: grab must be <= 64");
     if (cfg->lanes_per_chain > 2) return fail(DR_ERR_INVALID_ARG, "dr_chains_set_launch: lanes_per_chain must be 1 or 2");
     if (cfg->sort_by_length > 2) return fail(DR_ERR_INVALID_ARG, "dr_chains_set_launch: sort_by_length must be 0, 1 or 2");
+    if (cfg->refill > 2) return fail(DR_ERR_INVALID_ARG, "dr_chains_set_launch: refill must be 0, 1 or 2");
+    if (cfg->refill_event_pct > 100 || cfg->refill_advance_pct > 100)
+        return fail(DR_ERR_INVALID_ARG, "dr_chains_set_launch: refill thresholds are percentages (1..100)");
     if (cfg->block) c->launch.block = cfg->block;
     if (cfg->blocks_per_cu) c->launch.blocks_per_cu = cfg->blocks_per_cu;
     if (cfg->grab) c->launch.grab = cfg->grab;
     if (cfg->lanes_per_chain) c->launch.lanes_per_chain = cfg->lanes_per_chain;
     if (cfg->sort_by_length) c->launch.sort_by_length = cfg->sort_by_length == 1 ? 1u : 0u;
+    if (cfg->refill) c->launch.refill = cfg->refill == 1 ? 1u : 0u;
+    if (cfg->refill_event_pct) c->launch.refill_event_pct = cfg->refill_event_pct;
+    if (cfg->refill_advance_pct) c->launch.refill_advance_pct = cfg->refill_advance_pct;
     g_err.clear();
     return DR_OK;
 }

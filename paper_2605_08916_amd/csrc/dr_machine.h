@@ -66,7 +66,7 @@ enum { PH_NEW = 0, PH_CAM = 1, PH_SHADOW = 2, PH_CONT = 3 };
 
 // Path state of one lane between ray queries.
 struct PathSM {
-    int phase, j, slot, li;
+    int phase, j, slot, li, nv;  // nv: vertices of the finished path
     bool shadow, cont;
     float cx, cy, r2;
     V3 x, d, n, beta, f, wi, wt, wl;
@@ -101,6 +101,7 @@ __device__ __forceinline__ bool sm_after_shadow(const DevScene& S, const U& u, P
         ray_begin(S, q, P.x, P.wi, INFINITY, false, ctr);
         return true;
     }
+    P.nv = j;
     rec.finish(P.f, j);
     P.phase = PH_NEW;
     return false;
@@ -156,6 +157,7 @@ __device__ __forceinline__ bool sm_event(const DevScene& S, const Cam& C, const 
     }
     if (P.phase == PH_CAM) {
         if (q.best < 0) {
+            P.nv = 0;
             rec.finish(P.f, 0);
             P.phase = PH_NEW;
             return false;
@@ -171,6 +173,7 @@ __device__ __forceinline__ bool sm_event(const DevScene& S, const Cam& C, const 
     if (P.phase == PH_SHADOW) return sm_after_shadow<L>(S, u, P, q, q.best >= 0, rec, ctr);
     // PH_CONT
     if (q.best < 0) {
+        P.nv = P.j;
         rec.finish(P.f, P.j);
         P.phase = PH_NEW;
         return false;

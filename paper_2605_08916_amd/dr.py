@@ -93,7 +93,8 @@ class dr_counters(C.Structure):
 
 class dr_launch_cfg(C.Structure):
     _fields_ = [("block", C.c_uint32), ("blocks_per_cu", C.c_uint32), ("grab", C.c_uint32),
-                ("lanes_per_chain", C.c_uint32), ("sort_by_length", C.c_uint32)]
+                ("lanes_per_chain", C.c_uint32), ("sort_by_length", C.c_uint32), ("refill", C.c_uint32),
+                ("refill_event_pct", C.c_uint32), ("refill_advance_pct", C.c_uint32)]
 
 
 _lib = None
@@ -359,16 +360,17 @@ class Chains:
         _check(lib().dr_stats(self.h, C.byref(c), _stream(stream)))
         return {k: getattr(c, k) for k, _ in dr_counters._fields_}
 
-    def set_launch(self, block=0, blocks_per_cu=0, grab=0, lanes_per_chain=0, sort_by_length=0):
-        """Zero keeps a field; sort_by_length: 1 on, 2 off."""
-        cfg = dr_launch_cfg(block, blocks_per_cu, grab, lanes_per_chain, sort_by_length)
+    def set_launch(self, block=0, blocks_per_cu=0, grab=0, lanes_per_chain=0, sort_by_length=0, refill=0,
+                   refill_event_pct=0, refill_advance_pct=0):
+        """Zero keeps a field; sort_by_length and refill: 1 on, 2 off."""
+        cfg = dr_launch_cfg(block, blocks_per_cu, grab, lanes_per_chain, sort_by_length, refill, refill_event_pct,
+                            refill_advance_pct)
         _check(lib().dr_chains_set_launch(self.h, C.byref(cfg)))
 
     def get_launch(self) -> dict:
         cfg = dr_launch_cfg()
         _check(lib().dr_chains_get_launch(self.h, C.byref(cfg)))
-        return dict(block=cfg.block, blocks_per_cu=cfg.blocks_per_cu, grab=cfg.grab, lanes_per_chain=cfg.lanes_per_chain,
-                    sort_by_length=cfg.sort_by_length)
+        return {k: getattr(cfg, k) for k, _ in dr_launch_cfg._fields_}
 
     def read_state(self, stream=None) -> dict:
         N, d, V = self.N, self.d, self.L - 1

@@ -463,6 +463,31 @@ def test_length_ordering_matches_identity_order(scenes, lanes):
     assert np.allclose(a["accum"], b["accum"], rtol=1e-5, atol=1e-6)
 
 
+@pytest.mark.parametrize("which,L,N", [("tiny", 4, 1500), ("spheres_small", 8, 5000)])
+def test_refill_form_matches_straight_line(scenes, which, L, N):
+    """The ray-refill form of the fused kernel (lanes refill with their next
+    ray or step while others traverse) gives exactly the chains of the
+    straight-line form, over several launches and with path-length ordering."""
+    say(f"[refill vs straight] scene={which} L={L} N={N}")
+    S = dr.Scene(scenes[which])
+    out = []
+    for refill, sort in ((2, 2), (1, 2), (1, 1)):
+        ch = dr.Chains(S, N, L, 91, k0=250.0)
+        ch.set_launch(refill=refill, sort_by_length=sort, lanes_per_chain=1)
+        assert ch.get_launch()["refill"] == (1 if refill == 1 else 0)
+        ch.step(1)
+        ch.step(5)
+        ch.step(3)
+        out.append(ch.read_state())
+    a = out[0]
+    for b in out[1:]:
+        assert np.array_equal(a["x"], b["x"]) and np.array_equal(a["killed"], b["killed"])
+        assert np.array_equal(a["score"][:, a["killed"] == 0], b["score"][:, b["killed"] == 0])
+        assert np.array_equal(a["path_rec"], b["path_rec"])
+        assert a["tour_count"] == b["tour_count"]
+        assert np.allclose(a["accum"], b["accum"], rtol=1e-5, atol=1e-6)
+
+
 def test_captured_frames_replay_like_eager(scenes):
     """A captured frame (re-init + n steps + resolve) replayed several times,
     with a camera change between replays and eager work in between, gives the
@@ -571,9 +596,12 @@ def test_autotune_restores_chains(scenes, tmp_path, monkeypatch):
     a.step(2)
     b.step(2)
     entry = autotune.tune(a, reps=1, use_cache=True, per_launch=2)
-    applied = dict(entry["cfg"], sort_by_length=1 if entry["cfg"]["sort_by_length"] == 1 else 0)
-    assert a.get_launch() == applied
-    assert len(entry["sweep"]) == 2 * 2 * len(autotune.GRABS) * len(autotune.LANES) * len(autotune.SORTS)
+    flags = ("sort_by_length", "refill")  # 1 on, 2 off in a request; 1/0 when read back
+    applied = {k: (int(v == 1) if k in flags else v) for k, v in entry["cfg"].items()}
+    got = a.get_launch()
+    assert {k: got[k] for k in applied} == applied
+    assert len(entry["sweep"]) == len(autotune.candidates()) == 2 * 2 * 2 * (
+        len(autotune.GRABS) * len(autotune.LANES) + len(autotune.REFILL_PCTS))
     a.step(3)
     b.step(3)
     sa, sb = a.read_state(), b.read_state()
