@@ -281,7 +281,11 @@ dr_status dr_frame_destroy(dr_frame* f);
  * log(p + eps) (n) and, if grad_dev is non-NULL, the score grad_u log(p + eps)
  * (n x d) by the reverse-mode adjoint over the taken path (discrete choices
  * held fixed).  rec_dev (n x (L-1), nullable) receives the path record as in
- * dr_state.path_rec.  Asynchronous. */
+ * dr_state.path_rec.  f_dev and logp_dev are nullable too.  Without grad_dev
+ * the points are evaluated by the ray-refill form (lanes take the next point
+ * or ray as theirs finish), with results bit-identical to the form that also
+ * computes the score.  Allocates a scratch buffer of 4(L-1)n bytes from the
+ * stream-ordered pool.  Asynchronous. */
 dr_status dr_eval_logp_grad(dr_scene* s, uint32_t L, const float* u_dev, uint32_t n, float eps, float* f_dev,
                             float* logp_dev, float* grad_dev, uint32_t* rec_dev, void* hip_stream);
 

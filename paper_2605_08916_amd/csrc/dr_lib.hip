@@ -1565,9 +1565,19 @@ dr_status dr_eval_logp_grad(dr_scene* s, uint32_t L, const float* u_dev, uint32_
     hipStream_t st = (hipStream_t)hip_stream;
     void* rs = nullptr;
     HIP_TRY(hipMallocAsync(&rs, sizeof(uint32_t) * (L - 1) * (size_t)n, st));
-    const int blk = 128;
-    DR_DISPATCH_L((int)L, launch_eval, dim3((n + blk - 1) / blk), dim3(blk), st, s->ds, u_dev, (int)n, eps, f_dev,
-                  logp_dev, grad_dev, (uint32_t*)rs, rec_dev);
+    if (!grad_dev) {
+        // forward only: the ray-refill evaluator, persistent, points taken
+        // from a counter in the scratch buffer
+        const int blk = 256;
+        const int blocks = (int)std::min<long>((long)g_num_cu(s->device) * 4, ((long)n + blk - 1) / blk);
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t*)rs, (size_t)1, 0u);
+        DR_DISPATCH_L((int)L, launch_eval_sm, dim3(blocks), dim3(blk), st, s->ds, u_dev, (int)n, eps, f_dev,
+                      logp_dev, rec_dev, (uint32_t*)rs, 50);
+    } else {
+        const int blk = 128;
+        DR_DISPATCH_L((int)L, launch_eval, dim3((n + blk - 1) / blk), dim3(blk), st, s->ds, u_dev, (int)n, eps, f_dev,
+                      logp_dev, grad_dev, (uint32_t*)rs, rec_dev);
+    }
     hipError_t e = hipGetLastError();
     (void)hipFreeAsync(rs, st);
     if (e != hipSuccess) return fail(DR_ERR_DEVICE, std::string("dr_eval_logp_grad: ") + hipGetErrorString(e));

@@ -105,6 +105,21 @@ def test_eval_matches_oracle(orc, scenes, which, L, n):
     assert np.all(g[zero] == 0)
 
 
+@pytest.mark.parametrize("which,L,n", [("tiny", 4, 3000), ("spheres_small", 8, 20000)])
+def test_forward_only_eval_matches_eval_with_score(scenes, which, L, n):
+    """Forward-only evaluation (the ray-refill evaluator) returns exactly the
+    f, log p and path records of the evaluation that also runs the adjoint."""
+    say(f"[eval forward-only vs with score] scene={which} L={L} n={n}")
+    S = dr.Scene(scenes[which])
+    g = torch.Generator().manual_seed(5)
+    u = torch.rand((n, 4 * (L - 1)), generator=g).cuda()
+    f0, lp0, _, r0 = S.eval_logp_grad(L, u, grad=False, rec=True)
+    f1, lp1, g1, r1 = S.eval_logp_grad(L, u, grad=True, rec=True)
+    torch.cuda.synchronize()
+    assert torch.equal(f0, f1) and torch.equal(lp0, lp1) and torch.equal(r0, r1)
+    assert torch.isfinite(g1).all()
+
+
 def test_autograd_matches_finite_differences_and_oracle(orc, scenes):
     from paper_2605_08916_amd.autograd import LogContribution
     sc = scenes["spheres_small"]
