@@ -92,6 +92,7 @@ struct DevScene {
     float tmin;
     int W, H;
     int stack_cap;  // traversal stack entries per lane (the tree's exact worst case, <= DR_STACK)
+    int n_tris;
 };
 struct Cam {
     V3 eye, cu, cv, cw;
@@ -130,12 +131,13 @@ __device__ __forceinline__ bool slab(float lx, float ly, float lz, float hx, flo
 }
 
 // Moller-Trumbore, two-sided; t in (tmin, inf) before the caller's range test.
+// The reciprocal of the determinant is the hardware one (1 ulp).
 __device__ __forceinline__ bool tri_test(const DevTri& T, V3 o, V3 d, float tmin, float& t) {
     const V3 e1 = xyz(T.e1), e2 = xyz(T.e2);
     const V3 pv = cross(d, e2);
     const float det = dot(e1, pv);
     if (det == 0.0f) return false;
-    const float inv = 1.0f / det;
+    const float inv = __builtin_amdgcn_rcpf(det);
     const V3 tv = o - xyz(T.v0);
     const float b1 = dot(tv, pv) * inv;
     if (b1 < 0.0f || b1 > 1.0f) return false;
@@ -162,6 +164,12 @@ __device__ __forceinline__ DevNode load_node(const DevNode* nodes, int i) {
 
 __device__ __forceinline__ float f4(const float4& v, int q) { return q == 0 ? v.x : (q == 1 ? v.y : (q == 2 ? v.z : v.w)); }
 __device__ __forceinline__ int i4(const int4& v, int q) { return q == 0 ? v.x : (q == 1 ? v.y : (q == 2 ? v.z : v.w)); }
+// Component q of v for a run-time q, as a two-level select (no branches).
+__device__ __forceinline__ int sel4(const int4& v, int q) {
+    const int lo = (q & 1) ? v.y : v.x;
+    const int hi = (q & 1) ? v.w : v.z;
+    return (q & 2) ? hi : lo;
+}
 
 // One node visit of a ray query: tests the node's four child boxes, tests the
 // triangles of every hit leaf child (the lanes of a wavefront loop over their
@@ -173,26 +181,29 @@ __device__ __forceinline__ bool visit_node(const DevScene& S, int node, V3 o, V3
                                            float& bt, int& best, uint32_t& best_prim, int (&kc)[4], Counters& ctr) {
     const DevNode n = load_node(S.nodes, node);
     ctr.nodes++;
+    // all four boxes are tested without branching (an empty slot's result is
+    // masked afterwards), so the node's eight loads issue together
     float tn[4];
     bool hit[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
-        hit[q] = i4(n.count, q) >= 0 && slab(f4(n.lox, q), f4(n.loy, q), f4(n.loz, q), f4(n.hix, q), f4(n.hiy, q),
-                                              f4(n.hiz, q), o, inv, S.tmin, bt, tn[q]);
+        hit[q] = slab(f4(n.lox, q), f4(n.loy, q), f4(n.loz, q), f4(n.hix, q), f4(n.hiy, q), f4(n.hiz, q), o, inv,
+                      S.tmin, bt, tn[q]) &
+                 (i4(n.count, q) >= 0);
     uint32_t leaves = 0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-        if (hit[q] && i4(n.count, q) > 0) leaves |= 1u << q;
+    for (int q = 0; q < 4; ++q) leaves |= (hit[q] & (i4(n.count, q) > 0)) ? 1u << q : 0u;
     while (leaves) {
         const int q = __ffs(leaves) - 1;
         leaves &= leaves - 1u;
-        const int cnt = i4(n.count, q);
-        const int first = i4(n.child, q);
+        const int cnt = sel4(n.count, q);
+        const int first = sel4(n.child, q);
         for (int k0 = first; k0 < first + cnt; k0 += 4) {
+            // four triangles' loads in flight at once; slots past the leaf
+            // (clamped to the array) are loaded but not tested
             DevTri T[4];
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
-                if (k0 + e < first + cnt) T[e] = S.tris[k0 + e];
+            for (int e = 0; e < 4; ++e) T[e] = S.tris[min(k0 + e, S.n_tris - 1)];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 if (k0 + e >= first + cnt) break;

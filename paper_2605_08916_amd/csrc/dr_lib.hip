@@ -1225,6 +1225,7 @@ dr_status dr_scene_create(const dr_scene_desc* desc, int device, dr_scene** out)
     S->ds.mats = (const float4*)dmats;
     S->ds.lights = (const float4*)dlights;
     S->ds.n_lights = (int)desc->n_lights;
+    S->ds.n_tris = (int)T;
     S->ds.tmin = (float)(1e-4 * diag);
     S->ds.cam = (const float4*)dcam;
     S->ds.W = (int)desc->camera.width;
