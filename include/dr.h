@@ -233,11 +233,16 @@ dr_status dr_stats(dr_chains* c, dr_counters* out, void* hip_stream);
  * a wavefront runs the shading events once refill_event_pct percent of its
  * lanes with rays wait for one, and the step-finishing code once
  * refill_advance_pct percent of its busy lanes do (1..100).  grab and
- * lanes_per_chain do not apply to the refill form.  Zeros keep the current
+ * lanes_per_chain do not apply to the refill form.  sort_by_tile (1: before
+ * each launch, order the chains by the screen tile of their film coordinates,
+ * 64 x 64 tiles in Morton order, killed chains last, so a wavefront's camera
+ * rays and the shadow rays from their hits are coherent; takes precedence
+ * over sort_by_length; 2: off).  Zeros keep the current
  * value.  Defaults: 256 threads, 3 blocks per compute unit, 1 chain per pop,
  * 2 lanes per chain when n_chains is below two wavefronts per SIMD
  * (n_cu * 512) else 1, sorting off (it pays only when chains outnumber the
- * resident lanes several times over), refill off, thresholds 50 and 50.  The
+ * resident lanes several times over), refill off, thresholds 50 and 50,
+ * tile ordering off.  The
  * form and the order in which chains are processed never change results. */
 typedef struct {
     uint32_t block;
@@ -248,6 +253,7 @@ typedef struct {
     uint32_t refill;
     uint32_t refill_event_pct;
     uint32_t refill_advance_pct;
+    uint32_t sort_by_tile;
 } dr_launch_cfg;
 dr_status dr_chains_set_launch(dr_chains* c, const dr_launch_cfg* cfg);
 dr_status dr_chains_get_launch(dr_chains* c, dr_launch_cfg* cfg);

@@ -2,11 +2,10 @@
 
 It sweeps the kernel form (straight-line or ray-refill), the threads per
 block, the resident blocks per compute unit of the persistent grid, the number
-of chains a lane takes per queue pop, lanes per chain, the path-length
-ordering of chains and the refill thresholds, times `dr_step(n)` (n steps per
-launch, as the caller will issue them) for each candidate with HIP events on
-the launch stream, and
-caches the fastest configuration in a JSON file keyed by device name, path
+of chains a lane takes per queue pop, lanes per chain, the ordering of chains
+(none, by path length, by screen tile) and the refill thresholds, times
+`dr_step(n)` (n steps per launch, as the caller will issue them) for each
+candidate with HIP events on the launch stream, and caches the fastest configuration in a JSON file keyed by device name, path
 length, chain count and triangle count.  The chain state is saved before and
 restored after the sweep, so tuning does not advance the chains.
 """
@@ -23,7 +22,8 @@ BLOCKS = (64, 128, 256)
 BLOCKS_PER_CU = (1, 2, 3, 4, 6, 8)
 GRABS = (1,)
 LANES = (1, 2)
-SORTS = (2, 1)  # path-length ordering off, on
+# chain ordering before a launch: (sort_by_length, sort_by_tile), 1 on, 2 off
+ORDERS = ((2, 2), (1, 2), (2, 1))
 REFILL_PCTS = ((50, 50),)  # (event, advance) thresholds of the ray-refill form
 
 
@@ -35,14 +35,14 @@ def candidates():
     out = []
     for block in BLOCKS:
         for bpc in BLOCKS_PER_CU:
-            for sort in SORTS:
+            for by_len, by_tile in ORDERS:
                 for grab in GRABS:
                     for lanes in LANES:
                         out.append(dict(block=block, blocks_per_cu=bpc, grab=grab, lanes_per_chain=lanes,
-                                        sort_by_length=sort, refill=2))
+                                        sort_by_length=by_len, sort_by_tile=by_tile, refill=2))
                 for ev, adv in REFILL_PCTS:
-                    out.append(dict(block=block, blocks_per_cu=bpc, sort_by_length=sort, refill=1,
-                                    refill_event_pct=ev, refill_advance_pct=adv))
+                    out.append(dict(block=block, blocks_per_cu=bpc, sort_by_length=by_len, sort_by_tile=by_tile,
+                                    refill=1, refill_event_pct=ev, refill_advance_pct=adv))
     return out
 
 

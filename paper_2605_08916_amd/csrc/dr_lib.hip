@@ -235,40 +235,72 @@ __global__ void __launch_bounds__(256) k_init_accumulate(KParams P, DevScene S, 
     }
 }
 
-// ---- grouping chains by their last path length (a counting sort over
-// DR_NBIN keys, block-aggregated so each block issues one global atomic per
-// key).  bins[0..15] counts, bins[16..31] running positions.
-__global__ void __launch_bounds__(256) k_sort_hist(const uint32_t* key, int N, uint32_t* bins) {
-    __shared__ uint32_t h[DR_NBIN];
-    if (threadIdx.x < DR_NBIN) h[threadIdx.x] = 0;
+// ---- grouping chains before a fused launch: a counting sort over nbins keys,
+// block-aggregated (one global atomic per block and key).  Keys: the last
+// path length (DR_NBIN keys: 0..7 vertices, killed), or the screen tile of
+// the chain's film coordinates (64 x 64 tiles in Morton order, then killed
+// chains: DR_TILE_BINS keys).  bins[0..nbins) counts, bins[nbins..2 nbins)
+// running offsets.
+#define DR_TILE_BINS 4097
+__device__ __forceinline__ uint32_t order_key(const KBufs& B, int N, int c, int by_tile, int nbins) {
+    if (!by_tile) return min(B.key[c], (uint32_t)(nbins - 1));
+    if (B.killed[c]) return DR_TILE_BINS - 1;
+    const uint32_t tx = min((uint32_t)(B.x[c] * 64.0f), 63u), ty = min((uint32_t)(B.x[(size_t)N + c] * 64.0f), 63u);
+    uint32_t m = 0;
+#pragma unroll
+    for (int b = 0; b < 6; ++b) m |= (((tx >> b) & 1u) << (2 * b)) | (((ty >> b) & 1u) << (2 * b + 1));
+    return m;
+}
+__global__ void __launch_bounds__(256) k_sort_hist(KBufs B, int N, int by_tile, int nbins) {
+    __shared__ uint32_t h[DR_TILE_BINS];
+    for (int b = threadIdx.x; b < nbins; b += blockDim.x) h[b] = 0;
     __syncthreads();
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < N) atomicAdd(&h[min(key[c], (uint32_t)(DR_NBIN - 1))], 1u);
+    if (c < N) atomicAdd(&h[order_key(B, N, c, by_tile, nbins)], 1u);
     __syncthreads();
-    if (threadIdx.x < DR_NBIN && h[threadIdx.x]) atomicAdd(&bins[threadIdx.x], h[threadIdx.x]);
+    for (int b = threadIdx.x; b < nbins; b += blockDim.x)
+        if (h[b]) atomicAdd(&B.bins[b], h[b]);
 }
-__global__ void k_sort_prefix(uint32_t* bins) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    uint32_t run = 0;
-    for (int b = 0; b < DR_NBIN; ++b) {
-        bins[16 + b] = run;
+// Exclusive prefix of the counts (one block of 256 threads: a chunk of bins
+// per thread, a sequential pass over the 256 chunk sums).
+__global__ void __launch_bounds__(256) k_sort_prefix(uint32_t* bins, int nbins) {
+    __shared__ uint32_t part[256];
+    const int per = (nbins + 255) / 256;
+    const int b0 = threadIdx.x * per, b1 = min(b0 + per, nbins);
+    uint32_t sum = 0;
+    for (int b = b0; b < b1; ++b) sum += bins[b];
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int t = 0; t < 256; ++t) {
+            const uint32_t v = part[t];
+            part[t] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    uint32_t run = part[threadIdx.x];
+    for (int b = b0; b < b1; ++b) {
+        bins[nbins + b] = run;
         run += bins[b];
     }
 }
-__global__ void __launch_bounds__(256) k_sort_scatter(const uint32_t* key, int N, uint32_t* bins, uint32_t* order) {
-    __shared__ uint32_t h[DR_NBIN], base[DR_NBIN];
-    if (threadIdx.x < DR_NBIN) h[threadIdx.x] = 0;
+__global__ void __launch_bounds__(256) k_sort_scatter(KBufs B, int N, int by_tile, int nbins) {
+    __shared__ uint32_t h[DR_TILE_BINS], base[DR_TILE_BINS];
+    for (int b = threadIdx.x; b < nbins; b += blockDim.x) h[b] = 0;
     __syncthreads();
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t k = 0, r = 0;
     if (c < N) {
-        k = min(key[c], (uint32_t)(DR_NBIN - 1));
+        k = order_key(B, N, c, by_tile, nbins);
         r = atomicAdd(&h[k], 1u);
     }
     __syncthreads();
-    if (threadIdx.x < DR_NBIN && h[threadIdx.x]) base[threadIdx.x] = atomicAdd(&bins[16 + threadIdx.x], h[threadIdx.x]);
+    for (int b = threadIdx.x; b < nbins; b += blockDim.x)
+        if (h[b]) base[b] = atomicAdd(&B.bins[nbins + b], h[b]);
     __syncthreads();
-    if (c < N) order[base[k] + r] = (uint32_t)c;
+    if (c < N) B.order[base[k] + r] = (uint32_t)c;
 }
 // alt[row][q] = state[row][order[q]]: chains move to the slots the sort gave them
 __global__ void __launch_bounds__(256) k_slots_gather(const uint32_t* state, uint32_t* alt, const uint32_t* order,
@@ -782,7 +814,7 @@ struct dr_chains {
     uint64_t seed = 0;
     int n_partials = 0;
     int record = 0, count = 0;
-    dr_launch_cfg launch{256, 2, 1, 2, 0, 0, 50, 50};
+    dr_launch_cfg launch{256, 2, 1, 2, 0, 0, 50, 50, 0};
     int n_cu = 256;
     int rows_move = 0, rows_all = 0;  // state rows moved per sorted launch / restored before host access
     bool permuted = false;            // chains may sit outside the slot of their id
@@ -871,13 +903,15 @@ static void enqueue_steps(dr_chains* c, uint32_t n_steps, hipStream_t st) {
     P.count = c->count;
     const int N = P.N;
     if (c->P.mode == DR_MODE_FUSED) {
-        const int sorted = c->launch.sort_by_length ? 1 : 0;
-        if (sorted) {
+        const int by_tile = c->launch.sort_by_tile ? 1 : 0;
+        const int sorted = c->launch.sort_by_length && !by_tile ? 1 : 0;  // the kernels record length keys
+        if (by_tile || sorted) {
+            const int nb = by_tile ? DR_TILE_BINS : DR_NBIN;
             const dim3 gs((N + 255) / 256), bs(256);
-            hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, c->kb.bins, (size_t)32, 0u);
-            hipLaunchKernelGGL(k_sort_hist, gs, bs, 0, st, c->kb.key, N, c->kb.bins);
-            hipLaunchKernelGGL(k_sort_prefix, dim3(1), dim3(64), 0, st, c->kb.bins);
-            hipLaunchKernelGGL(k_sort_scatter, gs, bs, 0, st, c->kb.key, N, c->kb.bins, c->kb.order);
+            hipLaunchKernelGGL(k_fill_u32, dim3(16), dim3(256), 0, st, c->kb.bins, (size_t)(2 * nb), 0u);
+            hipLaunchKernelGGL(k_sort_hist, gs, bs, 0, st, c->kb, N, by_tile, nb);
+            hipLaunchKernelGGL(k_sort_prefix, dim3(1), bs, 0, st, c->kb.bins, nb);
+            hipLaunchKernelGGL(k_sort_scatter, gs, bs, 0, st, c->kb, N, by_tile, nb);
             hipLaunchKernelGGL(k_slots_gather, dim3(gs.x, c->rows_move), bs, 0, st, c->kb.state, c->kb.alt,
                                c->kb.order, N);
             hipLaunchKernelGGL(k_copy_u32, dim3(2048), bs, 0, st, c->kb.alt, c->kb.state,
@@ -1333,7 +1367,7 @@ dr_status dr_chains_init(dr_scene* s, const dr_params* p, uint64_t seed, uint32_
     get(&q, 64); B.steps = (unsigned long long*)q;
     get(&q, sizeof(uint32_t) * N); B.key = (uint32_t*)q;
     get(&q, sizeof(uint32_t) * N); B.order = (uint32_t*)q;
-    get(&q, sizeof(uint32_t) * 32); B.bins = (uint32_t*)q;
+    get(&q, sizeof(uint32_t) * 2 * DR_TILE_BINS); B.bins = (uint32_t*)q;
     B.sigma = p->sigma_diag;
     if (!ok) {
         c->mem.release();
@@ -1534,6 +1568,7 @@ dr_status dr_chains_set_launch(dr_chains* c, const dr_launch_cfg* cfg) {
     if (cfg->lanes_per_chain > 2) return fail(DR_ERR_INVALID_ARG, "dr_chains_set_launch: lanes_per_chain must be 1 or 2");
     if (cfg->sort_by_length > 2) return fail(DR_ERR_INVALID_ARG, "dr_chains_set_launch: sort_by_length must be 0, 1 or 2");
     if (cfg->refill > 2) return fail(DR_ERR_INVALID_ARG, "dr_chains_set_launch: refill must be 0, 1 or 2");
+    if (cfg->sort_by_tile > 2) return fail(DR_ERR_INVALID_ARG, "dr_chains_set_launch: sort_by_tile must be 0, 1 or 2");
     if (cfg->refill_event_pct > 100 || cfg->refill_advance_pct > 100)
         return fail(DR_ERR_INVALID_ARG, "dr_chains_set_launch: refill thresholds are percentages (1..100)");
     if (cfg->block) c->launch.block = cfg->block;
@@ -1542,6 +1577,7 @@ dr_status dr_chains_set_launch(dr_chains* c, const dr_launch_cfg* cfg) {
     if (cfg->lanes_per_chain) c->launch.lanes_per_chain = cfg->lanes_per_chain;
     if (cfg->sort_by_length) c->launch.sort_by_length = cfg->sort_by_length == 1 ? 1u : 0u;
     if (cfg->refill) c->launch.refill = cfg->refill == 1 ? 1u : 0u;
+    if (cfg->sort_by_tile) c->launch.sort_by_tile = cfg->sort_by_tile == 1 ? 1u : 0u;
     if (cfg->refill_event_pct) c->launch.refill_event_pct = cfg->refill_event_pct;
     if (cfg->refill_advance_pct) c->launch.refill_advance_pct = cfg->refill_advance_pct;
     g_err.clear();

@@ -453,19 +453,21 @@ def test_paired_lanes_match_single_lane(scenes, which, L, N):
     assert np.allclose(a["accum"], b["accum"], rtol=1e-5, atol=1e-6)
 
 
-@pytest.mark.parametrize("lanes", [1, 2])
-def test_length_ordering_matches_identity_order(scenes, lanes):
-    """Processing chains grouped by their last path length (a counting sort
-    before each launch) gives exactly the chains of the identity order; only
-    the order of the splat additions differs."""
+@pytest.mark.parametrize("lanes,order", [(1, "length"), (2, "length"), (1, "tile"), (2, "tile")])
+def test_length_ordering_matches_identity_order(scenes, lanes, order):
+    """Processing chains grouped by their last path length, or by the screen
+    tile of their film coordinates (a counting sort and a move of the state
+    rows before each launch), gives exactly the chains of the identity order;
+    only the order of the splat additions differs."""
     N, L = 5000, 8
-    say(f"[sorted vs identity] scene=spheres_small L={L} N={N} lanes={lanes}")
+    say(f"[sorted vs identity] scene=spheres_small L={L} N={N} lanes={lanes} order={order}")
     S = dr.Scene(scenes["spheres_small"])
     out = []
     for sort in (2, 1):
         ch = dr.Chains(S, N, L, 57, k0=250.0)
-        ch.set_launch(lanes_per_chain=lanes, sort_by_length=sort)
-        assert ch.get_launch()["sort_by_length"] == (1 if sort == 1 else 0)
+        key = "sort_by_length" if order == "length" else "sort_by_tile"
+        ch.set_launch(lanes_per_chain=lanes, **{key: sort})
+        assert ch.get_launch()[key] == (1 if sort == 1 else 0)
         for _ in range(3):
             ch.step(1)
         ch.step(4)
@@ -611,11 +613,11 @@ def test_autotune_restores_chains(scenes, tmp_path, monkeypatch):
     a.step(2)
     b.step(2)
     entry = autotune.tune(a, reps=1, use_cache=True, per_launch=2)
-    flags = ("sort_by_length", "refill")  # 1 on, 2 off in a request; 1/0 when read back
+    flags = ("sort_by_length", "sort_by_tile", "refill")  # 1 on, 2 off in a request; 1/0 when read back
     applied = {k: (int(v == 1) if k in flags else v) for k, v in entry["cfg"].items()}
     got = a.get_launch()
     assert {k: got[k] for k in applied} == applied
-    assert len(entry["sweep"]) == len(autotune.candidates()) == 2 * 2 * 2 * (
+    assert len(entry["sweep"]) == len(autotune.candidates()) == 2 * 2 * len(autotune.ORDERS) * (
         len(autotune.GRABS) * len(autotune.LANES) + len(autotune.REFILL_PCTS))
     a.step(3)
     b.step(3)
