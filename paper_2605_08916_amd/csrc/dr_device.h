@@ -411,6 +411,11 @@ __device__ __forceinline__ uint32_t pixel_of(const DevScene& S, float u0, float 
 // odd lane the shadow ray, concurrently, and they swap the results with a
 // lane shuffle.  Without PAIR one lane traces both rays in turn.
 // ---------------------------------------------------------------------------
+// Value held by the adjacent lane (lane ^ 1): a DPP quad permutation
+// [1,0,3,2], read straight from the partner's register.
+__device__ __forceinline__ int swap_pair(int v) { return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false); }
+__device__ __forceinline__ float swap_pair(float v) { return __int_as_float(swap_pair(__float_as_int(v))); }
+
 template <bool PAIR>
 __device__ __forceinline__ void trace_vertex_rays(const DevScene& S, V3 x, bool shadow, V3 wl, float smax, bool cont,
                                                   V3 wi, bool& occluded, int& nslot, float& tn, uint32_t* stk,
@@ -420,8 +425,8 @@ __device__ __forceinline__ void trace_vertex_rays(const DevScene& S, V3 x, bool 
         float tt;
         const int r = trace(S, x, odd ? wl : wi, odd ? (shadow ? smax : -1.0f) : (cont ? INFINITY : -1.0f), odd, tt,
                             stk, stride, ctr);
-        const int ro = __shfl_xor(r, 1);
-        const float to = __shfl_xor(tt, 1);
+        const int ro = swap_pair(r);
+        const float to = swap_pair(tt);
         occluded = shadow && (odd ? r : ro) >= 0;
         nslot = cont ? (odd ? ro : r) : -1;
         tn = odd ? to : tt;
@@ -443,8 +448,8 @@ __device__ V3 path_forward(const DevScene& S, int L, const U& u, uint32_t* rec, 
     if (PAIR) {
         const bool odd = (threadIdx.x & 1) != 0;
         const int r = trace(S, C.eye, d, odd ? -1.0f : INFINITY, false, t, stk, stride, ctr);
-        slot = __shfl_xor(r, 1);
-        const float to = __shfl_xor(t, 1);
+        slot = swap_pair(r);
+        const float to = swap_pair(t);
         if (!odd) slot = r;
         else t = to;
     } else {

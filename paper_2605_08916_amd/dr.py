@@ -174,7 +174,7 @@ def dr_version() -> str:
     return lib().dr_version().decode()
 
 
-def dr_bvh_build(vertices: np.ndarray, indices: np.ndarray, max_leaf: int = 4):
+def dr_bvh_build(vertices: np.ndarray, indices: np.ndarray, max_leaf: int = 2):
     V = np.ascontiguousarray(vertices, np.float32).reshape(-1, 3)
     I = np.ascontiguousarray(indices, np.uint32).reshape(-1, 3)
     T = I.shape[0]
@@ -241,7 +241,7 @@ def dr_scene_create(sc: dict, device: int = 0, bvh=None):
 
 
 class Scene:
-    def __init__(self, sc: dict, device: int = 0, bvh=None, max_leaf: int = 4):
+    def __init__(self, sc: dict, device: int = 0, bvh=None, max_leaf: int = 2):
         if bvh is None:
             bvh = dr_bvh_build(sc["vertices"], sc["indices"], max_leaf)
         self.sc = sc

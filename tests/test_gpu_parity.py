@@ -484,13 +484,14 @@ def test_length_ordering_matches_identity_order(scenes, lanes, order):
 def test_refill_form_matches_straight_line(scenes, which, L, N):
     """The ray-refill form of the fused kernel (lanes refill with their next
     ray or step while others traverse) gives exactly the chains of the
-    straight-line form, over several launches and with path-length ordering."""
+    straight-line forms (one and two lanes per chain), over several launches
+    and with path-length ordering."""
     say(f"[refill vs straight] scene={which} L={L} N={N}")
     S = dr.Scene(scenes[which])
     out = []
-    for refill, sort in ((2, 2), (1, 2), (1, 1)):
+    for refill, sort, lanes in ((2, 2, 1), (1, 2, 1), (1, 1, 1), (2, 2, 2)):
         ch = dr.Chains(S, N, L, 91, k0=250.0)
-        ch.set_launch(refill=refill, sort_by_length=sort, lanes_per_chain=1)
+        ch.set_launch(refill=refill, sort_by_length=sort, lanes_per_chain=lanes)
         assert ch.get_launch()["refill"] == (1 if refill == 1 else 0)
         ch.step(1)
         ch.step(5)
