@@ -91,8 +91,9 @@ struct DevScene {
     int n_lights;
     float tmin;
     int W, H;
-    int stack_cap;  // traversal stack entries per lane (the tree's exact worst case, <= DR_STACK)
+    int stack_cap;   // traversal stack entries per lane (the tree's exact worst case, <= DR_STACK)
     int n_tris;
+    int leaf_batch;  // triangles fetched together per leaf iteration: 2 if no leaf holds more, else 4
 };
 struct Cam {
     V3 eye, cu, cv, cw;
@@ -171,6 +172,46 @@ __device__ __forceinline__ int sel4(const int4& v, int q) {
     return (q & 2) ? hi : lo;
 }
 
+// Triangle tests of the hit leaf children in `leaves` (the lanes of a
+// wavefront loop over their own hit leaves, lowest child first), BATCH
+// triangles' loads in flight at once; slots past a leaf (clamped to the
+// array) are loaded but not tested.  Returns true when an any-hit query has
+// found its hit.
+template <int BATCH>
+__device__ __forceinline__ bool leaf_tests(const DevScene& S, const DevNode& n, uint32_t leaves, V3 o, V3 d, float tmax,
+                                           bool anyhit, float& bt, int& best, uint32_t& best_prim, Counters& ctr) {
+    while (leaves) {
+        const int q = __ffs(leaves) - 1;
+        leaves &= leaves - 1u;
+        const int cnt = sel4(n.count, q);
+        const int first = sel4(n.child, q);
+        for (int k0 = first; k0 < first + cnt; k0 += BATCH) {
+            DevTri T[BATCH];
+#pragma unroll
+            for (int e = 0; e < BATCH; ++e) T[e] = S.tris[min(k0 + e, S.n_tris - 1)];
+#pragma unroll
+            for (int e = 0; e < BATCH; ++e) {
+                if (k0 + e >= first + cnt) break;
+                ctr.tris++;
+                float t;
+                if (tri_test(T[e], o, d, S.tmin, t) && t <= bt) {
+                    const uint32_t prim = __float_as_uint(T[e].v0.w);
+                    if (anyhit && t < tmax) {
+                        best = k0 + e;
+                        return true;
+                    }
+                    if (t < bt || (t == bt && prim < best_prim)) {
+                        bt = t;
+                        best = k0 + e;
+                        best_prim = prim;
+                    }
+                }
+            }
+        }
+    }
+    return false;
+}
+
 // One node visit of a ray query: tests the node's four child boxes, tests the
 // triangles of every hit leaf child (the lanes of a wavefront loop over their
 // own hit leaves, lowest child first, four triangles' loads in flight at
@@ -193,36 +234,12 @@ __device__ __forceinline__ bool visit_node(const DevScene& S, int node, V3 o, V3
     uint32_t leaves = 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) leaves |= (hit[q] & (i4(n.count, q) > 0)) ? 1u << q : 0u;
-    while (leaves) {
-        const int q = __ffs(leaves) - 1;
-        leaves &= leaves - 1u;
-        const int cnt = sel4(n.count, q);
-        const int first = sel4(n.child, q);
-        for (int k0 = first; k0 < first + cnt; k0 += 4) {
-            // four triangles' loads in flight at once; slots past the leaf
-            // (clamped to the array) are loaded but not tested
-            DevTri T[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) T[e] = S.tris[min(k0 + e, S.n_tris - 1)];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                if (k0 + e >= first + cnt) break;
-                ctr.tris++;
-                float t;
-                if (tri_test(T[e], o, d, S.tmin, t) && t <= bt) {
-                    const uint32_t prim = __float_as_uint(T[e].v0.w);
-                    if (anyhit && t < tmax) {
-                        best = k0 + e;
-                        return true;
-                    }
-                    if (t < bt || (t == bt && prim < best_prim)) {
-                        bt = t;
-                        best = k0 + e;
-                        best_prim = prim;
-                    }
-                }
-            }
-        }
+    // the batch size is a property of the scene (2 when no leaf holds more
+    // than 2 triangles), so the branch is uniform
+    if (S.leaf_batch == 2) {
+        if (leaf_tests<2>(S, n, leaves, o, d, tmax, anyhit, bt, best, best_prim, ctr)) return true;
+    } else {
+        if (leaf_tests<4>(S, n, leaves, o, d, tmax, anyhit, bt, best, best_prim, ctr)) return true;
     }
     float kt[4];
 #pragma unroll

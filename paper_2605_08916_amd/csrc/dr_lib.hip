@@ -326,8 +326,8 @@ __global__ void __launch_bounds__(256) k_copy_u32(const uint32_t* src, uint32_t*
 // the path's continuation and shadow rays are traced concurrently (one per
 // lane), and only the even lane performs the atomics.
 template <int L, bool PAIR>
-__global__ void __launch_bounds__(256) k_step_fused(KParams P, DevScene S, KBufs B, uint32_t nsteps, uint32_t grab,
-                                                    int sorted) {
+__device__ __forceinline__ void step_fused_body(const KParams& P, const DevScene& S, const KBufs& B, uint32_t nsteps,
+                                                uint32_t grab, int sorted) {
     extern __shared__ uint32_t s_stack[];
     uint32_t* stk = s_stack + threadIdx.x;
     const int stride = blockDim.x;
@@ -400,6 +400,23 @@ __global__ void __launch_bounds__(256) k_step_fused(KParams P, DevScene S, KBufs
         wave_add(&B.ctr[C_NODES], ctr.nodes);
         wave_add(&B.ctr[C_TRIS], ctr.tris);
     }
+}
+
+// Paired lanes (two per chain): at 128 of the kernel's registers or more a
+// SIMD holds two wavefronts, which is all the paired form has at the chain
+// counts it is used for.
+template <int L>
+__global__ void __launch_bounds__(256) k_step_fused_pair(KParams P, DevScene S, KBufs B, uint32_t nsteps, uint32_t grab,
+                                                         int sorted) {
+    step_fused_body<L, true>(P, S, B, nsteps, grab, sorted);
+}
+// One lane per chain (used when chains outnumber two wavefronts per SIMD):
+// registers capped for three wavefronts per SIMD, which hides more of the
+// traversal's memory latency than the spills it costs.
+template <int L>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+k_step_fused(KParams P, DevScene S, KBufs B, uint32_t nsteps, uint32_t grab, int sorted) {
+    step_fused_body<L, false>(P, S, B, nsteps, grab, sorted);
 }
 
 // Path records of the chain in slot c, written as the state machine reaches
@@ -851,8 +868,8 @@ static void launch_init_acc(dim3 g, dim3 b, hipStream_t st, const KParams& P, co
 template <int L>
 static void launch_fused(dim3 g, dim3 b, hipStream_t st, const KParams& P, const DevScene& S, const KBufs& B,
                          uint32_t n, uint32_t grab, bool pair, int sorted) {
-    if (pair) hipLaunchKernelGGL((k_step_fused<L, true>), g, b, stack_bytes(S, b.x), st, P, S, B, n, grab, sorted);
-    else hipLaunchKernelGGL((k_step_fused<L, false>), g, b, stack_bytes(S, b.x), st, P, S, B, n, grab, sorted);
+    if (pair) hipLaunchKernelGGL(k_step_fused_pair<L>, g, b, stack_bytes(S, b.x), st, P, S, B, n, grab, sorted);
+    else hipLaunchKernelGGL(k_step_fused<L>, g, b, stack_bytes(S, b.x), st, P, S, B, n, grab, sorted);
 }
 template <int L>
 static void launch_sm(dim3 g, dim3 b, hipStream_t st, const KParams& P, const DevScene& S, const KBufs& B, uint32_t n,
@@ -1260,6 +1277,12 @@ dr_status dr_scene_create(const dr_scene_desc* desc, int device, dr_scene** out)
     S->ds.lights = (const float4*)dlights;
     S->ds.n_lights = (int)desc->n_lights;
     S->ds.n_tris = (int)T;
+    {
+        int max_count = 0;
+        for (const DevNode& nd : dn)
+            max_count = std::max({max_count, nd.count.x, nd.count.y, nd.count.z, nd.count.w});
+        S->ds.leaf_batch = max_count <= 2 ? 2 : 4;
+    }
     S->ds.tmin = (float)(1e-4 * diag);
     S->ds.cam = (const float4*)dcam;
     S->ds.W = (int)desc->camera.width;
