@@ -118,13 +118,38 @@ __device__ __forceinline__ float safe_rcp(float d) {
     return 1.0f / (fabsf(d) < 1e-20f ? copysignf(1e-20f, d) : d);
 }
 
-// Slab test with a relative widening of the far distance so FP32 rounding
-// never culls a box whose triangles are hit (boxes are exact f32 bounds).
-__device__ __forceinline__ bool slab(float lx, float ly, float lz, float hx, float hy, float hz, V3 o, V3 inv,
+// Per-ray constants of the slab test.  A plane at coordinate p along axis a
+// is crossed at t = (p - o_a) inv_a, computed as one FMA p * inv_a + c with
+// c = -(o_a inv_a).  The rounding of o_a inv_a (and of c) is at most
+// |o_a inv_a| 2^-23 in t, so each axis's interval is widened by
+// E_a = |o_a inv_a| 2^-22, folded into the constants: the plane that bounds
+// the interval from below (the low plane when inv_a >= 0, else the high one)
+// takes c - E_a, the other c + E_a.  With the far distance also widened
+// relatively (the final FMA's own rounding), no box a ray truly enters
+// within (tmin, tmax) is ever culled.
+struct RaySlab {
+    V3 inv, clo, chi;  // clo / chi: constants of the low / high plane per axis
+};
+__device__ __forceinline__ float slab_const(float o, float inv, bool low) {
+    const float oi = o * inv;
+    const float e = fabsf(oi) * 2.384185791015625e-07f;  // 2^-22
+    return (low == (inv >= 0.0f)) ? -(oi + e) : -(oi - e);
+}
+__device__ __forceinline__ RaySlab ray_slab(V3 o, V3 d) {
+    RaySlab r;
+    r.inv = v3(safe_rcp(d.x), safe_rcp(d.y), safe_rcp(d.z));
+    r.clo = v3(slab_const(o.x, r.inv.x, true), slab_const(o.y, r.inv.y, true), slab_const(o.z, r.inv.z, true));
+    r.chi = v3(slab_const(o.x, r.inv.x, false), slab_const(o.y, r.inv.y, false), slab_const(o.z, r.inv.z, false));
+    return r;
+}
+
+// Slab test over (tmin, tmax) with the per-ray constants above; tnear is the
+// entry distance (used to order the children).
+__device__ __forceinline__ bool slab(float lx, float ly, float lz, float hx, float hy, float hz, const RaySlab& r,
                                      float tmin, float tmax, float& tnear) {
-    const float tx0 = (lx - o.x) * inv.x, tx1 = (hx - o.x) * inv.x;
-    const float ty0 = (ly - o.y) * inv.y, ty1 = (hy - o.y) * inv.y;
-    const float tz0 = (lz - o.z) * inv.z, tz1 = (hz - o.z) * inv.z;
+    const float tx0 = fmaf(lx, r.inv.x, r.clo.x), tx1 = fmaf(hx, r.inv.x, r.chi.x);
+    const float ty0 = fmaf(ly, r.inv.y, r.clo.y), ty1 = fmaf(hy, r.inv.y, r.chi.y);
+    const float tz0 = fmaf(lz, r.inv.z, r.clo.z), tz1 = fmaf(hz, r.inv.z, r.chi.z);
     const float tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), tmin));
     const float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fmaxf(tz0, tz1)) * 1.0000004f;
     tnear = tn;
@@ -218,7 +243,7 @@ __device__ __forceinline__ bool leaf_tests(const DevScene& S, const DevNode& n, 
 // once), and returns the hit inner children sorted near to far in kc (-1 =
 // none; a fixed sorting network keeps every index static).  Returns true when
 // an any-hit query has found its hit (slot in best).
-__device__ __forceinline__ bool visit_node(const DevScene& S, int node, V3 o, V3 d, V3 inv, float tmax, bool anyhit,
+__device__ __forceinline__ bool visit_node(const DevScene& S, int node, V3 o, V3 d, const RaySlab& rs, float tmax, bool anyhit,
                                            float& bt, int& best, uint32_t& best_prim, int (&kc)[4], Counters& ctr) {
     const DevNode n = load_node(S.nodes, node);
     ctr.nodes++;
@@ -228,8 +253,8 @@ __device__ __forceinline__ bool visit_node(const DevScene& S, int node, V3 o, V3
     bool hit[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
-        hit[q] = slab(f4(n.lox, q), f4(n.loy, q), f4(n.loz, q), f4(n.hix, q), f4(n.hiy, q), f4(n.hiz, q), o, inv,
-                      S.tmin, bt, tn[q]) &
+        hit[q] = slab(f4(n.lox, q), f4(n.loy, q), f4(n.loz, q), f4(n.hix, q), f4(n.hiy, q), f4(n.hiz, q), rs, S.tmin,
+                      bt, tn[q]) &
                  (i4(n.count, q) >= 0);
     uint32_t leaves = 0;
 #pragma unroll
@@ -287,7 +312,7 @@ __device__ int trace(const DevScene& S, V3 o, V3 d, float tmax, bool anyhit, flo
                      Counters& ctr) {
     t_hit = tmax;
     if (!(tmax > S.tmin)) return -1;
-    const V3 inv = v3(safe_rcp(d.x), safe_rcp(d.y), safe_rcp(d.z));
+    const RaySlab rs = ray_slab(o, d);
     float bt = tmax;
     int best = -1;
     uint32_t best_prim = 0xFFFFFFFFu;
@@ -296,7 +321,7 @@ __device__ int trace(const DevScene& S, V3 o, V3 d, float tmax, bool anyhit, flo
     ctr.rays++;
     while (true) {
         int kc[4];
-        if (visit_node(S, node, o, d, inv, tmax, anyhit, bt, best, best_prim, kc, ctr)) {
+        if (visit_node(S, node, o, d, rs, tmax, anyhit, bt, best, best_prim, kc, ctr)) {
             t_hit = bt;
             return best;
         }

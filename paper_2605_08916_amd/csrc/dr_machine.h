@@ -24,7 +24,8 @@ namespace dr {
 // Resumable ray query over (tmin, tmax): closest hit (ties in t to the lower
 // input triangle index) or, with anyhit, the first hit found.
 struct RayQ {
-    V3 o, d, inv;
+    V3 o, d;
+    RaySlab rs;
     float tmax, bt;
     int best;
     uint32_t best_prim;
@@ -46,7 +47,7 @@ __device__ __forceinline__ bool ray_begin(const DevScene& S, RayQ& q, V3 o, V3 d
     q.sp = 0;
     q.anyhit = anyhit;
     if (!(tmax > S.tmin)) return false;
-    q.inv = v3(safe_rcp(d.x), safe_rcp(d.y), safe_rcp(d.z));
+    q.rs = ray_slab(o, d);
     ctr.rays++;
     return true;
 }
@@ -56,7 +57,7 @@ __device__ __forceinline__ bool ray_begin(const DevScene& S, RayQ& q, V3 o, V3 d
 // -1) and, for a closest-hit query, q.bt its distance.
 __device__ __forceinline__ bool ray_step(const DevScene& S, RayQ& q, uint32_t* stk, int stride, Counters& ctr) {
     int kc[4];
-    if (visit_node(S, q.node, q.o, q.d, q.inv, q.tmax, q.anyhit, q.bt, q.best, q.best_prim, kc, ctr)) return true;
+    if (visit_node(S, q.node, q.o, q.d, q.rs, q.tmax, q.anyhit, q.bt, q.best, q.best_prim, kc, ctr)) return true;
     if (next_node(kc, q.node, q.sp, stk, stride, S.stack_cap)) return false;
     if (q.anyhit) q.best = -1;
     return true;
