@@ -49,9 +49,10 @@ def parse():
                     help="only run warmup + steps of the fused form (for hardware-counter runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates the FETCH_SIZE/WRITE_SIZE counters)")
-    ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
-                    help="no GPU: write the HBM traffic summary of the fused kernel from four rocprofv3 --pmc "
-                         "output folders (FETCH_SIZE and WRITE_SIZE of --profile-only, then of --copy-probe)")
+    ap.add_argument("--traffic-summary", nargs="+", metavar="DIR",
+                    help="no GPU: write the HBM traffic summary of the fused kernel from rocprofv3 --pmc output "
+                         "folders: FETCH_SIZE and WRITE_SIZE of --profile-only, then of --copy-probe, optionally "
+                         "followed by TCC_HIT_sum/TCC_MISS_sum and SQ_WAVE_CYCLES/SQ_ACTIVE_INST_VALU folders")
     return ap.parse_args()
 
 
@@ -88,7 +89,7 @@ def _pmc_rows(folder, counter):
 
 
 def write_traffic_summary(dirs, chains, per_launch):
-    fetch_dir, write_dir, cfetch_dir, cwrite_dir = dirs
+    fetch_dir, write_dir, cfetch_dir, cwrite_dir = dirs[:4]
 
     def fused_mean(folder, counter):
         v = [x for k, x in _pmc_rows(folder, counter) if "k_step_fused" in k]
@@ -110,7 +111,10 @@ def write_traffic_summary(dirs, chains, per_launch):
         "# HBM traffic of k_step_fused_pair<8>: procedural spheres 53k triangles, 512x512, L = 8",
         f"# counters: rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) -d <out> -- {cmd}",
         "# calibration: rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) -d <out> -- python3 bench.py --copy-probe",
-        f"# written by: python3 bench.py --traffic-summary <fetch> <write> <copy_fetch> <copy_write>",
+        "# written by: python3 bench.py --traffic-summary <fetch> <write> <copy_fetch> <copy_write> [<tcc> <sq2>]",
+        "# tcc: --pmc TCC_HIT_sum TCC_MISS_sum; sq2: --pmc SQ_WAVE_CYCLES SQ_WAIT_ANY SQ_ACTIVE_INST_ANY "
+        "SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_VMEM SQ_ACTIVE_INST_LDS SQ_ACTIVE_INST_SCA SQ_INST_CYCLES_VMEM_RD "
+        "(same --profile-only command); valu_issue_frac is per wavefront",
         f"sources_digest: {sources_digest()}",
         f"chains: {chains}",
         f"steps_per_launch: {per_launch}",
@@ -125,9 +129,29 @@ def write_traffic_summary(dirs, chains, per_launch):
         f"hbm_bytes_per_launch: {rd + wr:.0f}",
         f"hbm_bytes_per_chain_step: {(rd + wr) / (chains * per_launch):.1f}",
     ]
+    if len(dirs) >= 6:
+        hit, _ = fused_mean(dirs[4], "TCC_HIT_sum")
+        miss, _ = fused_mean(dirs[4], "TCC_MISS_sum")
+        valu, _ = fused_mean(dirs[5], "SQ_ACTIVE_INST_VALU")
+        wc, _ = fused_mean(dirs[5], "SQ_WAVE_CYCLES")
+        lines += [f"l2_hit_rate: {hit / (hit + miss):.4f}", f"valu_issue_frac: {valu / wc:.4f}"]
     with open(TRAFFIC_FILE, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
+
+
+def read_counters(chains, per_launch):
+    """L2 hit rate and VALU issue fraction of the fused kernel from the same
+    committed counter summary (empty when it does not match the sources)."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            kv = dict(l.split(": ", 1) for l in f.read().splitlines() if l and not l.startswith("#"))
+    except OSError:
+        return {}
+    if (kv.get("sources_digest") != sources_digest() or int(kv.get("chains", -1)) != chains
+            or int(kv.get("steps_per_launch", -1)) != per_launch):
+        return {}
+    return {k: float(kv[k]) for k in ("l2_hit_rate", "valu_issue_frac") if k in kv}
 
 
 def read_traffic(chains, per_launch):
@@ -155,7 +179,8 @@ def mrse(img, ref):
 
 def time_steps(ch, torch, steps, warmup, per_frame=1):
     """Average ms per evolve step, steps issued as frames of dr_step(per_frame)
-    + dr_resolve, with events on the launch stream."""
+    + dr_resolve, with events on the launch stream; also the median over the
+    frames of ms per step."""
     stream = torch.cuda.current_stream()
     out = torch.empty((3, ch.scene.W * ch.scene.H), device="cuda", dtype=torch.float32)
     frames = max(1, steps // per_frame)
@@ -163,15 +188,55 @@ def time_steps(ch, torch, steps, warmup, per_frame=1):
         ch.step(per_frame)
         ch.resolve(out)
     torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(frames):
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(frames + 1)]
+    ev[0].record(stream)
+    for i in range(frames):
         ch.step(per_frame)
         ch.resolve(out)
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    per = [ev[i].elapsed_time(ev[i + 1]) / per_frame for i in range(frames)]
+    return ev[0].elapsed_time(ev[frames]) / (frames * per_frame), frames * per_frame, float(np.median(per))
+
+
+def achievable_bandwidth(torch, reps=5):
+    """HBM bandwidth a plain device copy reaches on this GPU (1 GiB read + 1
+    GiB written per copy), GB/s."""
+    n = 1 << 28
+    src = torch.ones(n, device="cuda", dtype=torch.float32)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * 4 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    return gbs
+
+
+def frame_mrse(ch, torch, ms_per_step, ref, frame_ms=33.3):
+    """MRSE of the image one frame of frame_ms gives: re-initialise (a scene
+    change), as many steps as fit, resolve."""
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    ch.reinit(1)
     e1.record(stream)
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / (frames * per_frame), frames * per_frame
+    ms_init = e0.elapsed_time(e1)
+    n = max(1, int((frame_ms - ms_init) / ms_per_step))
+    e0.record(stream)
+    ch.reinit(1)
+    ch.step(n)
+    ch.resolve()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    img, _ = ch.image_read()
+    return dict(steps=n, frame_ms=e0.elapsed_time(e1), init_ms=ms_init, mrse=mrse(img.astype(np.float64), ref))
 
 
 def time_kernel_only(ch, torch, launches, per_launch):
@@ -250,9 +315,9 @@ def main():
     # ---- fused persistent form: throughput
     ch = dr.Chains(scene, N, L, seed, mode=dr.DR_MODE_FUSED)
     torch.cuda.synchronize()
-    ms_fused, steps_done = time_steps(ch, torch, a.steps, a.warmup, F)
+    ms_fused, steps_done, ms_median = time_steps(ch, torch, a.steps, a.warmup, F)
     value = N / (ms_fused * 1e-3)
-    ms_single, _ = time_steps(ch, torch, max(8, a.steps // 4), 2, 1)
+    ms_single, _, _ = time_steps(ch, torch, max(8, a.steps // 4), 2, 1)
     ms_launch = time_kernel_only(ch, torch, max(4, a.steps // (4 * F)), F)
     ms_kernel = ms_launch / F
     launch_cfg = ch.get_launch()
@@ -287,6 +352,8 @@ def main():
     bytes_step = b_state + b_trav + b_shade + b_splat
     achieved = bytes_step * N * F / (ms_launch * 1e-3) / 1e9
     traffic = read_traffic(N, F)
+    counters = read_counters(N, F)
+    hbm_copy = achievable_bandwidth(torch)
 
     res = {
         "metric": "chain-steps/s (f+∇log f) and MRSE at 33 ms/frame, fused vs plain",
@@ -296,6 +363,7 @@ def main():
         "steps": steps_done,
         "warmup": a.warmup,
         "ms_per_step": ms_fused,
+        "ms_per_step_median_frame": ms_median,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -311,43 +379,51 @@ def main():
                            "alg_bytes": bytes_step},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "achievable_copy_GBs": hbm_copy, "frac_of_achievable": achieved / hbm_copy,
+                     "l2_hit_rate": counters.get("l2_hit_rate"), "valu_issue_frac": counters.get("valu_issue_frac"),
                      "traffic_unit": "HBM bytes per launch", "alg_bytes_per_launch": bytes_step * N * F,
                      "kernel": f"k_step_fused{'_pair' if launch_cfg['lanes_per_chain'] == 2 else ''}<{L}>",
                      "launch_ms": ms_launch, "steps_per_launch": F},
     }
 
-    # ---- plain multi-kernel form on the same workload
-    if not a.no_plain:
-        cp = dr.Chains(scene, N, L, seed, mode=dr.DR_MODE_PLAIN)
-        ms_plain, _ = time_steps(cp, torch, max(2 * F, a.steps // 2), a.warmup, F)
-        res["plain"] = {"value": N / (ms_plain * 1e-3), "ms_per_step": ms_plain}
-        res["fused_over_plain"] = ms_plain / ms_fused
-        cp.close()
-
-    # ---- MRSE after a 33.3 ms frame of fused steps (re-init + steps + resolve)
+    ref = None
     if not a.no_mrse:
         ref = scene.pt_render(L, 777, 256)
         torch.cuda.synchronize()
         ref = ref.cpu().numpy().astype(np.float64)
-        # frame budget: re-init (scene change) + n33 steps + resolve <= 33.3 ms
+
+    # ---- plain multi-kernel form on the same workload
+    if not a.no_plain:
+        cp = dr.Chains(scene, N, L, seed, mode=dr.DR_MODE_PLAIN)
+        ms_plain, _, _ = time_steps(cp, torch, max(2 * F, a.steps // 2), a.warmup, F)
+        res["plain"] = {"value": N / (ms_plain * 1e-3), "ms_per_step": ms_plain}
+        res["fused_over_plain"] = ms_plain / ms_fused
+        if ref is not None:
+            # both forms make the same decisions from the same streams, so at
+            # equal step counts they give the same image; in a 33 ms frame the
+            # plain form fits fewer steps
+            res["plain"]["mrse_33ms"] = frame_mrse(cp, torch, ms_plain, ref)
+        cp.close()
+
+    # ---- MRSE after a 33.3 ms frame of fused steps (re-init + steps + resolve)
+    if ref is not None:
+        res["mrse_33ms"] = dict(frame_mrse(ch, torch, ms_fused, ref),
+                                reference="independent path tracing, 256 spp per pixel (seed 777)")
+        # independent path tracing given the same 33.3 ms (spp that fit), for context
         stream = torch.cuda.current_stream()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        scene.pt_render(L, 5, 1)
         e0.record(stream)
-        ch.reinit(1)
+        scene.pt_render(L, 5, 4)
         e1.record(stream)
         torch.cuda.synchronize()
-        ms_init = e0.elapsed_time(e1)
-        n33 = max(1, int((33.3 - ms_init) / ms_fused))
+        spp = max(1, int(33.3 / (e0.elapsed_time(e1) / 4)))
         e0.record(stream)
-        ch.reinit(1)
-        ch.step(n33)
-        out = ch.resolve()
+        img = scene.pt_render(L, 99, spp)
         e1.record(stream)
         torch.cuda.synchronize()
-        img, _ = ch.image_read()
-        res["mrse_33ms"] = {"steps": n33, "frame_ms": e0.elapsed_time(e1), "init_ms": ms_init,
-                            "mrse": mrse(img.astype(np.float64), ref),
-                            "reference": "independent path tracing, 256 spp per pixel"}
+        res["pt_equal_time_33ms"] = {"spp": spp, "frame_ms": e0.elapsed_time(e1),
+                                     "mrse": mrse(img.cpu().numpy().astype(np.float64), ref)}
     ch.close()
 
     if not a.no_cpu_baseline:

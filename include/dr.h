@@ -121,6 +121,23 @@ dr_status dr_scene_create(const dr_scene_desc* desc, int device, dr_scene** out)
  * in device memory.  The image size cannot change. */
 dr_status dr_scene_set_camera(dr_scene* s, const dr_camera* cam);
 
+/* Device memory hooks, for callers whose framework owns device memory (a
+ * caching allocator): alloc(bytes, hip_stream, user) returns device memory
+ * aligned to 256 bytes, or NULL; free_(ptr, bytes, hip_stream, user) returns
+ * it.  hip_stream is the stream the buffer is used on (NULL for scene data,
+ * which is uploaded synchronously).  Buffers allocated after the call (scenes,
+ * chain sets, the scratch of dr_eval_logp_grad) use the hooks, and each buffer
+ * is released through the hooks that allocated it: chain sets and scenes at
+ * destroy after the device is idle, the evaluation scratch right after its
+ * kernels are enqueued, so free_ must be stream-ordered (the memory may be
+ * reused only by work ordered after that stream's).  Both NULL restores
+ * hipMalloc/hipFree; one NULL is DR_ERR_INVALID_ARG.  The hooks must stay
+ * callable while any buffer they allocated exists, also after other hooks are
+ * installed.  Process-wide; not to be called while other dr_* calls run. */
+typedef void* (*dr_alloc_fn)(size_t bytes, void* hip_stream, void* user);
+typedef void (*dr_free_fn)(void* ptr, size_t bytes, void* hip_stream, void* user);
+dr_status dr_set_allocator(dr_alloc_fn alloc, dr_free_fn free_, void* user);
+
 /* Device layout of a created scene: triangles, 4-wide BVH nodes (128 B
  * each), and the traversal stack a lane needs (the exact worst case over the
  * tree's root-to-leaf paths, at most 64 entries of 4 bytes).  Kernels that

@@ -769,16 +769,50 @@ dr_status fail(dr_status s, const std::string& msg) {
         if (e_ != hipSuccess) return fail(DR_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+// Device memory: hipMalloc, or the caller's hooks installed by
+// dr_set_allocator.  Every block remembers the hooks that made it.
+struct AllocHooks {
+    dr_alloc_fn alloc = nullptr;
+    dr_free_fn free_ = nullptr;
+    void* user = nullptr;
+};
+static AllocHooks g_hooks;
+
+static hipError_t dev_alloc(void** p, size_t bytes, void* stream, const AllocHooks& h) {
+    if (!h.alloc) return hipMalloc(p, bytes);
+    *p = h.alloc(bytes, stream, h.user);
+    if (!*p) return hipErrorOutOfMemory;
+    if (reinterpret_cast<uintptr_t>(*p) % 256) {  // the kernels' vector loads need aligned buffers
+        h.free_(*p, bytes, stream, h.user);
+        *p = nullptr;
+        return hipErrorInvalidValue;
+    }
+    return hipSuccess;
+}
+static void dev_free(void* p, size_t bytes, void* stream, const AllocHooks& h) {
+    if (h.free_) h.free_(p, bytes, stream, h.user);
+    else (void)hipFree(p);
+}
+
 struct DevAlloc {
-    std::vector<void*> ptrs;
+    struct Block {
+        void* p;
+        size_t bytes;
+        AllocHooks hooks;
+        void* stream;
+    };
+    std::vector<Block> blocks;
+    void* stream = nullptr;  // stream handed to the allocator hooks
     hipError_t get(void** p, size_t bytes) {
-        hipError_t e = hipMalloc(p, bytes ? bytes : 4);
-        if (e == hipSuccess) ptrs.push_back(*p);
+        bytes = bytes ? bytes : 4;
+        const AllocHooks h = g_hooks;
+        const hipError_t e = dev_alloc(p, bytes, stream, h);
+        if (e == hipSuccess) blocks.push_back({*p, bytes, h, stream});
         return e;
     }
     void release() {
-        for (void* p : ptrs) (void)hipFree(p);
-        ptrs.clear();
+        for (const Block& b : blocks) dev_free(b.p, b.bytes, b.stream, b.hooks);
+        blocks.clear();
     }
 };
 
@@ -1313,6 +1347,16 @@ dr_status dr_scene_set_camera(dr_scene* s, const dr_camera* cam) {
     return DR_OK;
 }
 
+dr_status dr_set_allocator(dr_alloc_fn alloc, dr_free_fn free_, void* user) {
+    if ((alloc == nullptr) != (free_ == nullptr))
+        return fail(DR_ERR_INVALID_ARG, "dr_set_allocator: give both hooks or neither");
+    g_hooks.alloc = alloc;
+    g_hooks.free_ = free_;
+    g_hooks.user = alloc ? user : nullptr;
+    g_err.clear();
+    return DR_OK;
+}
+
 dr_status dr_scene_get_stats(const dr_scene* s, dr_scene_stats* out) {
     if (!s || !out) return fail(DR_ERR_INVALID_ARG, "dr_scene_get_stats: null argument");
     out->n_triangles = s->n_tris;
@@ -1326,6 +1370,7 @@ dr_status dr_scene_get_stats(const dr_scene* s, dr_scene_stats* out) {
 void dr_scene_destroy(dr_scene* s) {
     if (!s) return;
     (void)hipSetDevice(s->device);
+    (void)hipDeviceSynchronize();  // allocator hooks may hand the memory out again at once
     s->mem.release();
     delete s;
 }
@@ -1341,6 +1386,7 @@ dr_status dr_chains_init(dr_scene* s, const dr_params* p, uint64_t seed, uint32_
     if (p->mode > 1) return fail(DR_ERR_INVALID_ARG, "dr_chains_init: unknown mode");
     HIP_TRY(hipSetDevice(s->device));
     auto* c = new dr_chains();
+    c->mem.stream = hip_stream;
     c->scene = s;
     c->P = *p;
     c->seed = seed;
@@ -1624,7 +1670,14 @@ dr_status dr_eval_logp_grad(dr_scene* s, uint32_t L, const float* u_dev, uint32_
     (void)hipGetLastError();  // drop a stale error left by an earlier, unrelated call
     hipStream_t st = (hipStream_t)hip_stream;
     void* rs = nullptr;
-    HIP_TRY(hipMallocAsync(&rs, sizeof(uint32_t) * (L - 1) * (size_t)n, st));
+    const AllocHooks hooks = g_hooks;
+    const size_t rs_bytes = sizeof(uint32_t) * (L - 1) * (size_t)n;
+    if (hooks.alloc) {
+        if (dev_alloc(&rs, rs_bytes, st, hooks) != hipSuccess)
+            return fail(DR_ERR_OUT_OF_MEMORY, "dr_eval_logp_grad: scratch allocation failed");
+    } else {
+        HIP_TRY(hipMallocAsync(&rs, rs_bytes, st));
+    }
     if (!grad_dev) {
         // forward only: the ray-refill evaluator, persistent, points taken
         // from a counter in the scratch buffer
@@ -1639,7 +1692,8 @@ dr_status dr_eval_logp_grad(dr_scene* s, uint32_t L, const float* u_dev, uint32_
                       logp_dev, grad_dev, (uint32_t*)rs, rec_dev);
     }
     hipError_t e = hipGetLastError();
-    (void)hipFreeAsync(rs, st);
+    if (hooks.alloc) dev_free(rs, rs_bytes, st, hooks);
+    else (void)hipFreeAsync(rs, st);
     if (e != hipSuccess) return fail(DR_ERR_DEVICE, std::string("dr_eval_logp_grad: ") + hipGetErrorString(e));
     g_err.clear();
     return DR_OK;

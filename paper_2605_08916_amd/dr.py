@@ -21,7 +21,7 @@ DR_MODE_FUSED, DR_MODE_PLAIN = 0, 1
 NO_VERTEX = 0xFFFFFFFF
 
 EXPORTED = [
-    "dr_last_error", "dr_version", "dr_bvh_build", "dr_scene_create", "dr_scene_set_camera", "dr_scene_get_stats",
+    "dr_last_error", "dr_version", "dr_bvh_build", "dr_scene_create", "dr_scene_set_camera", "dr_scene_get_stats", "dr_set_allocator",
     "dr_scene_destroy",
     "dr_chains_init", "dr_chains_reinit", "dr_step", "dr_resolve", "dr_image_read", "dr_chains_destroy",
     "dr_chains_read_state", "dr_chains_write_state", "dr_chains_set_record", "dr_chains_set_counters", "dr_stats",
@@ -55,6 +55,40 @@ class dr_bvh_node(C.Structure):
 class dr_camera(C.Structure):
     _fields_ = [("eye", C.c_float * 3), ("at", C.c_float * 3), ("up", C.c_float * 3), ("vfov_deg", C.c_float),
                 ("width", C.c_uint32), ("height", C.c_uint32)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+# Every callback pair ever installed stays referenced for the life of the
+# process: buffers allocated through a pair are freed through it later, also
+# after another allocator has been installed.
+_hooks_alive = []
+
+
+def use_torch_allocator(enable: bool = True):
+    """Serve the library's device buffers from torch's caching allocator (or
+    go back to hipMalloc/hipFree).  Buffers keep the allocator that made them."""
+    if not enable:
+        _check(lib().dr_set_allocator(ALLOC_FN(), FREE_FN(), None))
+        return
+    import torch
+
+    def _alloc(nbytes, stream, user):
+        try:
+            s = stream if stream else torch.cuda.current_stream().cuda_stream
+            return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(s))
+        except Exception:
+            return None
+
+    def _free(ptr, nbytes, stream, user):
+        try:
+            torch.cuda.caching_allocator_delete(int(ptr))
+        except Exception:
+            pass
+
+    hooks = (ALLOC_FN(_alloc), FREE_FN(_free))
+    _hooks_alive.append(hooks)
+    _check(lib().dr_set_allocator(hooks[0], hooks[1], None))
 
 
 class dr_scene_stats(C.Structure):
@@ -120,6 +154,7 @@ def lib():
         "dr_scene_set_camera": ([P, C.POINTER(dr_camera)], st),
         "dr_scene_destroy": ([P], None),
         "dr_scene_get_stats": ([P, C.POINTER(dr_scene_stats)], st),
+        "dr_set_allocator": ([ALLOC_FN, FREE_FN, P], st),
         "dr_chains_init": ([P, C.POINTER(dr_params), C.c_uint64, C.c_uint32, P, pp], st),
         "dr_chains_reinit": ([P, C.c_uint32, P], st),
         "dr_step": ([P, C.c_uint32, P], st),

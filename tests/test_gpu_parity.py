@@ -621,6 +621,38 @@ def test_adjoint_long_paths_with_segment_recompute(orc):
     assert checked > 5000 and bad <= 0.01 * checked
 
 
+def test_torch_allocator_serves_library_buffers(scenes):
+    """With torch's caching allocator installed as the library's allocator,
+    chain buffers and evaluation scratch come from torch, the results are the
+    same as with hipMalloc, and destroying the chains returns the memory."""
+    S = dr.Scene(scenes["tiny"])
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    dr.use_torch_allocator(True)
+    try:
+        a = dr.Chains(S, 2000, 4, 3, k0=250.0)
+        grown = torch.cuda.memory_allocated() - base
+        a.step(3)
+        u = torch.rand((500, 12), device="cuda")
+        fa = S.eval_logp_grad(4, u, grad=True)[0]
+        sa = a.read_state()
+    finally:
+        dr.use_torch_allocator(False)
+    say(f"[torch allocator] chain buffers {grown} bytes from torch")
+    assert grown > 0
+    b = dr.Chains(S, 2000, 4, 3, k0=250.0)
+    b.step(3)
+    fb = S.eval_logp_grad(4, u, grad=True)[0]
+    sb = b.read_state()
+    assert np.array_equal(sa["x"], sb["x"]) and np.array_equal(sa["killed"], sb["killed"])
+    assert sa["tour_count"] == sb["tour_count"]
+    assert torch.equal(fa, fb)
+    a.close()
+    del fa, u
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() - base <= grown - 1  # the chain set's buffers went back to torch
+
+
 def test_autotune_restores_chains(scenes, tmp_path, monkeypatch):
     """The launch autotuner sweeps configurations on the live chain set, then
     puts the chains back: tuning followed by n steps gives the chains n steps

@@ -153,5 +153,9 @@ def test_null_handles_rejected(L):
     assert L.dr_chains_reinit(None, 0, None) == dr.DR_ERR_INVALID_ARG
     assert L.dr_resolve(None, None, None) == dr.DR_ERR_INVALID_ARG
     assert L.dr_scene_get_stats(None, None) == dr.DR_ERR_INVALID_ARG
+    # allocator hooks: both or neither
+    keep = dr.ALLOC_FN(lambda n, s, u: None)
+    assert L.dr_set_allocator(keep, dr.FREE_FN(), None) == dr.DR_ERR_INVALID_ARG
+    assert L.dr_set_allocator(dr.ALLOC_FN(), dr.FREE_FN(), None) == dr.DR_OK
     assert L.dr_chains_destroy(None) == dr.DR_OK
     assert b"null" in L.dr_last_error() or L.dr_last_error() == b""
