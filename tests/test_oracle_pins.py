@@ -446,3 +446,60 @@ def test_chain_determinism_and_thread_independence(orc):
     assert np.array_equal(outs[0][0], outs[1][0])
     assert np.array_equal(outs[0][1], outs[1][1])
     assert outs[0][2] == outs[1][2]
+
+
+# ---------------------------------------------------------------------------
+# Bias term L*p/p of the modified killing rate (Sec. 5.2, Eq. adjoint-bias)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("gamma", [0.0, 0.5])
+def test_bias_term_gaussian_closed_form(gamma):
+    """For p = N(c, s^2 I) the Euler-Maruyama kernel (with the rotational
+    drift) maps p to N(c, (s^2 (a^2 + beta^2) + dt sigma2) I), so L*p/p has a
+    closed form; the grid quadrature must reproduce it."""
+    from oracle import bias
+    c, s, dt, sigma2 = (0.5, 0.5), 0.05, 1e-3, 1.0
+    dens = bias.wrapped_mixture([1.0], [c], [s], c0=0.0, images=0)
+    X, Y, p, t = bias.em_bias_term(dens, 128, dt, sigma2, gamma)
+    ref = bias.gaussian_term_closed_form(X, Y, c, s, dt, sigma2, gamma)
+    inner = (X - c[0]) ** 2 + (Y - c[1]) ** 2 < (3 * s) ** 2
+    assert np.abs(ref[inner]).max() > 50.0  # the term is far from zero here
+    assert np.abs(t - ref)[inner].max() < 1e-8
+
+
+def test_bias_term_is_order_dt():
+    """The bias term is O(dt) (sigma2 fixed): halving dt halves it on a
+    smooth four-mode target."""
+    from oracle import bias
+    mix = inputs.mixture_target(d=2, seed=11)
+    dens = bias.wrapped_mixture(mix["weights"], mix["means"], mix["stds"], c0=0.1)
+    out = []
+    for dt in (1e-3, 5e-4):
+        sd = math.sqrt(dt * 0.25)
+        _, _, p, t = bias.em_bias_term(dens, int(math.ceil(3.0 / sd)), dt, 0.25, gamma=0.5)
+        out.append(((np.abs(t) * p).sum() / p.sum(), np.abs(t).max()))
+    for a, b in zip(out[0], out[1]):
+        assert 1.8 < a / b < 2.2
+
+
+def test_bias_drift_is_the_chain_move(orc):
+    """The drift b of the bias term is the oracle chain's move: from one point
+    with a given score, the mean displacement of one step is dt b."""
+    import oracle as O
+    from oracle import bias
+    d, N, dt, sigma2, gamma = 2, 40000, 1e-3, 1.0, 0.5
+    x0 = np.array([0.53, 0.46])
+    dens = bias.wrapped_mixture([1.0], [(0.5, 0.5)], [0.05], images=0)
+    p, gx, gy = dens(np.array([x0[0]]), np.array([x0[1]]))
+    s = np.array([gx[0] / p[0], gy[0] / p[0]])
+    b = np.array([0.5 * sigma2 * s[0] + 0.5 * gamma * s[1], 0.5 * sigma2 * s[1] - 0.5 * gamma * s[0]])
+    C = O.Chains.mixture(d, [1.0], [(0.5, 0.5)], [0.05], 0.0, N, seed=5, stddev=math.sqrt(dt * sigma2), dt=dt,
+                         gamma=gamma, k0=1e-12)
+    C.set_state(np.tile(x0[:, None], (1, N)), np.tile(s[:, None], (1, N)), np.zeros(N), step=1, k0=1e-12)
+    C.step(1)
+    st = C.state()
+    assert st["killed"].sum() == 0
+    disp = st["x"] - x0[:, None]
+    disp -= np.round(disp)
+    se = math.sqrt(dt * sigma2 / N)
+    assert np.all(np.abs(disp.mean(axis=1) - dt * b) < 5 * se)
+    assert abs(dt * b[1] - dt * 0.5 * sigma2 * s[1]) > 10 * se  # the rotation is resolved
