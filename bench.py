@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--steps-per-frame", type=int, default=8)
     ap.add_argument("--profile-only", action="store_true",
                     help="only run warmup + steps of the fused form (for hardware-counter runs)")
+    ap.add_argument("--config", default=None,
+                    help="measure a named larger configuration instead of the headline line (instances, "
+                         "spheres_1080p_L16, interior); prints its own JSON line")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates the FETCH_SIZE/WRITE_SIZE counters)")
     ap.add_argument("--traffic-summary", nargs="+", metavar="DIR",
@@ -273,6 +276,74 @@ def cpu_baseline(sc, L, seconds, k0):
                        f"{dt:.1f} s)")
 
 
+def run_config(a, torch, dr, inputs):
+    """One JSON line for a larger configuration: chain-steps/s in frames of F
+    steps, rays and traversal work per chain-step, and the image a 33.3 ms
+    frame gives (re-initialise + steps + resolve) against independent path
+    tracing at 64 spp.  The interior configuration runs the real-time loop: a
+    captured frame graph replayed along the camera path, one reference per
+    sampled frame."""
+    fac, L, N = inputs.CONFIGS[a.config]
+    sc = fac()
+    d = 4 * (L - 1)
+    scene = dr.Scene(sc)
+    sigma = None
+    if a.config == "spheres_1080p_L16":
+        sigma = torch.from_numpy(inputs.per_chain_sigma(d, N, seed=4)).cuda()
+    F = max(1, a.steps_per_frame)
+    ch = dr.Chains(scene, N, L, 2024, sigma=sigma)
+    ms, steps, med = time_steps(ch, torch, a.steps, a.warmup, F)
+    ch.set_counters(True)
+    b0 = ch.stats()
+    ch.step(2)
+    b1 = ch.stats()
+    ch.set_counters(False)
+    cs = b1["chain_steps"] - b0["chain_steps"]
+    rays = (b1["rays"] - b0["rays"]) / cs
+    res = {"metric": "chain-steps/s (f+grad log f), larger configuration", "value": N / (ms * 1e-3),
+           "unit": "chain-steps/s", "ms_per_step": ms, "ms_per_step_median_frame": med, "steps": steps,
+           "config": {"workload": a.config, "triangles": int(sc["indices"].shape[0]), "width": scene.W,
+                      "height": scene.H, "path_len": L, "chains": N, "per_chain_sigma": sigma is not None,
+                      "steps_per_frame": F, "launch": ch.get_launch(), "scene": scene.stats()},
+           "rays_per_s": rays * N / (ms * 1e-3),
+           "per_chain_step": {"rays": rays, "node_visits": (b1["node_visits"] - b0["node_visits"]) / cs,
+                              "tri_tests": (b1["tri_tests"] - b0["tri_tests"]) / cs,
+                              "adjoint_fraction": (b1["adjoints"] - b0["adjoints"]) / cs}}
+    if not a.no_mrse:
+        if a.config == "interior":
+            # frame graph: re-init + n steps + resolve, replayed along the camera path
+            stream = torch.cuda.Stream()
+            img = torch.zeros((3, scene.W * scene.H), device="cuda")
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ch.reinit(1)
+            torch.cuda.synchronize()
+            n = max(1, int((33.3 - 2.0) / ms))
+            with torch.cuda.stream(stream):
+                frame = ch.capture_frame(n, True, img, stream)
+            frames = []
+            for f in (0, 20, 40, 59):
+                cam = inputs.camera_path(sc, f)
+                scene.set_camera(cam)
+                e0.record(stream)
+                frame.launch(stream)
+                e1.record(stream)
+                stream.synchronize()
+                ref = scene.pt_render(L, 700 + f, 64)
+                torch.cuda.synchronize()
+                frames.append({"frame": f, "frame_ms": e0.elapsed_time(e1),
+                               "mrse": mrse(img.cpu().numpy().astype(np.float64),
+                                            ref.cpu().numpy().astype(np.float64))})
+            frame.close()
+            res["realtime_loop"] = {"steps_per_frame": n, "frames": frames,
+                                    "reference": "independent path tracing, 64 spp per pixel"}
+        else:
+            ref = scene.pt_render(L, 777, 64)
+            torch.cuda.synchronize()
+            res["mrse_33ms"] = dict(frame_mrse(ch, torch, ms, ref.cpu().numpy().astype(np.float64)),
+                                    reference="independent path tracing, 64 spp per pixel")
+    print(json.dumps(res))
+
+
 def main():
     a = parse()
     if a.traffic_summary:
@@ -287,6 +358,9 @@ def main():
     from paper_2605_08916_amd import dr, inputs
 
     torch.cuda.set_device(0)
+    if a.config:
+        run_config(a, torch, dr, inputs)
+        return
     if a.copy_probe:
         n = 1 << 28
         src = torch.ones(n, device="cuda", dtype=torch.float32)
