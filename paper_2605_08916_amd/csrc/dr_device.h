@@ -303,11 +303,72 @@ __device__ __forceinline__ bool next_node(const int (&kc)[4], int& node, int& sp
     return true;
 }
 
+// Leaf entries share the traversal stack with inner nodes: a leaf of cnt
+// triangles from slot first is stored as -1 - (first << 5 | cnt) (cnt <= 16,
+// first < 2^24), inner nodes as their index (>= 0).
+__device__ __forceinline__ int leaf_code(int first, int cnt) { return -1 - ((first << 5) | cnt); }
+
+// Triangle tests of one leaf; returns true when an any-hit query has found
+// its hit (slot in best).
+template <int BATCH>
+__device__ __forceinline__ bool test_leaf(const DevScene& S, int code, V3 o, V3 d, float tmax, bool anyhit, float& bt,
+                                          int& best, uint32_t& best_prim, Counters& ctr) {
+    const int v = -1 - code;
+    const int first = v >> 5, cnt = v & 31;
+    for (int k0 = first; k0 < first + cnt; k0 += BATCH) {
+        DevTri T[BATCH];
+#pragma unroll
+        for (int e = 0; e < BATCH; ++e) T[e] = S.tris[min(k0 + e, S.n_tris - 1)];
+#pragma unroll
+        for (int e = 0; e < BATCH; ++e) {
+            if (k0 + e >= first + cnt) break;
+            ctr.tris++;
+            float t;
+            if (tri_test(T[e], o, d, S.tmin, t) && t <= bt) {
+                const uint32_t prim = __float_as_uint(T[e].v0.w);
+                if (anyhit && t < tmax) {
+                    best = k0 + e;
+                    return true;
+                }
+                if (t < bt || (t == bt && prim < best_prim)) {
+                    bt = t;
+                    best = k0 + e;
+                    best_prim = prim;
+                }
+            }
+        }
+    }
+    return false;
+}
+
+// Next work from the stack: an inner node to visit, or a leaf to hold as the
+// pending one (if the lane already holds one, the leaf stays on the stack
+// and the lane waits for the next leaf round).
+__device__ __forceinline__ void pop_entry(int& node, int& pleaf, int& sp, const uint32_t* stk, int stride) {
+    node = -1;
+    if (sp == 0) return;
+    const int e = (int)stk[(--sp) * stride];
+    if (e >= 0) node = e;
+    else if (pleaf == 0) pleaf = e;
+    else ++sp;
+}
+
+#define DR_LEAF_PCT 50  // leaf round once this share of the wavefront's busy lanes hold a pending leaf
+
 // One ray query over (tmin, tmax): the closest hit (ties in t go to the lower
 // input triangle index) or, with anyhit, the first hit found.  Returns the
 // triangle slot (leaf order) or -1; tmax <= tmin means "no ray" and returns -1
 // at once (used by paired lanes that have nothing to trace).  stk is this
 // lane's LDS stack, entries at stk[k * stride].
+//
+// Leaf tests are postponed (speculative traversal): a lane that reaches a leaf
+// holds it as pending and keeps visiting nodes (further leaves go to the
+// stack), and the wavefront tests triangles only once enough of its lanes hold
+// a leaf, or none can visit a node.  Node visits and leaf tests then each run
+// with many lanes active instead of a leaf round whenever any one lane meets a
+// leaf.  The closest hit and the tie rule do not depend on the order of the
+// tests (a postponed leaf only means fewer boxes culled meanwhile), and an
+// any-hit query only reports whether a hit exists.
 __device__ int trace(const DevScene& S, V3 o, V3 d, float tmax, bool anyhit, float& t_hit, uint32_t* stk, int stride,
                      Counters& ctr) {
     t_hit = tmax;
@@ -316,19 +377,81 @@ __device__ int trace(const DevScene& S, V3 o, V3 d, float tmax, bool anyhit, flo
     float bt = tmax;
     int best = -1;
     uint32_t best_prim = 0xFFFFFFFFu;
-    int sp = 0;
-    int node = 0;
+    int sp = 0, node = 0, pleaf = 0;
+    bool found = false;
+    const int cap = S.stack_cap;
     ctr.rays++;
     while (true) {
-        int kc[4];
-        if (visit_node(S, node, o, d, rs, tmax, anyhit, bt, best, best_prim, kc, ctr)) {
-            t_hit = bt;
-            return best;
+        const bool has_leaf = pleaf != 0, can_visit = node >= 0;
+        const uint64_t ml = __ballot(has_leaf), mv = __ballot(can_visit);
+        if (!(ml | mv)) break;
+        const int nl = __popcll(ml);
+        if (nl && (mv == 0 || 100 * nl >= DR_LEAF_PCT * __popcll(ml | mv))) {
+            if (has_leaf) {
+                const bool f = S.leaf_batch == 2 ? test_leaf<2>(S, pleaf, o, d, tmax, anyhit, bt, best, best_prim, ctr)
+                                                 : test_leaf<4>(S, pleaf, o, d, tmax, anyhit, bt, best, best_prim, ctr);
+                pleaf = 0;
+                if (f) {
+                    found = true;
+                    node = -1;
+                    sp = 0;
+                } else if (node < 0) {
+                    pop_entry(node, pleaf, sp, stk, stride);
+                }
+            }
+        } else if (can_visit) {
+            const DevNode n = load_node(S.nodes, node);
+            ctr.nodes++;
+            float tn[4];
+            bool hit[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                hit[q] = slab(f4(n.lox, q), f4(n.loy, q), f4(n.loz, q), f4(n.hix, q), f4(n.hiy, q), f4(n.hiz, q), rs,
+                              S.tmin, bt, tn[q]) &
+                         (i4(n.count, q) >= 0);
+            // hit leaves: the first becomes the pending leaf if the lane holds none, the others wait on the stack
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (hit[q] && i4(n.count, q) > 0) {
+                    const int code = leaf_code(i4(n.child, q), i4(n.count, q));
+                    if (pleaf == 0) pleaf = code;
+                    else if (sp < cap) stk[(sp++) * stride] = (uint32_t)code;
+                }
+            }
+            // hit inner children: visit the nearest next, push the others
+            // far-first (a fixed sorting network keeps every index static)
+            float kt[4];
+            int kc[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const bool inner = hit[q] && i4(n.count, q) == 0;
+                kt[q] = inner ? tn[q] : INFINITY;
+                kc[q] = inner ? i4(n.child, q) : -1;
+            }
+#define DR_CSWAP(i, j)                                       \
+    if (kt[j] < kt[i]) {                                     \
+        const float tt_ = kt[i]; kt[i] = kt[j]; kt[j] = tt_; \
+        const int cc_ = kc[i]; kc[i] = kc[j]; kc[j] = cc_;   \
+    }
+            DR_CSWAP(0, 1)
+            DR_CSWAP(2, 3)
+            DR_CSWAP(0, 2)
+            DR_CSWAP(1, 3)
+            DR_CSWAP(1, 2)
+#undef DR_CSWAP
+            if (kc[0] >= 0) {
+                if (kc[3] >= 0 && sp < cap) stk[(sp++) * stride] = (uint32_t)kc[3];
+                if (kc[2] >= 0 && sp < cap) stk[(sp++) * stride] = (uint32_t)kc[2];
+                if (kc[1] >= 0 && sp < cap) stk[(sp++) * stride] = (uint32_t)kc[1];
+                node = kc[0];
+            } else {
+                pop_entry(node, pleaf, sp, stk, stride);
+            }
         }
-        if (!next_node(kc, node, sp, stk, stride, S.stack_cap)) break;
     }
     t_hit = bt;
-    return anyhit ? -1 : best;
+    if (anyhit) return found ? best : -1;
+    return best;
 }
 
 // ---------------------------------------------------------------------------

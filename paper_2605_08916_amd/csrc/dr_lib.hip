@@ -1225,13 +1225,19 @@ dr_status dr_scene_create(const dr_scene_desc* desc, int device, dr_scene** out)
                 r.count = make_int4(ccnt[0], ccnt[1], ccnt[2], ccnt[3]);
             }
         }
-        // a visit pushes (inner children hit - 1) entries: the stack never
-        // holds more than the largest sum of that along a root-to-leaf path
+        // Stack bound.  Inner children and postponed leaves share the stack:
+        // a visit that descends pushes at most (children - 1) entries (the
+        // one descended into is not pushed), and a visit that does not
+        // descend pushes at most all its leaves and is followed by a pop.  So
+        // the height never exceeds, over root-to-node paths, the sum of
+        // (children - 1) along the path plus the children of its last node.
         need.assign(dn.size(), 0);
         for (int i = (int)dn.size() - 1; i >= 0; --i) {  // children have larger indices
+            const int4 cc = dn[i].count;
+            const int c = (cc.x >= 0) + (cc.y >= 0) + (cc.z >= 0) + (cc.w >= 0);
             int m = 0;
-            for (int c : kids[i]) m = std::max(m, need[c]);
-            need[i] = (kids[i].empty() ? 0 : (int)kids[i].size() - 1) + m;
+            for (int k : kids[i]) m = std::max(m, need[k]);
+            need[i] = kids[i].empty() ? c : std::max(c, c - 1 + m);
         }
         if (need[0] > DR_STACK) return fail(DR_ERR_UNSUPPORTED, "dr_scene_create: BVH needs a deeper traversal stack than 64");
     }
