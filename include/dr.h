@@ -255,7 +255,7 @@ dr_status dr_stats(dr_chains* c, dr_counters* out, void* hip_stream);
  * 64 x 64 tiles in Morton order, killed chains last, so a wavefront's camera
  * rays and the shadow rays from their hits are coherent; takes precedence
  * over sort_by_length; 2: off).  Zeros keep the current
- * value.  Defaults: 256 threads, 3 blocks per compute unit, 1 chain per pop,
+ * value.  Defaults: 256 threads, 4 blocks per compute unit, 1 chain per pop,
  * 2 lanes per chain when n_chains is below two wavefronts per SIMD
  * (n_cu * 512) else 1, sorting off (it pays only when chains outnumber the
  * resident lanes several times over), refill off, thresholds 50 and 50,

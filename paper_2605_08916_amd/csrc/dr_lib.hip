@@ -1400,7 +1400,7 @@ dr_status dr_chains_init(dr_scene* s, const dr_params* p, uint64_t seed, uint32_
     // two lanes per chain while chains alone cannot fill two wavefronts per
     // SIMD (4 SIMDs per compute unit, 64 lanes per wavefront); one otherwise
     c->launch.lanes_per_chain = (uint64_t)p->n_chains < (uint64_t)c->n_cu * 4 * 64 * 2 ? 2u : 1u;
-    c->launch.blocks_per_cu = 3;
+    c->launch.blocks_per_cu = 4;
     const int N = (int)p->n_chains, L = (int)p->max_path_len, d = 4 * (L - 1);
     c->kp.seed = seed;
     c->kp.N = N;

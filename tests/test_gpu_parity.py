@@ -55,6 +55,8 @@ def _bulk_and_bound(err, tol, bound, frac=0.999):
     shading point, where position rounding is amplified by 1/r^2), within
     `bound`."""
     err = np.asarray(err)
+    if err.size == 0:
+        return
     assert (err <= tol).mean() >= frac, ((err <= tol).mean(), np.sort(err)[-5:])
     assert err.max() <= bound, err.max()
 
@@ -265,6 +267,8 @@ def _compare_step(orc, sc, L, st, gs, os_, idx, seed, step0, k0, dt=1e-5, eps=1e
     assert np.all(werr <= 2 * praw + 1e-5), np.max(werr - 2 * praw)
     if check_score:
         live = m & (os_["killed"] == 0) & (gs["killed"] == 0) & (os_["p"] > 1e-3 * pscale)
+        if not live.any():  # e.g. a single chain that was killed: no score to compare
+            return
         go, gg = os_["score"][:, live], gs["score"][:, live].astype(np.float64)
         err = np.linalg.norm(gg - go, axis=0) / np.maximum(np.linalg.norm(go, axis=0), 1e-6)
         say(f"  score rel err median {np.median(err):.2e} p99 {np.quantile(err, 0.99):.2e}")
@@ -272,7 +276,9 @@ def _compare_step(orc, sc, L, st, gs, os_, idx, seed, step0, k0, dt=1e-5, eps=1e
 
 
 @pytest.mark.parametrize("mode", [dr.DR_MODE_FUSED, dr.DR_MODE_PLAIN])
-@pytest.mark.parametrize("which,L,N", [("tiny", 4, 1000), ("spheres_small", 8, 1500)])
+@pytest.mark.parametrize("which,L,N", [("tiny", 4, 1000), ("spheres_small", 8, 1500),
+                                       # degenerate shapes: one chain, the shortest path (d = 4), ragged counts
+                                       ("tiny", 2, 1), ("tiny", 2, 129), ("spheres_small", 3, 77)])
 def test_one_step_matches_oracle(orc, scenes, which, L, N, mode):
     say(f"[one step] scene={which} L={L} N={N} mode={mode}")
     k0 = 300.0
