@@ -254,13 +254,19 @@ dr_status dr_stats(dr_chains* c, dr_counters* out, void* hip_stream);
  * each launch, order the chains by the screen tile of their film coordinates,
  * 64 x 64 tiles in Morton order, killed chains last, so a wavefront's camera
  * rays and the shadow rays from their hits are coherent; takes precedence
- * over sort_by_length; 2: off).  Zeros keep the current
+ * over sort_by_length; 2: off), and node_cache (the number of top BVH nodes,
+ * stored breadth-first, each block of the straight-line fused kernel copies
+ * into LDS at start, 128 bytes each, at most 512; 1 caches only the root;
+ * DR_NODE_CACHE_AUTO: 341 (five levels) with two lanes per chain, 85 (four
+ * levels) with one; fewer when they would not fit beside the stacks).
+ * Zeros keep the current
  * value.  Defaults: 256 threads, 4 blocks per compute unit, 1 chain per pop,
  * 2 lanes per chain when n_chains is below two wavefronts per SIMD
  * (n_cu * 512) else 1, sorting off (it pays only when chains outnumber the
  * resident lanes several times over), refill off, thresholds 50 and 50,
- * tile ordering off.  The
+ * tile ordering off, automatic node cache.  The
  * form and the order in which chains are processed never change results. */
+#define DR_NODE_CACHE_AUTO 0xFFFFFFFFu
 typedef struct {
     uint32_t block;
     uint32_t blocks_per_cu;
@@ -271,6 +277,7 @@ typedef struct {
     uint32_t refill_event_pct;
     uint32_t refill_advance_pct;
     uint32_t sort_by_tile;
+    uint32_t node_cache;
 } dr_launch_cfg;
 dr_status dr_chains_set_launch(dr_chains* c, const dr_launch_cfg* cfg);
 dr_status dr_chains_get_launch(dr_chains* c, dr_launch_cfg* cfg);

@@ -94,7 +94,17 @@ struct DevScene {
     int stack_cap;   // traversal stack entries per lane (the tree's exact worst case, <= DR_STACK)
     int n_tris;
     int leaf_batch;  // triangles fetched together per leaf iteration: 2 if no leaf holds more, else 4
+    int n_top;       // top nodes the launching kernel holds in LDS (0: none)
 };
+
+// Copies the first S.n_top nodes into the start of the dynamic LDS (all
+// threads of the block call it, before any traversal).
+__device__ __forceinline__ void cache_top_nodes(const DevScene& S) {
+    extern __shared__ float4 s_dyn[];
+    const float4* g = reinterpret_cast<const float4*>(S.nodes);
+    for (int k = threadIdx.x; k < 8 * S.n_top; k += blockDim.x) s_dyn[k] = g[k];
+    __syncthreads();
+}
 struct Cam {
     V3 eye, cu, cv, cw;
 };
@@ -174,8 +184,12 @@ __device__ __forceinline__ bool tri_test(const DevTri& T, V3 o, V3 d, float tmin
     return t > tmin;
 }
 
-__device__ __forceinline__ DevNode load_node(const DevNode* nodes, int i) {
-    const float4* p = reinterpret_cast<const float4*>(nodes + i);
+// The first S.n_top nodes (the top levels: nodes are stored breadth-first)
+// may sit at the start of the kernel's dynamic LDS, copied there by the
+// kernel; every ray starts at the root, so its first visits read LDS.
+__device__ __forceinline__ DevNode load_node(const DevScene& S, int i) {
+    extern __shared__ float4 s_dyn[];
+    const float4* p = i < S.n_top ? s_dyn + 8 * i : reinterpret_cast<const float4*>(S.nodes + i);
     DevNode n;
     n.lox = p[0];
     n.loy = p[1];
@@ -245,7 +259,7 @@ __device__ __forceinline__ bool leaf_tests(const DevScene& S, const DevNode& n, 
 // an any-hit query has found its hit (slot in best).
 __device__ __forceinline__ bool visit_node(const DevScene& S, int node, V3 o, V3 d, const RaySlab& rs, float tmax, bool anyhit,
                                            float& bt, int& best, uint32_t& best_prim, int (&kc)[4], Counters& ctr) {
-    const DevNode n = load_node(S.nodes, node);
+    const DevNode n = load_node(S, node);
     ctr.nodes++;
     // all four boxes are tested without branching (an empty slot's result is
     // masked afterwards), so the node's eight loads issue together
@@ -400,7 +414,7 @@ __device__ int trace(const DevScene& S, V3 o, V3 d, float tmax, bool anyhit, flo
                 }
             }
         } else if (can_visit) {
-            const DevNode n = load_node(S.nodes, node);
+            const DevNode n = load_node(S, node);
             ctr.nodes++;
             float tn[4];
             bool hit[4];

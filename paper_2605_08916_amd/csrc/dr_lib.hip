@@ -329,7 +329,8 @@ template <int L, bool PAIR>
 __device__ __forceinline__ void step_fused_body(const KParams& P, const DevScene& S, const KBufs& B, uint32_t nsteps,
                                                 uint32_t grab, int sorted) {
     extern __shared__ uint32_t s_stack[];
-    uint32_t* stk = s_stack + threadIdx.x;
+    cache_top_nodes(S);  // the top nodes precede the stacks in LDS
+    uint32_t* stk = s_stack + S.n_top * 32 + threadIdx.x;
     const int stride = blockDim.x;
     const int lane = threadIdx.x & 63;
     const bool lead = PAIR ? (lane & 1) == 0 : true;
@@ -865,8 +866,9 @@ struct dr_chains {
     uint64_t seed = 0;
     int n_partials = 0;
     int record = 0, count = 0;
-    dr_launch_cfg launch{256, 2, 1, 2, 0, 0, 50, 50, 0};
+    dr_launch_cfg launch{256, 2, 1, 2, 0, 0, 50, 50, 0, DR_NODE_CACHE_AUTO};
     int n_cu = 256;
+    int lds_limit = 65536;             // bytes of LDS one block may use
     int rows_move = 0, rows_all = 0;  // state rows moved per sorted launch / restored before host access
     bool permuted = false;            // chains may sit outside the slot of their id
 };
@@ -902,8 +904,9 @@ static void launch_init_acc(dim3 g, dim3 b, hipStream_t st, const KParams& P, co
 template <int L>
 static void launch_fused(dim3 g, dim3 b, hipStream_t st, const KParams& P, const DevScene& S, const KBufs& B,
                          uint32_t n, uint32_t grab, bool pair, int sorted) {
-    if (pair) hipLaunchKernelGGL(k_step_fused_pair<L>, g, b, stack_bytes(S, b.x), st, P, S, B, n, grab, sorted);
-    else hipLaunchKernelGGL(k_step_fused<L>, g, b, stack_bytes(S, b.x), st, P, S, B, n, grab, sorted);
+    const size_t lds = stack_bytes(S, b.x) + (size_t)S.n_top * sizeof(DevNode);
+    if (pair) hipLaunchKernelGGL(k_step_fused_pair<L>, g, b, lds, st, P, S, B, n, grab, sorted);
+    else hipLaunchKernelGGL(k_step_fused<L>, g, b, lds, st, P, S, B, n, grab, sorted);
 }
 template <int L>
 static void launch_sm(dim3 g, dim3 b, hipStream_t st, const KParams& P, const DevScene& S, const KBufs& B, uint32_t n,
@@ -982,8 +985,17 @@ static void enqueue_steps(dr_chains* c, uint32_t n_steps, hipStream_t st) {
         const long lanes = (long)N * (pair ? 2 : 1);
         int blocks = (int)(c->n_cu * c->launch.blocks_per_cu);
         blocks = (int)std::max(1L, std::min((long)blocks, (lanes + blk - 1) / blk));
-        DR_DISPATCH_L(P.L, launch_fused, dim3(blocks), dim3(blk), st, P, c->scene->ds, c->kb, n_steps,
-                      c->launch.grab, pair, sorted);
+        DevScene S = c->scene->ds;
+        // automatic: five levels with paired lanes (two blocks per compute
+        // unit hold the chains), four with one lane (three blocks must fit)
+        const uint32_t nc = c->launch.node_cache == DR_NODE_CACHE_AUTO ? (pair ? 341u : 85u) : c->launch.node_cache;
+        S.n_top = (int)std::min<uint32_t>(nc, c->scene->n_nodes);
+        // the cached nodes and the stacks share the block's LDS: fewer nodes if they would not fit
+        const size_t stack_b = stack_bytes(S, blk);
+        if (stack_b + (size_t)S.n_top * sizeof(DevNode) > (size_t)c->lds_limit)
+            S.n_top = (int)(((size_t)c->lds_limit > stack_b ? (size_t)c->lds_limit - stack_b : 0) / sizeof(DevNode));
+        DR_DISPATCH_L(P.L, launch_fused, dim3(blocks), dim3(blk), st, P, S, c->kb, n_steps, c->launch.grab, pair,
+                      sorted);
     } else {
         const int blk = 256;
         const dim3 g((N + blk - 1) / blk), b(blk);
@@ -1185,10 +1197,11 @@ dr_status dr_scene_create(const dr_scene_desc* desc, int device, dr_scene** out)
         } else {
             dn.emplace_back();
             kids.emplace_back();
+            // breadth-first: node indices grow level by level, so the top
+            // levels are the first nodes (the kernels keep those in LDS)
             work.push_back({0, 0});
-            while (!work.empty()) {
-                const Item it = work.back();
-                work.pop_back();
+            for (size_t w = 0; w < work.size(); ++w) {
+                const Item it = work[w];
                 int ch[4];
                 const int k = gather(it.bin, ch);
                 float lo[3][4], hi[3][4];
@@ -1397,6 +1410,11 @@ dr_status dr_chains_init(dr_scene* s, const dr_params* p, uint64_t seed, uint32_
     c->P = *p;
     c->seed = seed;
     c->n_cu = g_num_cu(s->device);
+    {
+        int lim = 0;
+        if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, s->device) == hipSuccess && lim > 0)
+            c->lds_limit = lim;
+    }
     // two lanes per chain while chains alone cannot fill two wavefronts per
     // SIMD (4 SIMDs per compute unit, 64 lanes per wavefront); one otherwise
     c->launch.lanes_per_chain = (uint64_t)p->n_chains < (uint64_t)c->n_cu * 4 * 64 * 2 ? 2u : 1u;
@@ -1644,6 +1662,8 @@ dr_status dr_chains_set_launch(dr_chains* c, const dr_launch_cfg* cfg) {
     if (cfg->sort_by_length > 2) return fail(DR_ERR_INVALID_ARG, "dr_chains_set_launch: sort_by_length must be 0, 1 or 2");
     if (cfg->refill > 2) return fail(DR_ERR_INVALID_ARG, "dr_chains_set_launch: refill must be 0, 1 or 2");
     if (cfg->sort_by_tile > 2) return fail(DR_ERR_INVALID_ARG, "dr_chains_set_launch: sort_by_tile must be 0, 1 or 2");
+    if (cfg->node_cache > 512 && cfg->node_cache != DR_NODE_CACHE_AUTO)
+        return fail(DR_ERR_INVALID_ARG, "dr_chains_set_launch: node_cache must be at most 512 (or automatic)");
     if (cfg->refill_event_pct > 100 || cfg->refill_advance_pct > 100)
         return fail(DR_ERR_INVALID_ARG, "dr_chains_set_launch: refill thresholds are percentages (1..100)");
     if (cfg->block) c->launch.block = cfg->block;
@@ -1653,6 +1673,7 @@ dr_status dr_chains_set_launch(dr_chains* c, const dr_launch_cfg* cfg) {
     if (cfg->sort_by_length) c->launch.sort_by_length = cfg->sort_by_length == 1 ? 1u : 0u;
     if (cfg->refill) c->launch.refill = cfg->refill == 1 ? 1u : 0u;
     if (cfg->sort_by_tile) c->launch.sort_by_tile = cfg->sort_by_tile == 1 ? 1u : 0u;
+    if (cfg->node_cache) c->launch.node_cache = cfg->node_cache;
     if (cfg->refill_event_pct) c->launch.refill_event_pct = cfg->refill_event_pct;
     if (cfg->refill_advance_pct) c->launch.refill_advance_pct = cfg->refill_advance_pct;
     g_err.clear();
