@@ -65,7 +65,7 @@ def parse():
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_fused_spheres53k_traffic.txt")
 KERNEL_SOURCES = ["paper_2605_08916_amd/csrc/dr_lib.hip", "paper_2605_08916_amd/csrc/dr_device.h",
                   "paper_2605_08916_amd/csrc/dr_adjoint.h", "paper_2605_08916_amd/csrc/dr_chain.h",
-                  "paper_2605_08916_amd/build.py"]
+                  "paper_2605_08916_amd/csrc/dr_machine.h", "include/dr.h", "paper_2605_08916_amd/build.py"]
 
 
 def sources_digest():
