@@ -415,12 +415,13 @@ def main():
     cc.close()
 
     # algorithmic bytes per chain-step of the fused kernel: state x and score
-    # read+write, killed flag read+write, path record write+read, BVH nodes
-    # (64 B) and triangles (48 B) fetched by traversal, the material/light
-    # records per vertex, and the 3-channel splat read-modify-write.
+    # read+write, killed flag read+write, path record write+read, 4-wide BVH
+    # nodes (128 B per visit) and triangles (48 B per test) fetched by
+    # traversal, the material/light records per vertex, and the 3-channel
+    # splat read-modify-write.
     verts = rays / 2.0
     b_state = 16 * d + 8 + 8 * (L - 1)
-    b_trav = nodes * 64 + tris * 48
+    b_trav = nodes * 128 + tris * 48
     b_shade = verts * (48 + 48 + 80)
     b_splat = 24
     bytes_step = b_state + b_trav + b_shade + b_splat
