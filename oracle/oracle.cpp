@@ -40,6 +40,7 @@
 #include <cstring>
 #include <memory>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 namespace orc {
@@ -419,8 +420,14 @@ static const double LUM[3] = {0.2126, 0.7152, 0.0722};
 template <class T>
 static void path_eval(const Scene& S, int L, const T* u, PathRec& rec, bool replay, T f[3]) {
     for (int c = 0; c < 3; ++c) f[c] = T(0.0);
-    if (!replay)
+    if (!replay) {
         for (int j = 0; j < L - 1; ++j) { rec.prim[j] = -1; rec.nee[j] = 0xFFFFFFFFu; }
+        // a point with a non-finite coordinate (a state that left the torus)
+        // has f = 0: its tour is killed and regenerates
+        if constexpr (std::is_same<T, double>::value)
+            for (int i = 0; i < 4 * (L - 1); ++i)
+                if (!std::isfinite(u[i])) return;
+    }
     const int nl = (int)S.lights.size();
 
     // camera ray

@@ -560,7 +560,7 @@ __device__ __forceinline__ bool bsdf_sample(const Material& m, V3 n, V3 wo, floa
 __device__ __forceinline__ int select_light(float a, int nl, float& ap) {
     const float sel = a * (float)nl;
     int li = (int)floorf(sel);
-    if (li > nl - 1) li = nl - 1;
+    li = min(max(li, 0), nl - 1);
     ap = a * (float)nl - (float)li;
     return li;
 }
@@ -616,10 +616,31 @@ __device__ __forceinline__ void trace_vertex_rays(const DevScene& S, V3 x, bool 
     }
 }
 
+// True when every coordinate of the point is finite (accessors over generated
+// coordinates skip the check).
+template <class U>
+__device__ __forceinline__ bool point_finite(const U& u, int d) {
+    if constexpr (U::kChecked) {
+        bool ok = true;
+        for (int i = 0; i < d; ++i) ok &= isfinite(u(i));
+        return ok;
+    } else {
+        return true;
+    }
+}
+
 template <bool PAIR, class U>
 __device__ V3 path_forward(const DevScene& S, int L, const U& u, uint32_t* rec, int rs, uint32_t* stk, int stride,
                            Counters& ctr, int* nverts = nullptr) {
     V3 f = v3(0.f, 0.f, 0.f);
+    // a point with a non-finite coordinate (a state that left the torus) has
+    // f = 0: its tour is killed and regenerates
+    if (!point_finite(u, 4 * (L - 1))) {
+        if (nverts) *nverts = 0;
+        if (rec)
+            for (int j = 1; j <= L - 1; ++j) rec[(j - 1) * rs] = DR_NO_VERTEX;
+        return f;
+    }
     const Cam C = load_cam(S);
     V3 d = camera_dir(C, u(0), u(1));
     float t;
@@ -697,6 +718,7 @@ __device__ V3 path_forward(const DevScene& S, int L, const U& u, uint32_t* rec, 
 
 // Coordinate accessors
 struct SoaU {  // chain state: coordinate i at p[i * stride]
+    static constexpr bool kChecked = true;
     const float* p;
     int stride;
     __device__ __forceinline__ float operator()(int i) const { return p[(size_t)i * stride]; }

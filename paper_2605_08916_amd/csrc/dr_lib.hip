@@ -617,6 +617,7 @@ __global__ void k_resolve(const float* accum, float* img, size_t npx, const doub
 
 // Path evaluation for n points (row-major n x d): f, log(p + eps), score, record.
 struct RowU {
+    static constexpr bool kChecked = true;
     const float* p;
     __device__ __forceinline__ float operator()(int i) const { return p[i]; }
 };
@@ -722,7 +723,8 @@ __global__ void __launch_bounds__(256) k_eval_sm(DevScene S, const float* u, int
 }
 
 // Independent path tracing, one thread per pixel.
-struct PtU {
+struct PtU {  // generated coordinates: always finite
+    static constexpr bool kChecked = false;
     uint64_t seed;
     uint32_t pix;
     uint64_t k;

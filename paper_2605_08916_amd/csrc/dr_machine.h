@@ -150,6 +150,11 @@ __device__ __forceinline__ bool sm_event(const DevScene& S, const Cam& C, const 
                                          const Rec& rec, Counters& ctr) {
     if (P.phase == PH_NEW) {
         P.f = v3(0.f, 0.f, 0.f);
+        if (!point_finite(u, 4 * (L - 1))) {  // as path_forward: f = 0, nothing traced
+            P.nv = 0;
+            rec.finish(P.f, 0);
+            return false;
+        }
         P.d = camera_dir(C, u(0), u(1));
         P.j = 1;
         P.phase = PH_CAM;

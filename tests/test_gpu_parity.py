@@ -449,6 +449,47 @@ def test_counters_and_scene_change(scenes):
     ch.step(1)
 
 
+@pytest.mark.parametrize("lanes", [1, 2])
+def test_non_finite_state_is_killed_and_regenerated(scenes, lanes):
+    """A chain whose position or score holds NaN or Inf evaluates to p = 0 at
+    its next step (nothing traced), is killed, and regenerates at the step
+    after; the frame buffer stays finite and every other chain is exactly what
+    it is in a clean run."""
+    S = dr.Scene(scenes["spheres_small"])
+    N, L = 2000, 8
+    bad = [5, 9, 11, 700]
+    runs = []
+    for inject in (False, True):
+        ch = dr.Chains(S, N, L, 23, k0=250.0)
+        ch.set_launch(lanes_per_chain=lanes)
+        ch.step(2)
+        st = ch.read_state()
+        x, sc, killed = st["x"].copy(), st["score"].copy(), st["killed"].copy()
+        if inject:
+            x[:, 5] = np.nan        # the whole position
+            x[7, 9] = np.inf        # one coordinate
+            sc[3, 11] = np.nan      # the score: the move carries it into x
+            x[2, 700] = np.nan      # the light block of the first vertex only
+            killed[bad] = 0
+        ch.write_state(x=x, score=sc, killed=killed, accum=st["accum"], step=st["step"],
+                       tour_count=st["tour_count"], k0=st["k0"])
+        ch.set_record(True)
+        ch.step(1)
+        a = ch.read_state()
+        ch.step(1)
+        b = ch.read_state()
+        runs.append((a, b))
+    (a0, b0), (a1, b1) = runs
+    say(f"[non-finite] lanes={lanes} killed {a1['killed'][bad]} p {a1['p'][bad]}")
+    assert a1["killed"][bad].all() and np.all(a1["p"][bad] == 0)
+    assert np.all(np.isfinite(b1["x"])) and np.all((b1["x"] >= 0) & (b1["x"] < 1))
+    assert np.all(np.isfinite(a1["accum"])) and np.all(np.isfinite(b1["accum"]))
+    good = np.setdiff1d(np.arange(N), bad)
+    for u, v in ((a0, a1), (b0, b1)):
+        assert np.array_equal(u["x"][:, good], v["x"][:, good])
+        assert np.array_equal(u["killed"][good], v["killed"][good])
+
+
 def test_scene_stats(scenes):
     """The device scene reports its size and the exact traversal stack bound
     its kernels reserve in LDS."""

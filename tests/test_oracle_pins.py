@@ -503,3 +503,35 @@ def test_bias_drift_is_the_chain_move(orc):
     se = math.sqrt(dt * sigma2 / N)
     assert np.all(np.abs(disp.mean(axis=1) - dt * b) < 5 * se)
     assert abs(dt * b[1] - dt * 0.5 * sigma2 * s[1]) > 10 * se  # the rotation is resolved
+
+
+def test_non_finite_state_is_killed_and_regenerated(orc):
+    """A point with a non-finite coordinate has f = 0 (nothing traced), so a
+    chain whose state left the torus is killed at its next step and
+    regenerates at the one after; the frame buffer stays finite."""
+    sc = inputs.cornell_tiny()
+    S = orc.Scene(sc)
+    L, d = 4, 12
+    u = inputs.random_points(d, 4, seed=2).astype(np.float64)
+    u[1, 5] = np.nan
+    u[2, 0] = np.inf
+    f, p, score, rec = S.path_eval(L, u)
+    assert np.all(f[1:3] == 0) and np.all(p[1:3] == 0) and np.all(np.isfinite(score))
+    N = 64
+    C = orc.Chains.scene(S, L, N, seed=3, k0=250.0)
+    C.init(nthreads=2)
+    st = C.state()
+    x = st["x"].astype(np.float32)
+    x[:, 5] = np.nan
+    x[7, 9] = np.inf
+    sc_ = st["score"].astype(np.float32)
+    sc_[3, 11] = np.nan
+    killed = np.zeros(N, np.uint32)
+    C.set_state(x, sc_, killed, step=(1 << 32) + 1, k0=250.0)
+    C.step(1, nthreads=2)
+    a = C.state()
+    assert a["killed"][[5, 9, 11]].all() and np.all(a["p"][[5, 9, 11]] == 0)
+    C.step(1, nthreads=2)
+    b = C.state()
+    assert np.all(np.isfinite(b["x"])) and np.all((b["x"] >= 0) & (b["x"] < 1))
+    assert np.all(np.isfinite(C.accum()["accum"]))
