@@ -490,6 +490,26 @@ def test_non_finite_state_is_killed_and_regenerated(scenes, lanes):
         assert np.array_equal(u["killed"][good], v["killed"][good])
 
 
+def test_all_black_initialisation(scenes):
+    """With every emitter off, p_lambda = 0 at initialisation: k0 falls back to
+    eps/(m dt), tours end, and the resolved image is exactly zero."""
+    sc = dict(scenes["tiny"])
+    sc["materials"] = sc["materials"].copy()
+    sc["materials"][:, 8:11] = 0.0
+    sc["lights"] = sc["lights"].copy()
+    sc["lights"][:, 9:12] = 0.0
+    S = dr.Scene(sc)
+    ch = dr.Chains(S, 1000, 4, 3)
+    ch.step(3)
+    st = ch.read_state()
+    say(f"[all black] k0 {st['k0']} p_lambda {st['p_lambda_hat']} tours {st['tour_count']}")
+    assert st["p_lambda_hat"] == 0.0
+    assert st["k0"] == pytest.approx(1e-8 / (64 * 1e-5), rel=1e-6)
+    assert st["tour_count"] > 0
+    img, _ = ch.image_read()
+    assert np.all(img == 0)
+
+
 def test_scene_stats(scenes):
     """The device scene reports its size and the exact traversal stack bound
     its kernels reserve in LDS."""

@@ -535,3 +535,27 @@ def test_non_finite_state_is_killed_and_regenerated(orc):
     b = C.state()
     assert np.all(np.isfinite(b["x"])) and np.all((b["x"] >= 0) & (b["x"] < 1))
     assert np.all(np.isfinite(C.accum()["accum"]))
+
+
+def _black(sc):
+    """The scene with every emitter switched off (p = 0 everywhere)."""
+    sc = dict(sc)
+    sc["materials"] = sc["materials"].copy()
+    sc["materials"][:, 8:11] = 0.0
+    sc["lights"] = sc["lights"].copy()
+    sc["lights"][:, 9:12] = 0.0
+    return sc
+
+
+def test_all_black_initialisation(orc):
+    """p_lambda = 0 at initialisation: k0 falls back to eps/(m dt) (reading
+    A6), so tours end at rate 1/(m dt), and the image stays exactly zero."""
+    S = orc.Scene(_black(inputs.cornell_tiny()))
+    C = orc.Chains.scene(S, 4, 128, seed=3)
+    C.init(nthreads=2)
+    C.step(3, nthreads=2)
+    acc = C.accum()
+    assert acc["p_lambda_hat"] == 0.0
+    assert acc["k0"] == pytest.approx(1e-8 / (64 * 1e-5), rel=1e-12)
+    assert acc["tour_count"] > 0
+    assert np.all(acc["accum"] == 0) and np.all(C.resolve() == 0)
