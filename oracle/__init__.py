@@ -73,6 +73,10 @@ def lib():
         L.orc_bsdf_sample.argtypes = [F, D, D, C.c_double, C.c_double, D, D]
         L.orc_bsdf_sample.restype = C.c_int
         L.orc_bsdf_eval.argtypes = [F, D, D, D, D]
+        L.orc_delta_sample.argtypes = [F, D, C.c_int, D, C.c_double, D, D]
+        L.orc_delta_sample.restype = C.c_int
+        L.orc_fresnel_dielectric.argtypes = [C.c_double, C.c_double]
+        L.orc_fresnel_dielectric.restype = C.c_double
         L.orc_onb.argtypes = [D, D, D]
         L.orc_ggx_d.argtypes = [C.c_double, C.c_double]
         L.orc_ggx_d.restype = C.c_double
@@ -205,6 +209,22 @@ def bsdf_sample(mat, n, wo, u, v):
     ok = lib().orc_bsdf_sample(_p(m, C.c_float), _p(n, C.c_double), _p(wo, C.c_double), u, v, _p(wi, C.c_double),
                                _p(wt, C.c_double))
     return bool(ok), wi, wt
+
+
+def delta_sample(mat, n, front, wo, u):
+    """Delta lobe of a smooth conductor or dielectric: (lobe, wi, weight)."""
+    m = np.ascontiguousarray(mat, np.float32)
+    n = np.ascontiguousarray(n, np.float64)
+    wo = np.ascontiguousarray(wo, np.float64)
+    wi = np.zeros(3)
+    wt = np.zeros(3)
+    lobe = lib().orc_delta_sample(_p(m, C.c_float), _p(n, C.c_double), 1 if front else 0, _p(wo, C.c_double), u,
+                                  _p(wi, C.c_double), _p(wt, C.c_double))
+    return int(lobe), wi, wt
+
+
+def fresnel_dielectric(ci: float, etap: float) -> float:
+    return lib().orc_fresnel_dielectric(ci, etap)
 
 
 def bsdf_eval(mat, n, wo, wi):

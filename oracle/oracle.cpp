@@ -10,10 +10,12 @@
 //   * Philox4x32-10 counter-based generator [Sec. 4.3, the tour state's rng;
 //     generator of Salmon et al. 2011] and the uniform / Gaussian /
 //     exponential draws built on it.
-//   * f(u): a primary-sample-space path sampler (camera, Lambertian and GGX
-//     conductor surfaces, quad area lights with next-event estimation).  The
-//     paper does not specify its sampler; the definition used here is the
-//     one written out in the design notes (readings A1, A10, A13-A15).
+//   * f(u): a primary-sample-space path sampler (camera, Lambertian, GGX
+//     conductor, smooth conductor and smooth dielectric surfaces [Sec. 6, the
+//     material set of the test scenes], quad area lights with next-event
+//     estimation).  The paper does not specify its sampler; the definition
+//     used here is the one written out in the design notes (readings A1,
+//     A10, A13-A15, A24).
 //   * score = grad_u ln(p(u) + eps) by forward-mode dual numbers over the
 //     taken path (discrete choices held fixed) [Sec. 5, Langevin drift].
 //   * The Diffusion Restore chain: initialise / evolve / resolve
@@ -27,9 +29,9 @@
 //   * An analytic wrapped-Gaussian-mixture target on the torus, used to pin
 //     the chain's estimator against closed forms.
 //
-// Precision: FP64 everywhere, except the three decisions that map a float to
-// an integer (pixel index, light index, kill), which are taken in FP32 exactly
-// as the GPU kernels take them.
+// Precision: FP64 everywhere, except the decisions that map a float to an
+// integer (pixel index, light index, kill, reflect-or-refract), which are
+// taken in FP32 as the GPU kernels take them.
 //
 // Built with: g++ -O2 -std=c++17 -ffp-contract=off -fPIC -shared -pthread
 
@@ -149,12 +151,14 @@ static inline V3<double> vald(const V3<double>& a) { return a; }
 // Scene: triangles, materials, quad lights, pinhole camera.
 // ----------------------------------------------------------------------------
 struct Material {
-    int kind;            // 0 Lambertian, 1 GGX conductor
+    int kind;            // 0 Lambertian, 1 GGX conductor, 2 smooth conductor, 3 smooth dielectric
     double albedo[3];
     double rough;        // GGX alpha
-    double f0[3];        // Schlick normal-incidence reflectance
+    double f0[3];        // Schlick normal-incidence reflectance (conductors)
     double Le[3];        // emitted radiance (emitter triangles)
+    double eta;          // dielectric: index of refraction of the inside (the side opposite e1 x e2)
 };
+static inline bool is_delta(const Material& m) { return m.kind >= 2; }
 struct Light {
     V3<double> p0, e1, e2, n;  // parallelogram p0 + a e1 + b e2, unit normal e1 x e2
     double area;
@@ -402,15 +406,66 @@ static bool bsdf_sample(const Material& m, const V3<double>& n, const V3<T>& wo,
     return true;
 }
 
+// Fresnel reflectance of a smooth dielectric interface for unpolarised light
+// (the Fresnel equations: the mean of the squared s- and p-amplitude ratios).
+// ci = cosine on the incident side, etap = n_transmitted / n_incident.  Returns
+// 1 under total internal reflection; ct is the transmitted cosine.
+template <class T> static T fresnel_dielectric(const T& ci, double etap, T& ct) {
+    T sin2_t = (1.0 - ci * ci) / (etap * etap);
+    if (val(sin2_t) >= 1.0) {
+        ct = T(0.0);
+        return T(1.0);
+    }
+    ct = sqrt(1.0 - sin2_t);
+    T rs = (ci - etap * ct) / (ci + etap * ct);  // n_i cos_i vs n_t cos_t, over n_i
+    T rp = (etap * ci - ct) / (etap * ci + ct);  // n_t cos_i vs n_i cos_t, over n_i
+    return 0.5 * (rs * rs + rp * rp);
+}
+
+// Delta (specular) lobes.  n faces wo; `front` says wo lies on the e1 x e2
+// side (outside a dielectric).  Smooth conductor: mirror direction, weight
+// Schlick's F at the incidence cosine.  Smooth dielectric: the coordinate u
+// picks reflection when u < F (in FP32, as the kernels decide), else
+// refraction by Snell's law; the weights are F/F = 1 and, for refraction,
+// (1-F)/(1-F) divided by etap^2 (radiance is compressed into the denser
+// medium).  lobe = 0 reflection, 1 refraction.
+template <class T>
+static void delta_sample(const Material& m, const V3<double>& n, bool front, const V3<T>& wo, const T& u, V3<T>& wi,
+                         T weight[3], int& lobe) {
+    V3<T> nn = lift<T>(n);
+    T ci = dot(nn, wo);
+    lobe = 0;
+    if (m.kind == 2) {
+        wi = nn * (2.0 * ci) - wo;
+        T one_m = 1.0 - ci;
+        T f5 = one_m * one_m * one_m * one_m * one_m;
+        for (int c = 0; c < 3; ++c) weight[c] = m.f0[c] + (1.0 - m.f0[c]) * f5;
+        return;
+    }
+    const double etap = front ? m.eta : 1.0 / m.eta;
+    T ct;
+    T F = fresnel_dielectric(ci, etap, ct);
+    if ((float)val(u) < (float)val(F)) {
+        wi = nn * (2.0 * ci) - wo;
+        for (int c = 0; c < 3; ++c) weight[c] = T(1.0);
+        return;
+    }
+    lobe = 1;
+    wi = wo * (-1.0 / etap) + nn * (ci / etap - ct);
+    for (int c = 0; c < 3; ++c) weight[c] = T(1.0 / (etap * etap));
+}
+
 // ----------------------------------------------------------------------------
 // The path sampler f(u) (reading A1).  d = 4(L-1); block 0 = film; vertex j
 // (1..L-1) uses light block (u[4j-2], u[4j-1]) and, for j <= L-2, BSDF block
-// (u[4j], u[4j+1]).  Emission only at the primary hit; next-event estimation
-// at every vertex; no MIS, no Russian roulette.
+// (u[4j], u[4j+1]).  Emission at the primary hit and at a vertex reached from
+// a delta (specular) vertex; next-event estimation at every non-delta vertex;
+// no MIS, no Russian roulette (readings A1, A24).
 // ----------------------------------------------------------------------------
 struct PathRec {
     // per vertex j = 1..L-1: triangle index (or -1), and light code
-    // (light << 1 | contributed) or 0xFFFFFFFF when the vertex does not exist
+    // (light << 1 | contributed; at a delta vertex lobe << 1) or 0xFFFFFFFF
+    // when the vertex does not exist
     int prim[32];
     uint32_t nee[32];
 };
@@ -449,6 +504,7 @@ static void path_eval(const Scene& S, int L, const T* u, PathRec& rec, bool repl
     V3<double> ng = normalize(nw);
     double side = dot(ng, vald(d));
     V3<double> n = side > 0 ? ng * -1.0 : ng;
+    bool front = !(side > 0);
     {
         const Material& m = S.mats[S.tmat[prim]];
         if (dot(nw, vald(d)) < 0.0)
@@ -459,8 +515,10 @@ static void path_eval(const Scene& S, int L, const T* u, PathRec& rec, bool repl
     for (int j = 1; j <= L - 1; ++j) {
         const Material& m = S.mats[S.tmat[prim]];
         V3<T> wo = d * -1.0;
-        // ---- next-event estimation at vertex j
-        {
+        // ---- next-event estimation at vertex j (none at a delta vertex:
+        // its BSDF is zero for every light sample)
+        if (!replay && is_delta(m)) rec.nee[j - 1] = 0;
+        if (!is_delta(m)) {
             const T& a = u[4 * j - 2];
             const T& b = u[4 * j - 1];
             // light selection: FP32 decision, as on the device
@@ -498,7 +556,13 @@ static void path_eval(const Scene& S, int L, const T* u, PathRec& rec, bool repl
         // ---- BSDF sampling and the next vertex
         V3<T> wi;
         T wgt[3];
-        if (!bsdf_sample<T>(m, n, wo, u[4 * j], u[4 * j + 1], wi, wgt)) break;
+        if (is_delta(m)) {
+            int lobe;
+            delta_sample<T>(m, n, front, wo, u[4 * j], wi, wgt, lobe);
+            if (!replay) rec.nee[j - 1] = (uint32_t)lobe << 1;
+        } else if (!bsdf_sample<T>(m, n, wo, u[4 * j], u[4 * j + 1], wi, wgt)) {
+            break;
+        }
         for (int c = 0; c < 3; ++c) beta[c] = beta[c] * wgt[c];
         int nprim;
         if (!replay) {
@@ -513,8 +577,16 @@ static void path_eval(const Scene& S, int L, const T* u, PathRec& rec, bool repl
         x = x + wi * tn;
         d = wi;
         prim = nprim;
-        V3<double> ng2 = normalize(cross(S.vert(prim, 1) - S.vert(prim, 0), S.vert(prim, 2) - S.vert(prim, 0)));
-        n = dot(ng2, vald(d)) > 0 ? ng2 * -1.0 : ng2;
+        V3<double> nw2 = cross(S.vert(prim, 1) - S.vert(prim, 0), S.vert(prim, 2) - S.vert(prim, 0));
+        V3<double> ng2 = normalize(nw2);
+        front = !(dot(ng2, vald(d)) > 0);
+        n = front ? ng2 : ng2 * -1.0;
+        // emission seen through a delta vertex (next-event estimation cannot
+        // reach it): the emitter's radiance times the throughput
+        if (is_delta(m) && dot(nw2, vald(d)) < 0.0) {
+            const Material& me = S.mats[S.tmat[prim]];
+            for (int c = 0; c < 3; ++c) f[c] = f[c] + beta[c] * me.Le[c];
+        }
     }
 }
 
@@ -803,9 +875,19 @@ double orc_uniform(uint64_t seed, uint32_t chain, uint64_t step, uint32_t tag, u
 
 void orc_box_muller(double u0, double u1, double* z) { box_muller(u0, u1, z[0], z[1]); }
 
-// materials: nm x 11 floats (kind, albedo[3], roughness, f0[3], Le[3])
+// materials: nm x 12 floats (kind, albedo[3], roughness, f0[3], Le[3], eta)
 // lights:    nl x 12 floats (p0[3], e1[3], e2[3], Le[3])
 // camera:    10 floats (eye[3], at[3], up[3], vfov_deg)
+// One material from its 12 floats (kind, albedo[3], roughness, f0[3], Le[3], eta).
+static Material mat_from(const float* q) {
+    Material m;
+    m.kind = (int)q[0];
+    for (int c = 0; c < 3; ++c) { m.albedo[c] = q[1 + c]; m.f0[c] = q[5 + c]; m.Le[c] = q[8 + c]; }
+    m.rough = q[4];
+    m.eta = q[11];
+    return m;
+}
+
 void* orc_scene_new(const float* V, int nv, const uint32_t* I, int nt, const uint32_t* tmat, const float* mats, int nm,
                     const float* lights, int nl, const float* cam, int W, int H, int brute) {
     auto* S = new Scene();
@@ -814,12 +896,7 @@ void* orc_scene_new(const float* V, int nv, const uint32_t* I, int nt, const uin
     S->idx.assign(I, I + 3 * (size_t)nt);
     S->tmat.assign(tmat, tmat + nt);
     for (int i = 0; i < nm; ++i) {
-        const float* q = mats + 11 * i;
-        Material m;
-        m.kind = (int)q[0];
-        for (int c = 0; c < 3; ++c) { m.albedo[c] = q[1 + c]; m.f0[c] = q[5 + c]; m.Le[c] = q[8 + c]; }
-        m.rough = q[4];
-        S->mats.push_back(m);
+        S->mats.push_back(mat_from(mats + 12 * i));
     }
     for (int i = 0; i < nl; ++i) {
         const float* q = lights + 12 * i;
@@ -899,14 +976,6 @@ void orc_path_eval(void* s, int L, int n, const double* u, double eps, double* f
     });
 }
 
-// BSDF helpers for the material pins.  mat: 11 floats as in orc_scene_new.
-static Material mat_from(const float* q) {
-    Material m;
-    m.kind = (int)q[0];
-    for (int c = 0; c < 3; ++c) { m.albedo[c] = q[1 + c]; m.f0[c] = q[5 + c]; m.Le[c] = q[8 + c]; }
-    m.rough = q[4];
-    return m;
-}
 int orc_bsdf_sample(const float* mat, const double* n, const double* wo, double u, double v, double* wi,
                     double* weight) {
     Material m = mat_from(mat);
@@ -916,6 +985,20 @@ int orc_bsdf_sample(const float* mat, const double* n, const double* wo, double 
     wi[0] = w.x; wi[1] = w.y; wi[2] = w.z;
     for (int c = 0; c < 3; ++c) weight[c] = ok ? wt[c] : 0.0;
     return ok ? 1 : 0;
+}
+// Delta lobe sample (mat: a smooth conductor or dielectric); returns the lobe.
+int orc_delta_sample(const float* mat, const double* n, int front, const double* wo, double u, double* wi,
+                     double* weight) {
+    Material m = mat_from(mat);
+    V3<double> nn = {n[0], n[1], n[2]}, o = {wo[0], wo[1], wo[2]}, w;
+    int lobe;
+    delta_sample<double>(m, nn, front != 0, o, u, w, weight, lobe);
+    wi[0] = w.x; wi[1] = w.y; wi[2] = w.z;
+    return lobe;
+}
+double orc_fresnel_dielectric(double ci, double etap) {
+    double ct;
+    return fresnel_dielectric<double>(ci, etap, ct);
 }
 void orc_bsdf_eval(const float* mat, const double* n, const double* wo, const double* wi, double* fs) {
     Material m = mat_from(mat);

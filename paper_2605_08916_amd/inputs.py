@@ -8,8 +8,10 @@ A scene is a dict of numpy arrays:
   vertices     (V, 3) float32
   indices      (T, 3) uint32
   tri_material (T,)   uint32
-  materials    (M, 11) float32: kind (0 Lambertian, 1 GGX conductor),
-               albedo[3], roughness (GGX alpha), f0[3], Le[3]
+  materials    (M, 12) float32: kind (0 Lambertian, 1 GGX conductor,
+               2 smooth conductor, 3 smooth dielectric), albedo[3],
+               roughness (GGX alpha), f0[3], Le[3], eta (dielectric index
+               of refraction on the side opposite e1 x e2)
   lights       (NL, 12) float32: parallelogram p0[3], e1[3], e2[3], Le[3];
                it emits on the side of e1 x e2 and also appears in the mesh
                as two triangles wound the same way with an emissive material
@@ -26,11 +28,12 @@ import math
 
 import numpy as np
 
-KIND_LAMBERT, KIND_GGX = 0, 1
+KIND_LAMBERT, KIND_GGX, KIND_MIRROR, KIND_GLASS = 0, 1, 2, 3
 
 
-def material(kind=KIND_LAMBERT, albedo=(0.5, 0.5, 0.5), rough=0.0, f0=(0.0, 0.0, 0.0), Le=(0.0, 0.0, 0.0)):
-    return [float(kind), *map(float, albedo), float(rough), *map(float, f0), *map(float, Le)]
+def material(kind=KIND_LAMBERT, albedo=(0.5, 0.5, 0.5), rough=0.0, f0=(0.0, 0.0, 0.0), Le=(0.0, 0.0, 0.0),
+             eta=1.5):
+    return [float(kind), *map(float, albedo), float(rough), *map(float, f0), *map(float, Le), float(eta)]
 
 
 class _Builder:
@@ -125,6 +128,72 @@ def cornell_tiny(seed: int = 1, width: int = 64, height: int = 64) -> dict:
     sc = B.finish(cam, width, height, "cornell_tiny")
     assert sc["indices"].shape[0] == 32
     return sc
+
+
+def specular_box(seed: int = 2, width: int = 64, height: int = 64, subdiv: int = 2) -> dict:
+    """Cornell-style box with the delta materials: a smooth-dielectric
+    icosphere (eta 1.5, outward winding), a tall box of smooth conductor
+    (f0 per channel U[0.6, 0.95]) and a smooth-conductor back wall panel, so
+    that paths run through glass (caustics on the floor, total internal
+    reflection) and chains of mirror bounces.  Walls Lambertian, albedo per
+    channel U[0.3, 0.8]; ceiling light of radiance 15."""
+    rng = np.random.default_rng(seed)
+    B = _Builder()
+
+    def lam():
+        return B.add_material(material(KIND_LAMBERT, albedo=rng.uniform(0.3, 0.8, 3)))
+
+    B.add_quad([0, 0, 0], [1, 0, 0], [0, 0, 1], lam())     # floor
+    B.add_quad([0, 1, 0], [0, 0, 1], [1, 0, 0], lam())     # ceiling
+    B.add_quad([0, 0, 0], [0, 1, 0], [1, 0, 0], lam())     # back wall
+    B.add_quad([0, 0, 0], [0, 0, 1], [0, 1, 0], lam())     # left wall
+    B.add_quad([1, 0, 0], [0, 1, 0], [0, 0, 1], lam())     # right wall
+    mirror = B.add_material(material(KIND_MIRROR, f0=rng.uniform(0.6, 0.95, 3)))
+    B.add_quad([0.55, 0.1, 0.001], [0, 0.6, 0], [0.35, 0, 0], mirror)   # panel on the back wall, facing +z
+    metal = B.add_material(material(KIND_MIRROR, f0=rng.uniform(0.6, 0.95, 3)))
+    for q in _box_faces((0.72, 0.25, 0.35), (0.2, 0.5, 0.2), 20.0):
+        B.add_mesh(np.stack(q), [[0, 1, 2], [0, 2, 3]], metal)
+    glass = B.add_material(material(KIND_GLASS, eta=1.5))
+    V, F = icosphere(subdiv)
+    B.add_mesh(V * 0.17 + np.array([0.33, 0.17, 0.6]), F, glass)
+    B.add_light([0.4, 0.999, 0.4], [0.2, 0, 0], [0, 0, 0.2], (15.0, 15.0, 15.0))
+    cam = [0.5, 0.5, 2.2, 0.5, 0.5, 0.0, 0.0, 1.0, 0.0, 40.0]
+    return B.finish(cam, width, height, "specular_box")
+
+
+def mirror_plane(f0=(0.9, 0.6, 0.3), Le=(4.0, 3.0, 2.0), width: int = 16, height: int = 16) -> dict:
+    """A smooth-conductor square in the plane z = -1 (side 4, centred) facing
+    +z; a quad light in the plane z = 1 facing -z (towards the mirror); the
+    camera at the origin looking down -z.  The light is seen only through the
+    mirror (used to pin the delta lobes)."""
+    B = _Builder()
+    m = B.add_material(material(KIND_MIRROR, f0=f0))
+    B.add_quad([-2, -2, -1], [4, 0, 0], [0, 4, 0], m)               # e1 x e2 = +z
+    B.add_light([-0.3, -0.2, 1.0], [0, 0.5, 0], [0.7, 0, 0], Le)    # e1 x e2 = -z
+    cam = [0.0, 0.0, 0.0, 0.0, 0.0, -1.0, 0.0, 1.0, 0.0, 60.0]
+    return B.finish(cam, width, height, "mirror_plane")
+
+
+def glass_slab(eta: float = 1.5, Le=(4.0, 3.0, 2.0), thickness: float = 0.5, width: int = 16,
+               height: int = 16, eye_z: float = 0.0) -> dict:
+    """A closed smooth-dielectric slab between the planes z = -1 and
+    z = -1 - thickness (side 4, outward winding: two faces and four thin
+    sides), a quad light in the plane z = -3 facing +z, the camera at
+    (0, 0, eye_z) looking down -z (above the slab by default; inside it for
+    eye_z in (-1 - thickness, -1)).  Rays reach the light only through the
+    slab's lower face."""
+    B = _Builder()
+    g = B.add_material(material(KIND_GLASS, eta=eta))
+    z0, z1, h = -1.0, -1.0 - thickness, 2.0
+    B.add_quad([-h, -h, z0], [2 * h, 0, 0], [0, 2 * h, 0], g)             # top face, normal +z
+    B.add_quad([-h, -h, z1], [0, 2 * h, 0], [2 * h, 0, 0], g)             # bottom face, normal -z
+    B.add_quad([-h, -h, z1], [2 * h, 0, 0], [0, 0, thickness], g)         # y = -h, normal -y
+    B.add_quad([-h, h, z1], [0, 0, thickness], [2 * h, 0, 0], g)          # y = +h, normal +y
+    B.add_quad([-h, -h, z1], [0, 0, thickness], [0, 2 * h, 0], g)         # x = -h, normal -x
+    B.add_quad([h, -h, z1], [0, 2 * h, 0], [0, 0, thickness], g)          # x = +h, normal +x
+    B.add_light([-1.5, -1.5, -3.0], [3.0, 0, 0], [0, 3.0, 0], Le)         # e1 x e2 = +z
+    cam = [0.0, 0.0, eye_z, 0.0, 0.0, eye_z - 1.0, 0.0, 1.0, 0.0, 60.0]
+    return B.finish(cam, width, height, "glass_slab")
 
 
 def white_furnace(albedo: float = 0.5, Le: float = 1.0, width: int = 8, height: int = 8) -> dict:

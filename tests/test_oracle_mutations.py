@@ -31,6 +31,16 @@ MUTANTS = [
     ("box_muller_radius", "std::sqrt(-2.0 * std::log(1.0 - u0))", "std::sqrt(-std::log(1.0 - u0))",
      "test_box_muller_and_exponential_moments"),
     ("dual_sqrt", "r.g[i] = a.g[i] / (2.0 * r.v);", "r.g[i] = a.g[i] / r.v;", "test_score_matches_finite_differences"),
+    ("snell_direction", "wi = wo * (-1.0 / etap) + nn * (ci / etap - ct);", "wi = wo * (-1.0 / etap) + nn * (ci - ct);",
+     "test_dielectric_lobe"),
+    ("fresnel_parallel", "T rp = (etap * ci - ct) / (etap * ci + ct);", "T rp = (ci - etap * ct) / (ci + etap * ct);",
+     "test_dielectric_fresnel_fixed_points"),
+    ("radiance_eta", "weight[c] = T(1.0 / (etap * etap));", "weight[c] = T(1.0);",
+     "test_radiance_seen_from_inside_the_dielectric"),
+    ("leaving_index", "const double etap = front ? m.eta : 1.0 / m.eta;", "const double etap = m.eta;",
+     "test_glass_slab_branches"),
+    ("mirror_schlick", "T one_m = 1.0 - ci;", "T one_m = ci;", "test_mirror_lobe"),
+    ("delta_emission", "if (is_delta(m) && dot(nw2, vald(d)) < 0.0) {", "if (false) {", "test_mirror_plane_closed_form"),
     ("estimator_scale", "(double)npx * C->k0 / (double)C->tour_count", "C->k0 / (double)C->tour_count",
      "test_restore_image_tends_to_path_tracing"),
 ]

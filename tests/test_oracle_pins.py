@@ -303,11 +303,14 @@ def test_one_bounce_closed_form_value_and_gradient(orc):
             assert abs(fd - score[k, i]) <= 1e-5 * max(1.0, abs(fd)), (k, i, fd, score[k, i])
 
 
-@pytest.mark.parametrize("which,L", [("tiny", 4), ("spheres_small", 6)])
+@pytest.mark.parametrize("which,L", [("tiny", 4), ("spheres_small", 6), ("specular", 8)])
 def test_score_matches_finite_differences(orc, which, L):
     """Forward-mode score equals central differences of ln(p + eps) wherever
-    both perturbed points keep the same discrete path (readings A13, A14)."""
-    sc = inputs.cornell_tiny() if which == "tiny" else inputs.procedural_spheres(n_spheres=3, subdiv=2)
+    both perturbed points keep the same discrete path (readings A13, A14);
+    the specular box runs it through mirror chains, refraction and emission
+    seen through delta vertices."""
+    sc = {"tiny": inputs.cornell_tiny, "specular": inputs.specular_box,
+          "spheres_small": lambda: inputs.procedural_spheres(n_spheres=3, subdiv=2)}[which]()
     S = orc.Scene(sc)
     d = 4 * (L - 1)
     u = inputs.random_points(d, 150, seed=21).astype(np.float64)
@@ -330,6 +333,184 @@ def test_score_matches_finite_differences(orc, which, L):
             assert abs(fd - score[k, i]) <= 2e-4 * max(1.0, abs(fd)), (k, i, fd, score[k, i])
             checked += 1
     assert checked > 200
+
+
+# ---------------------------------------------------------------------------
+# Delta materials: smooth conductor and smooth dielectric (Sec. 6 material set)
+# ---------------------------------------------------------------------------
+def _random_frames(rng, n):
+    """n unit normals and unit directions on the normal's side."""
+    nn = rng.normal(size=(n, 3))
+    nn /= np.linalg.norm(nn, axis=1, keepdims=True)
+    wo = rng.normal(size=(n, 3))
+    wo /= np.linalg.norm(wo, axis=1, keepdims=True)
+    wo *= np.sign(np.sum(wo * nn, axis=1, keepdims=True))
+    return nn, wo
+
+
+def test_mirror_lobe(orc):
+    """Smooth conductor: the law of reflection (wi + wo along n, equal angles,
+    unit length) and Schlick's F at its three fixed points: f0 at normal
+    incidence, 1 at grazing incidence, increasing towards grazing."""
+    mat = inputs.material(inputs.KIND_MIRROR, f0=(0.9, 0.6, 0.3))
+    f0 = np.asarray(mat[5:8], np.float32).astype(np.float64)  # the material is stored in FP32
+    rng = np.random.default_rng(5)
+    nn, wo = _random_frames(rng, 200)
+    for n, o in zip(nn, wo):
+        lobe, wi, wt = orc.delta_sample(mat, n, True, o, 0.5)
+        assert lobe == 0
+        assert abs(np.linalg.norm(wi) - 1) < 1e-12
+        s = wi + o
+        assert np.linalg.norm(np.cross(s, n)) < 1e-12 and np.dot(s, n) >= 0
+        assert abs(np.dot(wi, n) - np.dot(o, n)) < 1e-12
+        assert np.all(wt >= f0 - 1e-12) and np.all(wt <= 1 + 1e-12)
+    n = np.array([0.0, 0.0, 1.0])
+    _, wi, wt = orc.delta_sample(mat, n, True, n, 0.5)
+    assert np.allclose(wi, n) and np.allclose(wt, f0, rtol=0, atol=1e-15)
+    _, _, wt = orc.delta_sample(mat, n, True, np.array([1.0, 0.0, 0.0]), 0.5)
+    assert np.allclose(wt, 1.0)
+    prev = None
+    for th in np.linspace(0, 1.5, 16):
+        _, _, wt = orc.delta_sample(mat, n, True, np.array([math.sin(th), 0.0, math.cos(th)]), 0.5)
+        if prev is not None:
+            assert np.all(wt >= prev - 1e-15)
+        prev = wt
+
+
+@pytest.mark.parametrize("eta", [1.33, 1.5, 2.4])
+def test_dielectric_fresnel_fixed_points(orc, eta):
+    """Fresnel reflectance of a smooth dielectric against values that do not
+    come from its formula: ((eta - 1)/(eta + 1))^2 at normal incidence;
+    Brewster's angle, where the p-polarised part vanishes and the
+    s-polarised amplitude is (1 - eta^2)/(1 + eta^2); 1 at grazing incidence
+    and beyond the critical angle inside the denser medium; Stokes
+    reciprocity F(theta_i, eta) = F(theta_t, 1/eta) with Snell's theta_t."""
+    assert abs(orc.fresnel_dielectric(1.0, eta) - ((eta - 1) / (eta + 1)) ** 2) < 1e-15
+    assert abs(orc.fresnel_dielectric(1.0, 1 / eta) - ((eta - 1) / (eta + 1)) ** 2) < 1e-15
+    tb = math.atan(eta)
+    assert abs(orc.fresnel_dielectric(math.cos(tb), eta) - 0.5 * ((1 - eta ** 2) / (1 + eta ** 2)) ** 2) < 1e-14
+    assert abs(orc.fresnel_dielectric(0.0, eta) - 1.0) < 1e-15
+    crit = math.asin(1 / eta)
+    for th in np.linspace(crit + 1e-6, math.pi / 2, 7):
+        assert orc.fresnel_dielectric(math.cos(th), 1 / eta) == 1.0
+    for th in np.linspace(0.0, 1.55, 40):
+        st = math.sin(th) / eta
+        ct = math.sqrt(1 - st * st)
+        a, b = orc.fresnel_dielectric(math.cos(th), eta), orc.fresnel_dielectric(ct, 1 / eta)
+        assert 0.0 <= a <= 1.0 and abs(a - b) < 1e-13, (th, a, b)
+
+
+@pytest.mark.parametrize("front", [True, False])
+def test_dielectric_lobe(orc, front):
+    """Smooth dielectric sample: the coordinate u picks reflection exactly when
+    u < F; reflection obeys the law of reflection with weight 1; refraction
+    obeys Snell's law (sin_t etap = sin_i, in the plane of n and wo, on the
+    far side) with weight 1/etap^2, etap = eta entering, 1/eta leaving."""
+    eta = 1.5
+    mat = inputs.material(inputs.KIND_GLASS, eta=eta)
+    etap = eta if front else 1 / eta
+    rng = np.random.default_rng(9)
+    nn, wo = _random_frames(rng, 300)
+    refracted = 0
+    for n, o in zip(nn, wo):
+        ci = float(np.dot(n, o))
+        F = orc.fresnel_dielectric(ci, etap)
+        for u in (0.0, max(F - 1e-4, 0.0), min(F + 1e-4, 0.9999), 0.9999):
+            lobe, wi, wt = orc.delta_sample(mat, n, front, o, u)
+            assert abs(np.linalg.norm(wi) - 1) < 1e-12
+            if u < F:
+                assert lobe == 0
+                assert np.linalg.norm(np.cross(wi + o, n)) < 1e-12 and np.allclose(wt, 1.0)
+            else:
+                assert lobe == 1
+                refracted += 1
+                sin_i = np.linalg.norm(np.cross(n, o))
+                sin_t = np.linalg.norm(np.cross(n, wi))
+                assert abs(sin_t * etap - sin_i) < 1e-12
+                assert np.dot(wi, n) < 0
+                assert abs(np.dot(np.cross(n, o), wi)) < 1e-12                       # coplanar
+                assert np.dot(wi - np.dot(wi, n) * n, o - ci * n) <= 1e-12             # tangent reversed
+                assert np.allclose(wt, 1 / etap ** 2)
+    assert refracted > 100  # leaving the medium, total internal reflection takes the rest
+
+
+def test_mirror_plane_closed_form(orc):
+    """A light seen only in a smooth-conductor plane: the camera ray that
+    meets the mirror at normal incidence returns f0 Le; a ray returns
+    radiance exactly when the mirror image of the eye, through the mirror
+    point, lines up with the light (method of images), with F between f0
+    and 1; with one vertex the delta surface gives nothing (no next-event
+    estimation at a delta vertex)."""
+    f0, Le = np.array([0.9, 0.6, 0.3]), np.array([4.0, 3.0, 2.0])
+    sc = inputs.mirror_plane(f0=tuple(f0), Le=tuple(Le))
+    f0 = sc["materials"][0, 5:8].astype(np.float64)  # as stored (FP32)
+    S = orc.Scene(sc)
+    L = 3
+    u = np.full((1, 4 * (L - 1)), 0.3)
+    u[0, :2] = 0.5
+    f, _, _, _ = S.path_eval(L, u, grad=False)
+    assert np.allclose(f[0], f0 * Le, rtol=1e-14)
+    f1, _, _, _ = S.path_eval(2, np.random.default_rng(2).random((500, 4)), grad=False)
+    assert np.all(f1 == 0)
+    U = np.random.default_rng(4).random((3000, 4 * (L - 1)))
+    U[:, :2] = 0.5 + (U[:, :2] - 0.5) * 0.6
+    f, _, _, _ = S.path_eval(L, U, grad=False)
+    # primary direction of the pinhole model; image of the eye in z = -1 is (0, 0, -2)
+    th = math.tan(math.radians(60.0) / 2)
+    D = np.stack([(2 * U[:, 0] - 1) * th, (1 - 2 * U[:, 1]) * th, -np.ones(len(U))], 1)
+    P = D / -D[:, 2:3] * 1.0                      # meets z = -1
+    R = P - np.array([0.0, 0.0, -2.0])            # image ray through P
+    Q = P + R * (2.0 / R[:, 2:3])                 # meets z = +1
+    inside = (Q[:, 0] > -0.3) & (Q[:, 0] < 0.4) & (Q[:, 1] > -0.2) & (Q[:, 1] < 0.3)
+    edge = (np.minimum.reduce([np.abs(Q[:, 0] + 0.3), np.abs(Q[:, 0] - 0.4), np.abs(Q[:, 1] + 0.2),
+                               np.abs(Q[:, 1] - 0.3)]) < 1e-9)
+    lit = f[:, 0] > 0
+    assert np.array_equal(lit[~edge], inside[~edge]) and inside.sum() > 100
+    assert np.all(f[lit] >= f0 * Le * (1 - 1e-12)) and np.all(f[lit] <= Le * (1 + 1e-12))
+
+
+def test_glass_slab_branches(orc):
+    """Camera ray through a smooth-dielectric slab at normal incidence to a
+    light behind it: each choice sequence of the dielectric coordinates has
+    a fixed value.  Through-through returns Le (the 1/eta^2 entering and
+    eta^2 leaving cancel); reflection at the first face returns nothing;
+    two internal reflections then exit return Le; the decision sits at
+    F = ((eta - 1)/(eta + 1))^2."""
+    Le = np.array([4.0, 3.0, 2.0])
+    sc = inputs.glass_slab(eta=1.5, Le=tuple(Le))
+    S = orc.Scene(sc)
+    L = 6
+    F = 0.04
+
+    def f_of(choices):
+        u = np.full((1, 4 * (L - 1)), 0.5)
+        for j, c in enumerate(choices):
+            u[0, 4 * (j + 1)] = c
+        return S.path_eval(L, u, grad=False)[0][0]
+
+    T, R = 0.9, 0.01
+    assert np.allclose(f_of([T, T]), Le, rtol=1e-12)
+    assert np.all(f_of([R]) == 0)
+    assert np.allclose(f_of([T, R, R, T]), Le, rtol=1e-12)
+    assert np.all(f_of([T, R, T]) == 0)
+    assert np.all(f_of([T, R, R, R]) == 0)
+    assert np.all(f_of([F * (1 - 1e-4), T]) == 0) and np.allclose(f_of([F * (1 + 1e-4), T]), Le)
+
+
+def test_radiance_seen_from_inside_the_dielectric(orc):
+    """Radiance divided by the squared index of refraction is conserved
+    across a smooth interface, so a camera inside the slab sees a light
+    outside, through the lower face at normal incidence, as eta^2 Le (the
+    refraction branch; its probability 1 - F cancels its weight's)."""
+    eta, Le = 1.5, np.array([4.0, 3.0, 2.0])
+    S = orc.Scene(inputs.glass_slab(eta=eta, Le=tuple(Le), eye_z=-1.25))
+    L = 4
+    u = np.full((1, 4 * (L - 1)), 0.5)
+    u[0, 4] = 0.9
+    f = S.path_eval(L, u, grad=False)[0][0]
+    assert np.allclose(f, eta ** 2 * Le, rtol=1e-12)
+    u[0, 4] = 0.01
+    assert np.all(S.path_eval(L, u, grad=False)[0][0] == 0)
 
 
 # ---------------------------------------------------------------------------
