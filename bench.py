@@ -111,7 +111,7 @@ def write_traffic_summary(dirs, chains, per_launch):
     rd, wr = fk * 1024.0 * fs, wk * 1024.0 * ws
     cmd = f"python3 bench.py --profile-only --steps 8 --warmup 2 --chains {chains} --steps-per-frame {per_launch}"
     lines = [
-        "# HBM traffic of k_step_fused_pair<8>: procedural spheres 53k triangles, 512x512, L = 8",
+        "# HBM traffic of k_step_fused_pair<8, false>: procedural spheres 53k triangles, 512x512, L = 8",
         f"# counters: rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) -d <out> -- {cmd}",
         "# calibration: rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) -d <out> -- python3 bench.py --copy-probe",
         "# written by: python3 bench.py --traffic-summary <fetch> <write> <copy_fetch> <copy_write> [<tcc> <sq2>]",
@@ -457,7 +457,7 @@ def main():
                      "achievable_copy_GBs": hbm_copy, "frac_of_achievable": achieved / hbm_copy,
                      "l2_hit_rate": counters.get("l2_hit_rate"), "valu_issue_frac": counters.get("valu_issue_frac"),
                      "traffic_unit": "HBM bytes per launch", "alg_bytes_per_launch": bytes_step * N * F,
-                     "kernel": f"k_step_fused{'_pair' if launch_cfg['lanes_per_chain'] == 2 else ''}<{L}>",
+                     "kernel": f"k_step_fused{'_pair' if launch_cfg['lanes_per_chain'] == 2 else ''}<{L}, false>",
                      "launch_ms": ms_launch, "steps_per_launch": F},
     }
 

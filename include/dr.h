@@ -52,7 +52,7 @@ const char* dr_version(void);
 /* ------------------------------------------------------------------------
  * Scene (the integrand f of Sec. 3 is the path contribution of this scene).
  * ------------------------------------------------------------------------ */
-enum { DR_MAT_LAMBERT = 0, DR_MAT_GGX_CONDUCTOR = 1 };
+enum { DR_MAT_LAMBERT = 0, DR_MAT_GGX_CONDUCTOR = 1, DR_MAT_SMOOTH_CONDUCTOR = 2, DR_MAT_SMOOTH_DIELECTRIC = 3 };
 
 /* Parallelogram light p0 + a e1 + b e2 (a, b in [0,1]) emitting radiance Le
  * on the side of e1 x e2 (the paper's lights are diffuse area lights, Sec. 6
@@ -60,15 +60,28 @@ enum { DR_MAT_LAMBERT = 0, DR_MAT_GGX_CONDUCTOR = 1 };
  * triangles wound like e1 x e2 with an emissive material. */
 typedef struct { float p0[3], e1[3], e2[3], Le[3]; } dr_quad_light;
 
-/* Lambertian (albedo/pi) or GGX conductor (Trowbridge-Reitz D with alpha =
- * roughness, separable Smith G, Schlick F with normal reflectance f0);
- * Le is emitted radiance for emitter triangles. */
+/* The material set of the paper's test scenes (Sec. 6: diffuse, conductor,
+ * dielectric):
+ *   DR_MAT_LAMBERT            albedo/pi;
+ *   DR_MAT_GGX_CONDUCTOR      Trowbridge-Reitz D with alpha = roughness,
+ *                             separable Smith G, Schlick F with normal
+ *                             reflectance f0;
+ *   DR_MAT_SMOOTH_CONDUCTOR   perfect mirror weighted by Schlick's F (f0);
+ *   DR_MAT_SMOOTH_DIELECTRIC  Fresnel-weighted choice of mirror reflection or
+ *                             Snell refraction; eta is the index of refraction
+ *                             on the side opposite e1 x e2 (the outside is
+ *                             the e1 x e2 side, index 1), finite and > 0.
+ * The two smooth kinds have delta lobes: no next-event estimate is taken at
+ * their vertices, and emission is counted at a vertex reached through them.
+ * Le is emitted radiance for emitter triangles; eta is read only for the
+ * dielectric. */
 typedef struct {
     uint32_t kind;
     float albedo[3];
     float roughness;
     float f0[3];
     float Le[3];
+    float eta;
 } dr_material;
 
 /* Binary BVH node as built on the host: a >= 0 is an inner node with children

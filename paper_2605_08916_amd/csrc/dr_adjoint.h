@@ -54,14 +54,22 @@ __device__ __forceinline__ VState camera_state(const Cam& C, float u0, float u1,
     return s;
 }
 
-// State of vertex j+1 from vertex j (BSDF sample with block (u, v), then the
-// recorded next triangle Tn).  The sample is known to be valid.
+// State of vertex j+1 from vertex j (BSDF sample with block (u, v), or the
+// recorded lobe of a delta vertex, then the recorded next triangle Tn).  The
+// sample is known to be valid.
+template <bool DELTA>
 __device__ __forceinline__ VState advance(const DevScene& S, const VState& s, const DevTri& T, const DevTri& Tn, float u,
-                                          float v) {
+                                          float v, uint32_t recj) {
     const Material m = load_material(S, __float_as_uint(T.e1.w));
-    const V3 n = facing_normal(T, s.din);
+    bool front;
+    const V3 n = facing_normal(T, s.din, front);
     V3 wi, wt;
-    bsdf_sample(m, n, -s.din, u, v, wi, wt);
+    if (DELTA && is_delta(m)) {
+        int lobe = rec_light(recj) & 1;
+        delta_sample(m, n, front, -s.din, u, wi, wt, lobe);
+    } else {
+        bsdf_sample(m, n, -s.din, u, v, wi, wt);
+    }
     const V3 ngn = normalize(cross(xyz(Tn.e1), xyz(Tn.e2)));
     VState r;
     r.x = s.x + wi * plane_t(Tn, ngn, s.x, wi);
@@ -74,18 +82,63 @@ __device__ __forceinline__ VState advance(const DevScene& S, const VState& s, co
 // state (zero if it does not exist).  Writes the gradients of the light block
 // (4j-2, 4j-1) and, for j <= L-2, of the BSDF block (4j, 4j+1), scaled by
 // 1/(p + eps).  Returns the adjoints of vertex j's state.
-template <class U>
+template <bool DELTA, class U>
 __device__ Adj reverse_vertex(const DevScene& S, int L, int j, const VState& s, const Adj& an, uint32_t recj,
                               uint32_t recn, const U& u, float inv_pe, float* out, int os) {
     const DevTri T = S.tris[rec_slot(recj)];
     const Material m = load_material(S, __float_as_uint(T.e1.w));
-    const V3 n = facing_normal(T, s.din);
+    bool front;
+    const V3 n = facing_normal(T, s.din, front);
     const V3 wo = -s.din;
     V3 gx = v3(0.f, 0.f, 0.f), gwo = v3(0.f, 0.f, 0.f), gb = v3(0.f, 0.f, 0.f);
     float gu = 0.f, gv = 0.f, ga = 0.f, gbl = 0.f;
 
+    // ---- delta step j -> j+1: the direction follows from wo alone (the
+    // dielectric's lobe is the recorded one), so the BSDF block has no
+    // gradient; the emission counted at j+1 adds Le_{j+1} . d p / d beta'
+    const bool delta = DELTA && is_delta(m);
+    if (delta && j <= L - 2 && recn != DR_NO_VERTEX) {
+        int lobe = rec_light(recj) & 1;
+        V3 wi, W;
+        delta_sample(m, n, front, wo, 0.0f, wi, W, lobe);
+        const DevTri Tn = S.tris[rec_slot(recn)];
+        const V3 ngn = normalize(cross(xyz(Tn.e1), xyz(Tn.e2)));
+        const float Dn = dot(ngn, wi);
+        const float tp = dot(ngn, xyz(Tn.v0) - s.x) / Dn;
+        const float sc = dot(an.gx, wi) / Dn;
+        const V3 gproj = an.gx - ngn * sc;
+        gx = gx + gproj;
+        const V3 gwi = gproj * tp + an.gd;
+        V3 gbn = an.gb;
+        if (faces_ray(Tn, wi)) {
+            const V3 Le = load_material(S, __float_as_uint(Tn.e1.w)).Le;
+            gbn = gbn + v3(0.2126f * Le.x, 0.7152f * Le.y, 0.0722f * Le.z);
+        }
+        gb = gb + mul(gbn, W);
+        const float ci = dot(n, wo);
+        if (lobe == 0) {
+            // wi = 2 ci n - wo (mirror and dielectric reflection)
+            float g_ci = 2.0f * dot(gwi, n);
+            if (m.kind == MAT_MIRROR) {  // W = f0 + (1 - f0)(1 - ci)^5
+                const V3 gW = mul(gbn, s.beta);
+                const float om = 1.0f - ci;
+                const float om4 = om * om * om * om;
+                g_ci -= 5.0f * om4 *
+                        (gW.x * (1.0f - m.f0.x) + gW.y * (1.0f - m.f0.y) + gW.z * (1.0f - m.f0.z));
+            }
+            gwo = gwo - gwi + n * g_ci;
+        } else {
+            // wi = -wo / etap + (ci / etap - ct) n, ct^2 = 1 - (1 - ci^2) / etap^2; W constant
+            const float ie = 1.0f / rel_eta(m, front);
+            float ct;
+            fresnel_dielectric(ci, rel_eta(m, front), ct);
+            const float dct = ct > 0.0f ? ci * ie * ie / ct : 0.0f;
+            gwo = gwo - gwi * ie + n * (dot(gwi, n) * (ie - dct));
+        }
+    }
+
     // ---- BSDF step j -> j+1: x' = x + t' wi, din' = wi, beta' = beta * W
-    if (j <= L - 2 && recn != DR_NO_VERTEX) {
+    if (!delta && j <= L - 2 && recn != DR_NO_VERTEX) {
         const float uu = u(4 * j), vv = u(4 * j + 1);
         V3 tt, bb;
         onb(n, tt, bb);
@@ -246,7 +299,7 @@ __device__ Adj reverse_vertex(const DevScene& S, int L, int j, const VState& s, 
 }
 
 // score[i * os] = d ln(p + eps) / d u_i for the recorded path (rec[(j-1)*rs]).
-template <int L, class U>
+template <int L, bool DELTA = true, class U>
 __device__ void path_score(const DevScene& S, const U& u, const uint32_t* rec, int rs, float p, float eps, float* out,
                            int os) {
     constexpr int V = L - 1;
@@ -271,7 +324,7 @@ __device__ void path_score(const DevScene& S, const U& u, const uint32_t* rec, i
         for (int j = 1; j <= V; ++j) {
             if ((j - 1) % DR_SEG == 0) cp[(j - 1) / DR_SEG] = st;
             if (NSEG > 1 && j < V && (j - 1) / DR_SEG < NSEG - 1 && R[j + 1] != DR_NO_VERTEX)
-                st = advance(S, st, S.tris[rec_slot(R[j])], S.tris[rec_slot(R[j + 1])], u(4 * j), u(4 * j + 1));
+                st = advance<DELTA>(S, st, S.tris[rec_slot(R[j])], S.tris[rec_slot(R[j + 1])], u(4 * j), u(4 * j + 1), R[j]);
         }
     }
     Adj a;
@@ -289,7 +342,7 @@ __device__ void path_score(const DevScene& S, const U& u, const uint32_t* rec, i
             if (j <= V) {
                 tape[k] = st;
                 if (k < DR_SEG - 1 && j < V && R[j] != DR_NO_VERTEX && R[j + 1] != DR_NO_VERTEX)
-                    st = advance(S, st, S.tris[rec_slot(R[j])], S.tris[rec_slot(R[j + 1])], u(4 * j), u(4 * j + 1));
+                    st = advance<DELTA>(S, st, S.tris[rec_slot(R[j])], S.tris[rec_slot(R[j + 1])], u(4 * j), u(4 * j + 1), R[j]);
             }
         }
 #pragma unroll
@@ -298,7 +351,7 @@ __device__ void path_score(const DevScene& S, const U& u, const uint32_t* rec, i
             if (j <= V) {
                 const uint32_t rn = (j < V) ? R[j + 1] : DR_NO_VERTEX;
                 if (R[j] != DR_NO_VERTEX) {
-                    a = reverse_vertex(S, L, j, tape[k], a, R[j], rn, u, inv_pe, out, os);
+                    a = reverse_vertex<DELTA>(S, L, j, tape[k], a, R[j], rn, u, inv_pe, out, os);
                 } else {
                     out[(size_t)(4 * j - 2) * os] = 0.0f;
                     out[(size_t)(4 * j - 1) * os] = 0.0f;

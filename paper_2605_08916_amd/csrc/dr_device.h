@@ -79,7 +79,7 @@ struct alignas(128) DevNode {
 struct alignas(16) DevTri {
     float4 v0, e1, e2;
 };
-// Material: m0 = (kind, albedo), m1 = (roughness, f0), m2 = (Le, 0).
+// Material: m0 = (kind, albedo), m1 = (roughness, f0), m2 = (Le, eta).
 // Light: l0 = (p0, 0), l1 = (e1, 0), l2 = (e2, 0), l3 = (unit normal, area), l4 = (Le, 0).
 struct DevScene {
     const DevNode* nodes;
@@ -476,6 +476,17 @@ __device__ __forceinline__ V3 facing_normal(const DevTri& T, V3 din) {
     const V3 ng = normalize(cross(xyz(T.e1), xyz(T.e2)));
     return dot(ng, din) > 0.0f ? -ng : ng;
 }
+// Same; front: the incoming direction arrives on the e1 x e2 side (outside
+// a dielectric).
+__device__ __forceinline__ V3 facing_normal(const DevTri& T, V3 din, bool& front) {
+    const V3 ng = normalize(cross(xyz(T.e1), xyz(T.e2)));
+    front = !(dot(ng, din) > 0.0f);
+    return front ? ng : -ng;
+}
+// True when a ray along d meets the triangle's emitting (e1 x e2) side.
+__device__ __forceinline__ bool faces_ray(const DevTri& T, V3 d) {
+    return dot(cross(xyz(T.e1), xyz(T.e2)), d) < 0.0f;
+}
 
 // Orthonormal basis around a unit normal (Duff et al., JCGT 2017).
 __device__ __forceinline__ void onb(V3 n, V3& t, V3& b) {
@@ -492,11 +503,15 @@ __device__ __forceinline__ float smith_g1(float c, float a2) {
     return 2.0f / (1.0f + sqrtf(1.0f + a2 * (1.0f - c2) / c2));
 }
 
+enum { MAT_LAMBERT = 0, MAT_GGX = 1, MAT_MIRROR = 2, MAT_GLASS = 3 };
 struct Material {
     int kind;
     V3 albedo, f0, Le;
-    float a2;  // GGX alpha^2
+    float a2;   // GGX alpha^2
+    float eta;  // dielectric: index of refraction inside (opposite e1 x e2)
 };
+// Smooth conductor and smooth dielectric: BSDFs with a delta lobe.
+__device__ __forceinline__ bool is_delta(const Material& m) { return m.kind >= MAT_MIRROR; }
 __device__ __forceinline__ Material load_material(const DevScene& S, uint32_t id) {
     const float4 m0 = S.mats[3 * id], m1 = S.mats[3 * id + 1], m2 = S.mats[3 * id + 2];
     Material m;
@@ -505,6 +520,7 @@ __device__ __forceinline__ Material load_material(const DevScene& S, uint32_t id
     m.a2 = m1.x * m1.x;
     m.f0 = v3(m1.y, m1.z, m1.w);
     m.Le = xyz(m2);
+    m.eta = m2.w;
     return m;
 }
 
@@ -556,6 +572,58 @@ __device__ __forceinline__ bool bsdf_sample(const Material& m, V3 n, V3 wo, floa
     return true;
 }
 
+// Fresnel reflectance of a smooth dielectric for unpolarised light: the mean
+// of the squared s and p amplitude ratios.  ci: incident cosine (>= 0); etap:
+// n_transmitted / n_incident.  1 under total internal reflection; ct: the
+// transmitted cosine.
+__device__ __forceinline__ float fresnel_dielectric(float ci, float etap, float& ct) {
+    const float s2 = (1.0f - ci * ci) / (etap * etap);
+    if (s2 >= 1.0f) {
+        ct = 0.0f;
+        return 1.0f;
+    }
+    ct = sqrtf(1.0f - s2);
+    const float rs = (ci - etap * ct) / (ci + etap * ct);
+    const float rp = (etap * ci - ct) / (etap * ci + ct);
+    return 0.5f * (rs * rs + rp * rp);
+}
+
+// Relative index of refraction across a dielectric's surface, seen from the
+// incident side.
+__device__ __forceinline__ float rel_eta(const Material& m, bool front) { return front ? m.eta : 1.0f / m.eta; }
+
+// Delta lobe of a smooth conductor (mirror direction, weight Schlick's F at
+// the incidence cosine) or smooth dielectric (reflection when u < F, weight
+// 1; else Snell refraction, weight 1/etap^2: radiance scales with the
+// squared index).  n faces wo.  Lobe 0 reflection, 1 refraction; with
+// lobe >= 0 on entry the choice is taken as given (replay of a recorded
+// path) instead of drawn from u.
+__device__ __forceinline__ void delta_sample(const Material& m, V3 n, bool front, V3 wo, float u, V3& wi, V3& weight,
+                                             int& lobe) {
+    const float ci = dot(n, wo);
+    if (m.kind == MAT_MIRROR) {
+        wi = n * (2.0f * ci) - wo;
+        const float om = 1.0f - ci;
+        const float f5 = om * om * om * om * om;
+        weight = v3(m.f0.x + (1.0f - m.f0.x) * f5, m.f0.y + (1.0f - m.f0.y) * f5, m.f0.z + (1.0f - m.f0.z) * f5);
+        lobe = 0;
+        return;
+    }
+    const float etap = rel_eta(m, front);
+    float ct;
+    const float F = fresnel_dielectric(ci, etap, ct);
+    if (lobe < 0) lobe = u < F ? 0 : 1;
+    if (lobe == 0) {
+        wi = n * (2.0f * ci) - wo;
+        weight = v3(1.f, 1.f, 1.f);
+    } else {
+        const float ie = 1.0f / etap;
+        wi = wo * (-ie) + n * (ci * ie - ct);
+        const float w = ie * ie;
+        weight = v3(w, w, w);
+    }
+}
+
 // Light selection from the first coordinate of the light block, in FP32.
 __device__ __forceinline__ int select_light(float a, int nl, float& ap) {
     const float sel = a * (float)nl;
@@ -582,7 +650,13 @@ __device__ __forceinline__ uint32_t pixel_of(const DevScene& S, float u0, float 
 // Forward path contribution with next-event estimation.
 // U is an accessor: float operator()(int i) returns coordinate i of u.
 // rec (nullable): per vertex j = 1..L-1, rec[(j-1) * rs] = slot << 8 |
-// light << 1 | contributed, or DR_NO_VERTEX.
+// light << 1 | contributed (at a delta vertex: lobe << 1), or DR_NO_VERTEX.
+// Emission counts at the primary hit and at a vertex reached from a delta
+// vertex (next-event estimation cannot sample a light through a delta
+// lobe); a delta vertex takes no next-event estimate.
+//
+// DELTA: false compiles the delta-lobe handling out, for scenes without
+// smooth conductors or dielectrics.
 //
 // PAIR: two adjacent lanes evaluate the same path.  Both run the same control
 // flow on the same data (so they take the same branches and hold the same
@@ -629,7 +703,7 @@ __device__ __forceinline__ bool point_finite(const U& u, int d) {
     }
 }
 
-template <bool PAIR, class U>
+template <bool PAIR, bool DELTA = true, class U>
 __device__ V3 path_forward(const DevScene& S, int L, const U& u, uint32_t* rec, int rs, uint32_t* stk, int stride,
                            Counters& ctr, int* nverts = nullptr) {
     V3 f = v3(0.f, 0.f, 0.f);
@@ -661,14 +735,16 @@ __device__ V3 path_forward(const DevScene& S, int L, const U& u, uint32_t* rec, 
         DevTri T = S.tris[slot];
         {
             const Material m = load_material(S, __float_as_uint(T.e1.w));
-            if (dot(cross(xyz(T.e1), xyz(T.e2)), d) < 0.0f) f = f + m.Le;
+            if (faces_ray(T, d)) f = f + m.Le;
         }
         V3 beta = v3(1.f, 1.f, 1.f);
         const int nl = S.n_lights;
         for (; j <= L - 1; ++j) {
             const Material m = load_material(S, __float_as_uint(T.e1.w));
-            const V3 n = facing_normal(T, d);
+            bool front;
+            const V3 n = facing_normal(T, d, front);
             const V3 wo = -d;
+            const bool delta = DELTA && is_delta(m);
             // next-event estimation candidate
             float ap;
             const float a = u(4 * j - 2), b = u(4 * j - 1);
@@ -684,18 +760,24 @@ __device__ V3 path_forward(const DevScene& S, int L, const U& u, uint32_t* rec, 
             const float cy = -dot(xyz(l3), wl);
             // both cosines must clear 1e-6 (a vertex in the light's own plane
             // has cosines that are rounding noise around zero)
-            const bool shadow = cx > 1e-6f && cy > 1e-6f;
+            const bool shadow = !delta && cx > 1e-6f && cy > 1e-6f;
             // continuation candidate: BSDF sample at vertex j
             V3 wi = v3(0.f, 0.f, 1.f), wt = v3(0.f, 0.f, 0.f);
-            const bool cont = j < L - 1 && !(beta.x == 0.0f && beta.y == 0.0f && beta.z == 0.0f) &&
-                              bsdf_sample(m, n, wo, u(4 * j), u(4 * j + 1), wi, wt);
+            int lobe = -1;
+            bool cont = j < L - 1 && !(beta.x == 0.0f && beta.y == 0.0f && beta.z == 0.0f);
+            if (cont) {
+                if (delta) delta_sample(m, n, front, wo, u(4 * j), wi, wt, lobe);
+                else cont = bsdf_sample(m, n, wo, u(4 * j), u(4 * j + 1), wi, wt);
+            }
             bool occluded;
             int ns;
             float tn;
             trace_vertex_rays<PAIR>(S, x, shadow, wl, (1.0f - 1e-4f) * r, cont, wi, occluded, ns, tn, stk, stride,
                                     ctr);
             const bool contrib = shadow && !occluded;
-            if (rec) rec[(j - 1) * rs] = ((uint32_t)slot << 8) | ((uint32_t)li << 1) | (contrib ? 1u : 0u);
+            if (rec)
+                rec[(j - 1) * rs] = ((uint32_t)slot << 8) | ((uint32_t)(delta ? max(lobe, 0) : li) << 1) |
+                                    (contrib ? 1u : 0u);
             if (contrib) {
                 const V3 fs = bsdf_eval(m, n, wo, wl);
                 const float g = cx * cy / r2 * ((float)nl * l3.w);
@@ -707,6 +789,7 @@ __device__ V3 path_forward(const DevScene& S, int L, const U& u, uint32_t* rec, 
             d = wi;
             slot = ns;
             T = S.tris[slot];
+            if (delta && faces_ray(T, d)) f = f + mul(beta, load_material(S, __float_as_uint(T.e1.w)).Le);
         }
         ++j;
     }

@@ -120,9 +120,9 @@ __device__ __forceinline__ bool hold_kill_splat(const KParams& P, const KBufs& B
     return alive;
 }
 
-template <int L>
+template <int L, bool DELTA = true>
 __device__ __forceinline__ void score_at(const KParams& P, const KBufs& B, const DevScene& S, int c, float p) {
-    path_score<L>(S, SoaU{B.x + c, P.N}, B.rec + c, P.N, p, P.eps, B.score + c, P.N);
+    path_score<L, DELTA>(S, SoaU{B.x + c, P.N}, B.rec + c, P.N, p, P.eps, B.score + c, P.N);
 }
 
 // ===========================================================================
@@ -325,7 +325,7 @@ __global__ void __launch_bounds__(256) k_copy_u32(const uint32_t* src, uint32_t*
 // PAIR, two adjacent lanes share a chain: both run its step on the same data,
 // the path's continuation and shadow rays are traced concurrently (one per
 // lane), and only the even lane performs the atomics.
-template <int L, bool PAIR>
+template <int L, bool PAIR, bool DELTA>
 __device__ __forceinline__ void step_fused_body(const KParams& P, const DevScene& S, const KBufs& B, uint32_t nsteps,
                                                 uint32_t grab, int sorted) {
     extern __shared__ uint32_t s_stack[];
@@ -375,7 +375,7 @@ __device__ __forceinline__ void step_fused_body(const KParams& P, const DevScene
             else move(P.seed, P.d, P.N, P.stddev, P.gt, xc, B.score + c, B.sigma ? B.sigma + id : nullptr, id, s);
             const SoaU u{xc, P.N};
             int nv;
-            const V3 f = path_forward<PAIR>(S, L, u, B.rec + c, P.N, stk, stride, ctr, &nv);
+            const V3 f = path_forward<PAIR, DELTA>(S, L, u, B.rec + c, P.N, stk, stride, ctr, &nv);
             const float p = lum(f);
             const uint32_t pix = pixel_of(S, xc[0], xc[P.N]);
             const bool alive = hold_kill_splat(P, B, S, c, id, s, k0, f, p, pix, lead);
@@ -383,7 +383,7 @@ __device__ __forceinline__ void step_fused_body(const KParams& P, const DevScene
             if (sorted) B.key[c] = alive ? (uint32_t)nv : (uint32_t)(DR_NBIN - 1);
             if (lead) kills += alive ? 0u : 1u;
             if (alive) {
-                score_at<L>(P, B, S, c, p);
+                score_at<L, DELTA>(P, B, S, c, p);
                 if (lead) ++adj;
             }
             ++k;
@@ -405,19 +405,20 @@ __device__ __forceinline__ void step_fused_body(const KParams& P, const DevScene
 
 // Paired lanes (two per chain): at 128 of the kernel's registers or more a
 // SIMD holds two wavefronts, which is all the paired form has at the chain
-// counts it is used for.
-template <int L>
+// counts it is used for.  DELTA: the scene has smooth conductors or
+// dielectrics (false compiles their handling out).
+template <int L, bool DELTA>
 __global__ void __launch_bounds__(256) k_step_fused_pair(KParams P, DevScene S, KBufs B, uint32_t nsteps, uint32_t grab,
                                                          int sorted) {
-    step_fused_body<L, true>(P, S, B, nsteps, grab, sorted);
+    step_fused_body<L, true, DELTA>(P, S, B, nsteps, grab, sorted);
 }
 // One lane per chain (used when chains outnumber two wavefronts per SIMD):
 // registers capped for three wavefronts per SIMD, which hides more of the
 // traversal's memory latency than the spills it costs.
-template <int L>
+template <int L, bool DELTA>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 k_step_fused(KParams P, DevScene S, KBufs B, uint32_t nsteps, uint32_t grab, int sorted) {
-    step_fused_body<L, false>(P, S, B, nsteps, grab, sorted);
+    step_fused_body<L, false, DELTA>(P, S, B, nsteps, grab, sorted);
 }
 
 // Path records of the chain in slot c, written as the state machine reaches
@@ -447,7 +448,7 @@ enum { LS_POP = 0, LS_ADVANCE = 1, LS_EVENT = 2, LS_TRACE = 3, LS_DONE = 4 };
 // once ev_pct percent of the lanes tracing or waiting for an event do, and the
 // traversal otherwise.  So traversal keeps most lanes busy, and the long
 // ADVANCE code runs for many chains at once.
-template <int L>
+template <int L, bool DELTA>
 __global__ void __launch_bounds__(256) k_step_sm(KParams P, DevScene S, KBufs B, uint32_t nsteps, int sorted,
                                                  int ev_pct, int adv_pct) {
     extern __shared__ uint32_t s_stack[];
@@ -501,7 +502,7 @@ __global__ void __launch_bounds__(256) k_step_sm(KParams P, DevScene S, KBufs B,
                     if (sorted) B.key[c] = alive ? (uint32_t)ps.nv : (uint32_t)(DR_NBIN - 1);
                     kills += alive ? 0u : 1u;
                     if (alive) {
-                        score_at<L>(P, B, S, c, p);
+                        score_at<L, DELTA>(P, B, S, c, p);
                         ++adj;
                     }
                     ++steps;
@@ -516,7 +517,7 @@ __global__ void __launch_bounds__(256) k_step_sm(KParams P, DevScene S, KBufs B,
                         move(P.seed, P.d, P.N, P.stddev, P.gt, xc, B.score + c, B.sigma ? B.sigma + id : nullptr, id,
                              s);
                     ps.phase = PH_NEW;
-                    sm_event<L>(S, C, SoaU{xc, P.N}, ps, q, StepRec<L>{B.rec, P.N, c}, ctr);
+                    sm_event<L, DELTA>(S, C, SoaU{xc, P.N}, ps, q, StepRec<L>{B.rec, P.N, c}, ctr);
                     state = LS_TRACE;
                 } else {
                     state = LS_POP;
@@ -524,7 +525,7 @@ __global__ void __launch_bounds__(256) k_step_sm(KParams P, DevScene S, KBufs B,
             }
         } else if (ne && (nt == 0 || 100 * ne >= ev_pct * (nt + ne))) {
             if (state == LS_EVENT) {
-                if (sm_event<L>(S, C, SoaU{B.x + c, P.N}, ps, q, StepRec<L>{B.rec, P.N, c}, ctr)) {
+                if (sm_event<L, DELTA>(S, C, SoaU{B.x + c, P.N}, ps, q, StepRec<L>{B.rec, P.N, c}, ctr)) {
                     state = LS_TRACE;
                 } else {
                     state = LS_ADVANCE;
@@ -856,6 +857,7 @@ struct dr_scene {
     uint32_t cam_version = 0;
     uint32_t n_tris = 0;
     uint32_t n_nodes = 0;
+    bool has_delta = false;  // a triangle has a smooth conductor or dielectric
 };
 
 struct dr_chains {
@@ -905,15 +907,23 @@ static void launch_init_acc(dim3 g, dim3 b, hipStream_t st, const KParams& P, co
 }
 template <int L>
 static void launch_fused(dim3 g, dim3 b, hipStream_t st, const KParams& P, const DevScene& S, const KBufs& B,
-                         uint32_t n, uint32_t grab, bool pair, int sorted) {
+                         uint32_t n, uint32_t grab, bool pair, int sorted, bool delta) {
     const size_t lds = stack_bytes(S, b.x) + (size_t)S.n_top * sizeof(DevNode);
-    if (pair) hipLaunchKernelGGL(k_step_fused_pair<L>, g, b, lds, st, P, S, B, n, grab, sorted);
-    else hipLaunchKernelGGL(k_step_fused<L>, g, b, lds, st, P, S, B, n, grab, sorted);
+    if (delta) {
+        if (pair) hipLaunchKernelGGL((k_step_fused_pair<L, true>), g, b, lds, st, P, S, B, n, grab, sorted);
+        else hipLaunchKernelGGL((k_step_fused<L, true>), g, b, lds, st, P, S, B, n, grab, sorted);
+    } else {
+        if (pair) hipLaunchKernelGGL((k_step_fused_pair<L, false>), g, b, lds, st, P, S, B, n, grab, sorted);
+        else hipLaunchKernelGGL((k_step_fused<L, false>), g, b, lds, st, P, S, B, n, grab, sorted);
+    }
 }
 template <int L>
 static void launch_sm(dim3 g, dim3 b, hipStream_t st, const KParams& P, const DevScene& S, const KBufs& B, uint32_t n,
-                      int sorted, int ev_pct, int adv_pct) {
-    hipLaunchKernelGGL(k_step_sm<L>, g, b, stack_bytes(S, b.x), st, P, S, B, n, sorted, ev_pct, adv_pct);
+                      int sorted, int ev_pct, int adv_pct, bool delta) {
+    if (delta)
+        hipLaunchKernelGGL((k_step_sm<L, true>), g, b, stack_bytes(S, b.x), st, P, S, B, n, sorted, ev_pct, adv_pct);
+    else
+        hipLaunchKernelGGL((k_step_sm<L, false>), g, b, stack_bytes(S, b.x), st, P, S, B, n, sorted, ev_pct, adv_pct);
 }
 template <int L>
 static void launch_plain_score(dim3 g, dim3 b, hipStream_t st, const KParams& P, const DevScene& S, const KBufs& B) {
@@ -980,7 +990,7 @@ static void enqueue_steps(dr_chains* c, uint32_t n_steps, hipStream_t st) {
             int blocks = (int)(c->n_cu * c->launch.blocks_per_cu);
             blocks = (int)std::max(1L, std::min((long)blocks, ((long)N + blk - 1) / blk));
             DR_DISPATCH_L(P.L, launch_sm, dim3(blocks), dim3(blk), st, P, c->scene->ds, c->kb, n_steps, sorted,
-                          (int)c->launch.refill_event_pct, (int)c->launch.refill_advance_pct);
+                          (int)c->launch.refill_event_pct, (int)c->launch.refill_advance_pct, c->scene->has_delta);
             return;
         }
         const bool pair = c->launch.lanes_per_chain == 2;
@@ -997,7 +1007,7 @@ static void enqueue_steps(dr_chains* c, uint32_t n_steps, hipStream_t st) {
         if (stack_b + (size_t)S.n_top * sizeof(DevNode) > (size_t)c->lds_limit)
             S.n_top = (int)(((size_t)c->lds_limit > stack_b ? (size_t)c->lds_limit - stack_b : 0) / sizeof(DevNode));
         DR_DISPATCH_L(P.L, launch_fused, dim3(blocks), dim3(blk), st, P, S, c->kb, n_steps, c->launch.grab, pair,
-                      sorted);
+                      sorted, c->scene->has_delta);
     } else {
         const int blk = 256;
         const dim3 g((N + blk - 1) / blk), b(blk);
@@ -1079,8 +1089,12 @@ dr_status dr_scene_create(const dr_scene_desc* desc, int device, dr_scene** out)
     for (uint32_t t = 0; t < T; ++t)
         if (desc->tri_material[t] >= desc->n_materials)
             return fail(DR_ERR_INVALID_ARG, "dr_scene_create: material index out of range");
-    for (uint32_t m = 0; m < desc->n_materials; ++m)
-        if (desc->materials[m].kind > 1) return fail(DR_ERR_INVALID_ARG, "dr_scene_create: unknown material kind");
+    for (uint32_t m = 0; m < desc->n_materials; ++m) {
+        const dr_material& q = desc->materials[m];
+        if (q.kind > DR_MAT_SMOOTH_DIELECTRIC) return fail(DR_ERR_INVALID_ARG, "dr_scene_create: unknown material kind");
+        if (q.kind == DR_MAT_SMOOTH_DIELECTRIC && !(q.eta > 0.0f && std::isfinite(q.eta)))
+            return fail(DR_ERR_INVALID_ARG, "dr_scene_create: dielectric eta must be finite and > 0");
+    }
 
     // BVH: given or built here
     std::vector<dr_bvh_node> nodes;
@@ -1278,7 +1292,7 @@ dr_status dr_scene_create(const dr_scene_desc* desc, int device, dr_scene** out)
         const dr_material& q = desc->materials[m];
         mats[3 * m] = make_float4((float)q.kind, q.albedo[0], q.albedo[1], q.albedo[2]);
         mats[3 * m + 1] = make_float4(q.roughness, q.f0[0], q.f0[1], q.f0[2]);
-        mats[3 * m + 2] = make_float4(q.Le[0], q.Le[1], q.Le[2], 0.f);
+        mats[3 * m + 2] = make_float4(q.Le[0], q.Le[1], q.Le[2], q.kind == DR_MAT_SMOOTH_DIELECTRIC ? q.eta : 0.f);
     }
     std::vector<float4> lights(5 * desc->n_lights);
     for (uint32_t l = 0; l < desc->n_lights; ++l) {
@@ -1347,6 +1361,8 @@ dr_status dr_scene_create(const dr_scene_desc* desc, int device, dr_scene** out)
     S->cam = desc->camera;
     S->slot_to_prim = std::move(slot_to_prim);
     S->n_tris = T;
+    for (uint32_t t = 0; t < T && !S->has_delta; ++t)
+        S->has_delta = desc->materials[desc->tri_material[t]].kind >= DR_MAT_SMOOTH_CONDUCTOR;
     *out = S;
     g_err.clear();
     return DR_OK;

@@ -67,8 +67,8 @@ enum { PH_NEW = 0, PH_CAM = 1, PH_SHADOW = 2, PH_CONT = 3 };
 
 // Path state of one lane between ray queries.
 struct PathSM {
-    int phase, j, slot, li, nv;  // nv: vertices of the finished path
-    bool shadow, cont;
+    int phase, j, slot, li, nv;  // nv: vertices of the finished path; li: the lobe at a delta vertex
+    bool shadow, cont, delta;
     float cx, cy, r2;
     V3 x, d, n, beta, f, wi, wt, wl;
 };
@@ -76,7 +76,7 @@ struct PathSM {
 // Sets up the vertex at path.slot (the NEE and BSDF candidates of vertex j)
 // and issues its first ray.  Returns true when a ray is in flight; false when
 // the path is finished (path.phase == PH_NEW afterwards).
-template <int L, class U, class Rec>
+template <int L, bool DELTA, class U, class Rec>
 __device__ __forceinline__ bool sm_vertex(const DevScene& S, const U& u, PathSM& P, RayQ& q, const Rec& rec,
                                           Counters& ctr);
 
@@ -108,13 +108,15 @@ __device__ __forceinline__ bool sm_after_shadow(const DevScene& S, const U& u, P
     return false;
 }
 
-template <int L, class U, class Rec>
+template <int L, bool DELTA, class U, class Rec>
 __device__ __forceinline__ bool sm_vertex(const DevScene& S, const U& u, PathSM& P, RayQ& q, const Rec& rec,
                                           Counters& ctr) {
     const int j = P.j;
     const DevTri T = S.tris[P.slot];
     const Material m = load_material(S, __float_as_uint(T.e1.w));
-    P.n = facing_normal(T, P.d);
+    bool front;
+    P.n = facing_normal(T, P.d, front);
+    P.delta = DELTA && is_delta(m);
     const V3 wo = -P.d;
     float ap;
     const float a = u(4 * j - 2), b = u(4 * j - 1);
@@ -129,11 +131,16 @@ __device__ __forceinline__ bool sm_vertex(const DevScene& S, const U& u, PathSM&
     P.wl = w * (1.0f / r);
     P.cx = dot(P.n, P.wl);
     P.cy = -dot(xyz(l3), P.wl);
-    P.shadow = P.cx > 1e-6f && P.cy > 1e-6f;
+    P.shadow = !P.delta && P.cx > 1e-6f && P.cy > 1e-6f;
     P.wi = v3(0.f, 0.f, 1.f);
     P.wt = v3(0.f, 0.f, 0.f);
-    P.cont = j < L - 1 && !(P.beta.x == 0.0f && P.beta.y == 0.0f && P.beta.z == 0.0f) &&
-             bsdf_sample(m, P.n, wo, u(4 * j), u(4 * j + 1), P.wi, P.wt);
+    int lobe = -1;
+    P.cont = j < L - 1 && !(P.beta.x == 0.0f && P.beta.y == 0.0f && P.beta.z == 0.0f);
+    if (P.cont) {
+        if (P.delta) delta_sample(m, P.n, front, wo, u(4 * j), P.wi, P.wt, lobe);
+        else P.cont = bsdf_sample(m, P.n, wo, u(4 * j), u(4 * j + 1), P.wi, P.wt);
+    }
+    if (P.delta) P.li = max(lobe, 0);  // recorded in the light field
     if (P.shadow) {
         P.phase = PH_SHADOW;
         if (ray_begin(S, q, P.x, P.wl, (1.0f - 1e-4f) * r, true, ctr)) return true;
@@ -144,8 +151,9 @@ __device__ __forceinline__ bool sm_vertex(const DevScene& S, const U& u, PathSM&
 // Event of one lane whose query has finished (or that holds a new path, phase
 // PH_NEW with its coordinates in u): advances the path to its next ray query.
 // Returns true when a ray is in flight afterwards, false when the path is
-// finished (rec.finish has been called and phase is PH_NEW again).
-template <int L, class U, class Rec>
+// finished (rec.finish has been called and phase is PH_NEW again).  DELTA:
+// false compiles the delta-lobe handling out.
+template <int L, bool DELTA = true, class U, class Rec>
 __device__ __forceinline__ bool sm_event(const DevScene& S, const Cam& C, const U& u, PathSM& P, RayQ& q,
                                          const Rec& rec, Counters& ctr) {
     if (P.phase == PH_NEW) {
@@ -172,9 +180,9 @@ __device__ __forceinline__ bool sm_event(const DevScene& S, const Cam& C, const 
         P.x = C.eye + P.d * q.bt;
         const DevTri T = S.tris[P.slot];
         const Material m = load_material(S, __float_as_uint(T.e1.w));
-        if (dot(cross(xyz(T.e1), xyz(T.e2)), P.d) < 0.0f) P.f = P.f + m.Le;
+        if (faces_ray(T, P.d)) P.f = P.f + m.Le;
         P.beta = v3(1.f, 1.f, 1.f);
-        return sm_vertex<L>(S, u, P, q, rec, ctr);
+        return sm_vertex<L, DELTA>(S, u, P, q, rec, ctr);
     }
     if (P.phase == PH_SHADOW) return sm_after_shadow<L>(S, u, P, q, q.best >= 0, rec, ctr);
     // PH_CONT
@@ -189,7 +197,11 @@ __device__ __forceinline__ bool sm_event(const DevScene& S, const Cam& C, const 
     P.d = P.wi;
     P.slot = q.best;
     ++P.j;
-    return sm_vertex<L>(S, u, P, q, rec, ctr);
+    if (DELTA && P.delta) {  // emission seen through the delta vertex
+        const DevTri T = S.tris[P.slot];
+        if (faces_ray(T, P.d)) P.f = P.f + mul(P.beta, load_material(S, __float_as_uint(T.e1.w)).Le);
+    }
+    return sm_vertex<L, DELTA>(S, u, P, q, rec, ctr);
 }
 
 }  // namespace dr

@@ -45,7 +45,10 @@ class dr_quad_light(C.Structure):
 
 class dr_material(C.Structure):
     _fields_ = [("kind", C.c_uint32), ("albedo", C.c_float * 3), ("roughness", C.c_float), ("f0", C.c_float * 3),
-                ("Le", C.c_float * 3)]
+                ("Le", C.c_float * 3), ("eta", C.c_float)]
+
+
+DR_MAT_LAMBERT, DR_MAT_GGX_CONDUCTOR, DR_MAT_SMOOTH_CONDUCTOR, DR_MAT_SMOOTH_DIELECTRIC = 0, 1, 2, 3
 
 
 class dr_bvh_node(C.Structure):
@@ -250,6 +253,7 @@ def dr_scene_create(sc: dict, device: int = 0, bvh=None):
         mats[i].roughness = float(q[4])
         mats[i].f0[:] = [float(v) for v in q[5:8]]
         mats[i].Le[:] = [float(v) for v in q[8:11]]
+        mats[i].eta = float(q[11]) if q.shape[0] > 11 else 1.0
     lights = (dr_quad_light * Lt.shape[0])()
     for i, q in enumerate(Lt):
         lights[i].p0[:] = [float(v) for v in q[0:3]]

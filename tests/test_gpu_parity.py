@@ -42,6 +42,7 @@ def scenes():
     out = {}
     out["tiny"] = inputs.cornell_tiny()
     out["spheres_small"] = inputs.procedural_spheres(n_spheres=3, subdiv=3, width=128, height=128)
+    out["specular"] = inputs.specular_box()
     return out
 
 
@@ -83,7 +84,7 @@ def _eval_both(orc, sc, L, n, seed):
     return u, (f, logp, g), (fo, po, go), match
 
 
-@pytest.mark.parametrize("which,L,n", [("tiny", 4, 4000), ("spheres_small", 8, 3000)])
+@pytest.mark.parametrize("which,L,n", [("tiny", 4, 4000), ("spheres_small", 8, 3000), ("specular", 8, 4000)])
 def test_eval_matches_oracle(orc, scenes, which, L, n):
     say(f"[eval parity] scene={which} L={L} n={n}")
     u, (f, logp, g), (fo, po, go), match = _eval_both(orc, scenes[which], L, n, seed=5)
@@ -107,7 +108,7 @@ def test_eval_matches_oracle(orc, scenes, which, L, n):
     assert np.all(g[zero] == 0)
 
 
-@pytest.mark.parametrize("which,L,n", [("tiny", 4, 3000), ("spheres_small", 8, 20000)])
+@pytest.mark.parametrize("which,L,n", [("tiny", 4, 3000), ("spheres_small", 8, 20000), ("specular", 8, 20000)])
 def test_forward_only_eval_matches_eval_with_score(scenes, which, L, n):
     """Forward-only evaluation (the ray-refill evaluator) returns exactly the
     f, log p and path records of the evaluation that also runs the adjoint."""
@@ -276,7 +277,7 @@ def _compare_step(orc, sc, L, st, gs, os_, idx, seed, step0, k0, dt=1e-5, eps=1e
 
 
 @pytest.mark.parametrize("mode", [dr.DR_MODE_FUSED, dr.DR_MODE_PLAIN])
-@pytest.mark.parametrize("which,L,N", [("tiny", 4, 1000), ("spheres_small", 8, 1500),
+@pytest.mark.parametrize("which,L,N", [("tiny", 4, 1000), ("spheres_small", 8, 1500), ("specular", 8, 1500),
                                        # degenerate shapes: one chain, the shortest path (d = 4), ragged counts
                                        ("tiny", 2, 1), ("tiny", 2, 129), ("spheres_small", 3, 77)])
 def test_one_step_matches_oracle(orc, scenes, which, L, N, mode):
@@ -523,7 +524,7 @@ def test_scene_stats(scenes):
         assert st["stack_bytes_per_lane"] == 4 * st["stack_entries"]
 
 
-@pytest.mark.parametrize("which,L,N", [("tiny", 4, 1000), ("spheres_small", 8, 3000)])
+@pytest.mark.parametrize("which,L,N", [("tiny", 4, 1000), ("spheres_small", 8, 3000), ("specular", 8, 3000)])
 def test_paired_lanes_match_single_lane(scenes, which, L, N):
     """Two lanes per chain (continuation and shadow rays traced concurrently)
     must give exactly the chains one lane per chain gives."""
@@ -569,7 +570,7 @@ def test_length_ordering_matches_identity_order(scenes, lanes, order):
     assert np.allclose(a["accum"], b["accum"], rtol=1e-5, atol=1e-6)
 
 
-@pytest.mark.parametrize("which,L,N", [("tiny", 4, 1500), ("spheres_small", 8, 5000)])
+@pytest.mark.parametrize("which,L,N", [("tiny", 4, 1500), ("spheres_small", 8, 5000), ("specular", 8, 5000)])
 def test_refill_form_matches_straight_line(scenes, which, L, N):
     """The ray-refill form of the fused kernel (lanes refill with their next
     ray or step while others traverse) gives exactly the chains of the
@@ -670,12 +671,16 @@ def test_large_configs_sampled_parity(orc, name):
     _compare_step(orc, sc, L, st, gs, os_, idx, 91, step0, 100.0)
 
 
-def test_adjoint_long_paths_with_segment_recompute(orc):
+@pytest.mark.parametrize("which", ["interior", "specular"])
+def test_adjoint_long_paths_with_segment_recompute(orc, which):
     """Path length 16 (d = 60): the adjoint keeps one checkpoint per 8-vertex
-    segment and recomputes each segment in the reverse sweep.  Checked against
-    the oracle's forward-mode score and central differences (h = 1e-3) on the
-    device."""
-    sc = inputs.procedural_interior(n_inst=40, subdiv=3, width=320, height=180)
+    segment and recomputes each segment in the reverse sweep (through delta
+    vertices too, in the specular box).  Checked against the oracle's
+    forward-mode score and central differences (h = 1e-3) on the device."""
+    if which == "interior":
+        sc = inputs.procedural_interior(n_inst=40, subdiv=3, width=320, height=180)
+    else:
+        sc = inputs.specular_box(width=128, height=128)
     L, n, h = 16, 1024, 1e-3
     d = 4 * (L - 1)
     say(f"[adjoint L16] {sc['indices'].shape[0]} triangles, n={n}")
@@ -707,6 +712,44 @@ def test_adjoint_long_paths_with_segment_recompute(orc):
         bad += (same & (np.abs(fd - g[:, i]) > tol)).sum()
     say(f"  FD checked {checked}, outside tolerance {bad}")
     assert checked > 5000 and bad <= 0.01 * checked
+
+
+def test_delta_closed_forms_on_device():
+    """The closed forms that pin the oracle's delta lobes, on the device: a
+    light seen in a smooth-conductor plane at normal incidence is f0 Le; a
+    glass slab's branch values (through-through Le, reflection first 0, two
+    internal reflections then out Le); the n^2 radiance law from inside."""
+    Le = np.array([4.0, 3.0, 2.0])
+    say("[delta closed forms] mirror plane, glass slab, camera inside the slab")
+
+    def f_at(sc, L, rows):
+        S = dr.Scene(sc)
+        u = torch.tensor(np.asarray(rows, np.float32)).cuda()
+        f, _, _, _ = S.eval_logp_grad(L, u, grad=True, rec=True)
+        torch.cuda.synchronize()
+        return f.cpu().numpy().astype(np.float64)
+
+    sc = inputs.mirror_plane(f0=(0.9, 0.6, 0.3), Le=tuple(Le))
+    f0 = sc["materials"][0, 5:8].astype(np.float64)
+    u = np.full((1, 8), 0.3)
+    u[0, :2] = 0.5
+    assert np.allclose(f_at(sc, 3, u)[0], f0 * Le, rtol=1e-6)
+
+    L = 6
+    rows = []
+    for ch in ([0.9, 0.9], [0.01], [0.9, 0.01, 0.01, 0.9], [0.9, 0.01, 0.9]):
+        r = np.full(4 * (L - 1), 0.5)
+        for j, c in enumerate(ch):
+            r[4 * (j + 1)] = c
+        rows.append(r)
+    f = f_at(inputs.glass_slab(eta=1.5, Le=tuple(Le)), L, rows)
+    assert np.allclose(f[0], Le, rtol=1e-5) and np.all(f[1] == 0)
+    assert np.allclose(f[2], Le, rtol=1e-5) and np.all(f[3] == 0)
+
+    r = np.full(12, 0.5)
+    r[4] = 0.9
+    f = f_at(inputs.glass_slab(eta=1.5, Le=tuple(Le), eye_z=-1.25), 4, [r])
+    assert np.allclose(f[0], 1.5 ** 2 * Le, rtol=1e-5)
 
 
 def test_torch_allocator_serves_library_buffers(scenes):

@@ -159,3 +159,18 @@ def test_null_handles_rejected(L):
     assert L.dr_set_allocator(dr.ALLOC_FN(), dr.FREE_FN(), None) == dr.DR_OK
     assert L.dr_chains_destroy(None) == dr.DR_OK
     assert b"null" in L.dr_last_error() or L.dr_last_error() == b""
+
+
+def test_scene_create_validates_materials(L):
+    """Material kinds beyond the smooth dielectric, and a dielectric whose
+    index of refraction is not finite and positive, are rejected before any
+    device work."""
+    sc = inputs.specular_box()
+    glass = int(np.nonzero(sc["materials"][:, 0] == inputs.KIND_GLASS)[0][0])
+    for col, val, msg in ((0, 7.0, "material kind"), (11, 0.0, "eta"), (11, np.nan, "eta"), (11, -1.5, "eta")):
+        bad = dict(sc)
+        bad["materials"] = sc["materials"].copy()
+        bad["materials"][glass, col] = val
+        with pytest.raises(dr.DrError) as e:
+            dr.dr_scene_create(bad, 0)
+        assert e.value.status == dr.DR_ERR_INVALID_ARG and msg in str(e.value)
