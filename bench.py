@@ -49,7 +49,7 @@ def parse():
                     help="only run warmup + steps of the fused form (for hardware-counter runs)")
     ap.add_argument("--config", default=None,
                     help="measure a named larger configuration instead of the headline line (instances, "
-                         "spheres_1080p_L16, interior); prints its own JSON line")
+                         "spheres_1080p_L16, interior, spheres_specular); prints its own JSON line")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates the FETCH_SIZE/WRITE_SIZE counters)")
     ap.add_argument("--traffic-summary", nargs="+", metavar="DIR",

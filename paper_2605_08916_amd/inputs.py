@@ -305,11 +305,15 @@ def _plane(B, size, n, z0, mat):
     B.add_mesh(V, I, mat)
 
 
-def procedural_spheres(seed: int = 1, width: int = 512, height: int = 512, n_spheres: int = 10, subdiv: int = 4) -> dict:
+def procedural_spheres(seed: int = 1, width: int = 512, height: int = 512, n_spheres: int = 10, subdiv: int = 4,
+                       specular: bool = False) -> dict:
     """Noise-displaced icospheres (subdivision 4, 5,120 triangles each) on a
     tessellated ground plane; GGX conductors with roughness U[0.1, 0.5] and F0
     U[0.5, 0.95] per object; Lambertian 0.5 ground; two quad lights, each
-    partly occluded by a seeded blocker quad.  About 53k triangles."""
+    partly occluded by a seeded blocker quad.  About 53k triangles.  With
+    `specular`, every third sphere (k = 1 mod 3) is a smooth dielectric
+    (eta 1.5) and the next (k = 2 mod 3) a smooth conductor with the drawn
+    F0; the seeded draws, hence the geometry, are those of the default."""
     rng = np.random.default_rng(seed)
     B = _Builder()
     Vs, Fs = icosphere(subdiv)
@@ -323,7 +327,13 @@ def procedural_spheres(seed: int = 1, width: int = 512, height: int = 512, n_sph
             if all(np.linalg.norm(c[[0, 2]] - q[[0, 2]]) > (r + rq) * 1.2 for q, rq in placed):
                 break
         placed.append((c, r))
-        m = B.add_material(material(KIND_GGX, rough=rng.uniform(0.1, 0.5), f0=rng.uniform(0.5, 0.95, 3)))
+        rough, f0 = rng.uniform(0.1, 0.5), rng.uniform(0.5, 0.95, 3)
+        if specular and k % 3 == 1:
+            m = B.add_material(material(KIND_GLASS, eta=1.5))
+        elif specular and k % 3 == 2:
+            m = B.add_material(material(KIND_MIRROR, f0=f0))
+        else:
+            m = B.add_material(material(KIND_GGX, rough=rough, f0=f0))
         V = displaced(Vs, seed * 1000 + k) @ _rot(rng).T * r + c
         B.add_mesh(V, Fs, m)
     blocker = B.add_material(material(KIND_LAMBERT, albedo=(0.3, 0.3, 0.3)))
@@ -454,5 +464,6 @@ CONFIGS = {
     "spheres": (procedural_spheres, 8, 65536),
     "instances": (procedural_instances, 12, 1 << 20),
     "spheres_1080p_L16": (lambda seed=1: procedural_spheres(seed, 1920, 1080), 16, 1 << 21),
+    "spheres_specular": (lambda seed=1: procedural_spheres(seed, specular=True), 8, 65536),
     "interior": (procedural_interior, 8, 1 << 22),
 }

@@ -653,13 +653,13 @@ def test_captured_frames_replay_like_eager(scenes):
     frame.close()
 
 
-@pytest.mark.parametrize("name", ["instances", "spheres_1080p_L16", "interior"])
+@pytest.mark.parametrize("name", ["instances", "spheres_1080p_L16", "interior", "spheres_specular"])
 def test_large_configs_sampled_parity(orc, name):
     """The larger configurations at their real shapes: ~1M triangles with
     path length 12 and 1M chains; path length 16 with per-chain diagonal
     Sigma at 1920x1080 and 2M chains; ~2M triangles at 1920x1080 with 4M
-    chains.  One fused step on every chain, 512 sampled chains against the
-    oracle."""
+    chains; the 53k-triangle spheres with glass and mirror spheres.  One
+    fused step on every chain, 512 sampled chains against the oracle."""
     factory, L, N = inputs.CONFIGS[name]
     sc = factory()
     d = 4 * (L - 1)
