@@ -752,6 +752,34 @@ def test_delta_closed_forms_on_device():
     assert np.allclose(f[0], 1.5 ** 2 * Le, rtol=1e-5)
 
 
+def test_device_matches_stored_oracle_values():
+    """The device against the oracle values stored in tests/golden (written by
+    the oracle from seeded points on the tiny box, the specular box and the
+    mirror plane): path records equal, f and the score within the FP32
+    tolerances of the live parity tests."""
+    import json
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_paths.json")) as fh:
+        gold = json.load(fh)
+    for case in gold["cases"]:
+        say(f"[golden] {case['name']}: scene={case['scene']} L={case['L']} n={case['n']}")
+        L = case["L"]
+        S = dr.Scene(getattr(inputs, case["scene"])())
+        u = torch.tensor(np.asarray(case["u"], np.float32)).cuda()
+        f, logp, g, rec = S.eval_logp_grad(L, u, rec=True)
+        torch.cuda.synchronize()
+        f, g = f.cpu().numpy().astype(np.float64), g.cpu().numpy().astype(np.float64)
+        rec = rec.cpu().numpy().view(np.uint32)
+        ro = np.asarray(case["rec"], np.int64)
+        prim, nee = ro[:, 0::2], ro[:, 1::2]
+        rec_o = np.where(prim >= 0, (prim << 8) | (nee & 0xFF), 0xFFFFFFFF).astype(np.uint32)
+        assert np.array_equal(rec_o, rec), case["name"]
+        fo, po, go = np.asarray(case["f"]), np.asarray(case["p"]), np.asarray(case["score"])
+        _bulk_and_bound(_rel(f, fo, 1e-3 * max(1e-6, np.abs(fo).mean())).max(axis=1), 1e-4, 1e-2, frac=0.95)
+        live = po > 1e-3 * po.mean()
+        err = np.linalg.norm(g[live] - go[live], axis=1) / np.maximum(np.linalg.norm(go[live], axis=1), 1e-6)
+        assert np.median(err) < 1e-5 and err.max() < 1e-2, (case["name"], np.median(err), err.max())
+
+
 def test_torch_allocator_serves_library_buffers(scenes):
     """With torch's caching allocator installed as the library's allocator,
     chain buffers and evaluation scratch come from torch, the results are the

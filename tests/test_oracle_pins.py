@@ -740,3 +740,20 @@ def test_all_black_initialisation(orc):
     assert acc["k0"] == pytest.approx(1e-8 / (64 * 1e-5), rel=1e-12)
     assert acc["tour_count"] > 0
     assert np.all(acc["accum"] == 0) and np.all(C.resolve() == 0)
+
+
+def test_oracle_reproduces_its_golden_fixture(orc):
+    """Regression guard (not a pin): the oracle still returns the values that
+    tests/golden/make_golden.py stored from it (f, p, score, path record), so
+    a change to its arithmetic cannot pass unnoticed."""
+    import json
+    with open(os.path.join(HERE, "golden", "oracle_paths.json")) as fh:
+        gold = json.load(fh)
+    for case in gold["cases"]:
+        sc = getattr(inputs, case["scene"])()
+        u = np.asarray(case["u"], np.float64)
+        f, p, score, rec = orc.Scene(sc).path_eval(case["L"], u, eps=gold["eps"])
+        assert np.array_equal(rec.astype(np.int64), np.asarray(case["rec"], np.int64)), case["name"]
+        np.testing.assert_allclose(f, np.asarray(case["f"]), rtol=1e-12, atol=0, err_msg=case["name"])
+        np.testing.assert_allclose(p, np.asarray(case["p"]), rtol=1e-12, atol=0, err_msg=case["name"])
+        np.testing.assert_allclose(score, np.asarray(case["score"]), rtol=1e-9, atol=1e-12, err_msg=case["name"])
