@@ -221,7 +221,10 @@ dr_status dr_chains_destroy(dr_chains* c);
  *  f_over_p      3 x N float
  *  path_rec      (L-1) x N uint32 per vertex: (triangle << 8 | light << 1 |
  *                next-event contribution) or 0xFFFFFFFF for no vertex; the
- *                triangle is the original (input) index
+ *                triangle is the original (input) index; at a smooth
+ *                conductor or dielectric vertex the light field holds the
+ *                lobe (0 reflection, 1 refraction) and the contribution
+ *                bit is 0
  *  step          next global step index; tour_count; k0; p_lambda_hat */
 typedef struct {
     float* x; float* score; uint32_t* killed; float* accum;
