@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-mrse", action="store_true")
+    ap.add_argument("--no-scaling", action="store_true",
+                    help="skip the larger chain counts reported beside the headline line")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--chains", type=int, default=65536)
     ap.add_argument("--steps-per-frame", type=int, default=8)
@@ -170,6 +172,55 @@ def read_traffic(chains, per_launch):
             or int(kv.get("steps_per_launch", -1)) != per_launch):
         return None
     return float(kv["hbm_bytes_per_launch"])
+
+
+def alg_bytes_per_chain_step(rays, nodes, tris, d, L):
+    """Algorithmic bytes per chain-step of the fused kernel: state x and score
+    read+write, killed flag read+write, path record write+read, 4-wide BVH
+    nodes (128 B per visit) and triangles (48 B per test) fetched by
+    traversal, the material/light records per vertex, and the 3-channel
+    splat read-modify-write."""
+    verts = rays / 2.0
+    b_state = 16 * d + 8 + 8 * (L - 1)
+    b_trav = nodes * 128 + tris * 48
+    b_shade = verts * (48 + 48 + 80)
+    b_splat = 24
+    return b_state + b_trav + b_shade + b_splat
+
+
+def traversal_work(ch, warm=3, n=4):
+    """Rays, node visits, triangle tests and adjoint fraction per chain-step
+    from the library's counters (a separate, untimed pass)."""
+    for _ in range(warm):
+        ch.step(1)
+    ch.set_counters(True)
+    b0 = ch.stats()
+    ch.step(n)
+    b1 = ch.stats()
+    ch.set_counters(False)
+    cs = b1["chain_steps"] - b0["chain_steps"]
+    return tuple((b1[k] - b0[k]) / cs for k in ("rays", "node_visits", "tri_tests", "adjoints"))
+
+
+def chain_count_scaling(torch, dr, scene, L, F, hbm_copy, counts=(262144, 1048576)):
+    """The same scene and step at larger chain counts (the default launch rule
+    picks one lane per chain there): chain-steps/s and the algorithmic
+    bandwidth against the plain-copy bandwidth.  More resident wavefronts hide
+    more of the traversal's fetch latency."""
+    d = 4 * (L - 1)
+    out = []
+    for n in counts:
+        ch = dr.Chains(scene, n, L, 4048, mode=dr.DR_MODE_FUSED)
+        ms, _, _ = time_steps(ch, torch, 4 * F, F, F)
+        ms_launch = time_kernel_only(ch, torch, 3, F)
+        rays, nodes, tris, _ = traversal_work(ch, warm=0, n=2)
+        b = alg_bytes_per_chain_step(rays, nodes, tris, d, L)
+        gbs = b * n * F / (ms_launch * 1e-3) / 1e9
+        out.append({"chains": n, "value": n / (ms * 1e-3), "ms_per_step": ms, "lanes_per_chain":
+                    ch.get_launch()["lanes_per_chain"], "alg_GBs": gbs, "frac": gbs / HBM_PEAK_GBS,
+                    "frac_of_achievable": gbs / hbm_copy})
+        ch.close()
+    return out
 
 
 def lum(img):
@@ -414,21 +465,12 @@ def main():
     adj = (st["adjoints"] - base["adjoints"]) / csteps
     cc.close()
 
-    # algorithmic bytes per chain-step of the fused kernel: state x and score
-    # read+write, killed flag read+write, path record write+read, 4-wide BVH
-    # nodes (128 B per visit) and triangles (48 B per test) fetched by
-    # traversal, the material/light records per vertex, and the 3-channel
-    # splat read-modify-write.
-    verts = rays / 2.0
-    b_state = 16 * d + 8 + 8 * (L - 1)
-    b_trav = nodes * 128 + tris * 48
-    b_shade = verts * (48 + 48 + 80)
-    b_splat = 24
-    bytes_step = b_state + b_trav + b_shade + b_splat
+    bytes_step = alg_bytes_per_chain_step(rays, nodes, tris, d, L)
     achieved = bytes_step * N * F / (ms_launch * 1e-3) / 1e9
     traffic = read_traffic(N, F)
     counters = read_counters(N, F)
     hbm_copy = achievable_bandwidth(torch)
+    scaling_n = [] if a.no_scaling else chain_count_scaling(torch, dr, scene, L, F, hbm_copy)
 
     res = {
         "metric": "chain-steps/s (f+∇log f) and MRSE at 33 ms/frame, fused vs plain",
@@ -459,6 +501,7 @@ def main():
                      "traffic_unit": "HBM bytes per launch", "alg_bytes_per_launch": bytes_step * N * F,
                      "kernel": f"k_step_fused{'_pair' if launch_cfg['lanes_per_chain'] == 2 else ''}<{L}, false>",
                      "launch_ms": ms_launch, "steps_per_launch": F},
+        "chain_count_scaling": scaling_n,
     }
 
     ref = None
