@@ -409,6 +409,19 @@ def main():
     from paper_2605_08916_amd import dr, inputs
 
     torch.cuda.set_device(0)
+    if a.config and a.profile_only:
+        fac, L, N = inputs.CONFIGS[a.config]
+        scene = dr.Scene(fac())
+        sigma = None
+        if a.config == "spheres_1080p_L16":
+            sigma = torch.from_numpy(inputs.per_chain_sigma(4 * (L - 1), N, seed=4)).cuda()
+        ch = dr.Chains(scene, N, L, 2024, sigma=sigma)
+        F = max(1, a.steps_per_frame)
+        for _ in range(a.warmup + a.steps):
+            ch.step(F)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_only_launches": a.warmup + a.steps, "steps_per_launch": F, "config": a.config}))
+        return
     if a.config:
         run_config(a, torch, dr, inputs)
         return

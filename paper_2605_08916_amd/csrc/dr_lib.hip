@@ -157,7 +157,9 @@ __global__ void k_begin_init(KBufs B, uint32_t frame, int from_device) {
     B.steps[0] = (f << 32) + 1ull;
 }
 
-// Initialise, phase 1: x ~ mu and f(x) for every chain (Alg. 4.1).
+// Initialise, phase 1: x ~ mu and f(x) for every chain (Alg. 4.1).  DELTA:
+// the scene has smooth conductors or dielectrics.
+template <bool DELTA>
 __global__ void __launch_bounds__(256) k_init_eval(KParams P, DevScene S, KBufs B) {
     extern __shared__ uint32_t s_stack[];
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -166,8 +168,8 @@ __global__ void __launch_bounds__(256) k_init_eval(KParams P, DevScene S, KBufs 
     if (c < P.N) {
         regen(P.seed, P.d, P.N, B.x + c, c, s0);
         int nv;
-        const V3 f = path_forward<false>(S, P.L, SoaU{B.x + c, P.N}, B.rec + c, P.N, s_stack + threadIdx.x, blockDim.x,
-                                         ctr, &nv);
+        const V3 f = path_forward<false, DELTA>(S, P.L, SoaU{B.x + c, P.N}, B.rec + c, P.N, s_stack + threadIdx.x,
+                                                blockDim.x, ctr, &nv);
         B.p_tmp[c] = lum(f);
         B.f_tmp[c] = f.x;
         B.f_tmp[(size_t)P.N + c] = f.y;
@@ -739,6 +741,7 @@ struct PtU {  // generated coordinates: always finite
         return v;
     }
 };
+template <bool DELTA>
 __global__ void __launch_bounds__(256) k_pt(DevScene S, int L, uint64_t seed, uint32_t spp, float* img) {
     extern __shared__ uint32_t s_stack[];
     const int pix = blockIdx.x * blockDim.x + threadIdx.x;
@@ -748,7 +751,7 @@ __global__ void __launch_bounds__(256) k_pt(DevScene S, int L, uint64_t seed, ui
     V3 acc = v3(0.f, 0.f, 0.f);
     for (uint32_t k = 0; k < spp; ++k) {
         const PtU u{seed, (uint32_t)pix, (uint64_t)k, S.W, S.H, pix % S.W, pix / S.W};
-        acc = acc + path_forward<false>(S, L, u, nullptr, 0, s_stack + threadIdx.x, blockDim.x, ctr);
+        acc = acc + path_forward<false, DELTA>(S, L, u, nullptr, 0, s_stack + threadIdx.x, blockDim.x, ctr);
     }
     const float inv = 1.0f / (float)spp;
     img[pix] = acc.x * inv;
@@ -954,7 +957,10 @@ static void enqueue_init(dr_chains* c, uint32_t frame, int from_device, hipStrea
     hipLaunchKernelGGL(k_begin_init, dim3(1), dim3(64), 0, st, c->kb, frame, from_device);
     hipLaunchKernelGGL(k_fill_f32, dim3(1024), dim3(256), 0, st, c->kb.accum, 3 * npx);
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, c->kb.ctr, (int)C_N);
-    hipLaunchKernelGGL(k_init_eval, g, b, stack_bytes(c->scene->ds, blk), st, P, c->scene->ds, c->kb);
+    if (c->scene->has_delta)
+        hipLaunchKernelGGL(k_init_eval<true>, g, b, stack_bytes(c->scene->ds, blk), st, P, c->scene->ds, c->kb);
+    else
+        hipLaunchKernelGGL(k_init_eval<false>, g, b, stack_bytes(c->scene->ds, blk), st, P, c->scene->ds, c->kb);
     hipLaunchKernelGGL(k_reduce_p, dim3(c->n_partials), dim3(256), 0, st, P, c->kb);
     hipLaunchKernelGGL(k_finish_k0, dim3(1), dim3(64), 0, st, P, c->kb, c->n_partials, (double)c->P.k0, (double)c->P.m);
     const int with_score = c->P.mode == DR_MODE_FUSED ? 1 : 0;
@@ -1751,8 +1757,12 @@ dr_status dr_pt_render(dr_scene* s, uint32_t L, uint64_t seed, uint32_t spp, flo
     (void)hipGetLastError();  // drop a stale error left by an earlier, unrelated call
     const int npx = s->ds.W * s->ds.H;
     const int blk = 128;
-    hipLaunchKernelGGL(k_pt, dim3((npx + blk - 1) / blk), dim3(blk), stack_bytes(s->ds, blk), (hipStream_t)hip_stream, s->ds,
-                       (int)L, seed, spp, img_dev);
+    if (s->has_delta)
+        hipLaunchKernelGGL(k_pt<true>, dim3((npx + blk - 1) / blk), dim3(blk), stack_bytes(s->ds, blk),
+                           (hipStream_t)hip_stream, s->ds, (int)L, seed, spp, img_dev);
+    else
+        hipLaunchKernelGGL(k_pt<false>, dim3((npx + blk - 1) / blk), dim3(blk), stack_bytes(s->ds, blk),
+                           (hipStream_t)hip_stream, s->ds, (int)L, seed, spp, img_dev);
     HIP_TRY(hipGetLastError());
     g_err.clear();
     return DR_OK;
