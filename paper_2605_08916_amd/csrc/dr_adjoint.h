@@ -31,16 +31,24 @@ __device__ __forceinline__ uint32_t rec_slot(uint32_t r) { return r >> 8; }
 __device__ __forceinline__ int rec_light(uint32_t r) { return (int)((r >> 1) & 0x7Fu); }
 __device__ __forceinline__ bool rec_contrib(uint32_t r) { return (r & 1u) != 0; }
 
+// Division and square root in the adjoint: the hardware reciprocal and
+// square root (within 1 ulp), the quotient as a product with the reciprocal.  The adjoint divides often, and these roundings sit far below
+// the score's own conditioning.  (Directions and decisions are recomputed
+// with the forward path's own functions, so they stay bit-identical.)
+__device__ __forceinline__ float arcp(float b) { return __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ float adiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ float asqrt(float a) { return __builtin_amdgcn_sqrtf(a); }
+
 // d G1/dc / G1 for the separable Smith term.
 __device__ __forceinline__ float smith_dlog(float c, float a2) {
     const float c2 = c * c;
-    const float lam = sqrtf(1.0f + a2 * (1.0f - c2) / c2);
-    return a2 / (c2 * c * lam * (1.0f + lam));
+    const float lam = asqrt(1.0f + adiv(a2 * (1.0f - c2), c2));
+    return adiv(a2, c2 * c * lam * (1.0f + lam));
 }
 
 // Position of the hit on triangle T along (o, d): plane distance.
 __device__ __forceinline__ float plane_t(const DevTri& T, V3 ng, V3 o, V3 d) {
-    return dot(ng, xyz(T.v0) - o) / dot(ng, d);
+    return adiv(dot(ng, xyz(T.v0) - o), dot(ng, d));
 }
 
 // Camera vertex (vertex 1) state.
@@ -104,8 +112,9 @@ __device__ Adj reverse_vertex(const DevScene& S, int L, int j, const VState& s, 
         const DevTri Tn = S.tris[rec_slot(recn)];
         const V3 ngn = normalize(cross(xyz(Tn.e1), xyz(Tn.e2)));
         const float Dn = dot(ngn, wi);
-        const float tp = dot(ngn, xyz(Tn.v0) - s.x) / Dn;
-        const float sc = dot(an.gx, wi) / Dn;
+        const float iDn = arcp(Dn);
+        const float tp = dot(ngn, xyz(Tn.v0) - s.x) * iDn;
+        const float sc = dot(an.gx, wi) * iDn;
         const V3 gproj = an.gx - ngn * sc;
         gx = gx + gproj;
         const V3 gwi = gproj * tp + an.gd;
@@ -129,10 +138,10 @@ __device__ Adj reverse_vertex(const DevScene& S, int L, int j, const VState& s, 
             gwo = gwo - gwi + n * g_ci;
         } else {
             // wi = -wo / etap + (ci / etap - ct) n, ct^2 = 1 - (1 - ci^2) / etap^2; W constant
-            const float ie = 1.0f / rel_eta(m, front);
+            const float ie = arcp(rel_eta(m, front));
             float ct;
             fresnel_dielectric(ci, rel_eta(m, front), ct);
-            const float dct = ct > 0.0f ? ci * ie * ie / ct : 0.0f;
+            const float dct = ct > 0.0f ? adiv(ci * ie * ie, ct) : 0.0f;
             gwo = gwo - gwi * ie + n * (dot(gwi, n) * (ie - dct));
         }
     }
@@ -149,20 +158,21 @@ __device__ Adj reverse_vertex(const DevScene& S, int L, int j, const VState& s, 
         V3 h = v3(0.f, 0.f, 0.f);
         float oh = 0.f, ch = 0.f, sh = 0.f, co = 0.f, ci = 0.f, den = 1.f, r = 0.f, lz = 0.f, wg = 0.f;
         if (m.kind == 0) {
-            r = sqrtf(uu);
-            lz = sqrtf(1.0f - uu);
+            r = asqrt(uu);
+            lz = asqrt(1.0f - uu);
             wi = tt * (r * cp) + bb * (r * sp) + n * lz;
             W = m.albedo;
         } else {
             den = (1.0f - uu) + m.a2 * uu;
-            ch = sqrtf((1.0f - uu) / den);
-            sh = sqrtf(m.a2 * uu / den);
+            const float iden = arcp(den);
+            ch = asqrt((1.0f - uu) * iden);
+            sh = asqrt(m.a2 * uu * iden);
             h = tt * (sh * cp) + bb * (sh * sp) + n * ch;
             oh = dot(wo, h);
             wi = h * (2.0f * oh) - wo;
             ci = dot(n, wi);
             co = dot(n, wo);
-            wg = smith_g1(co, m.a2) * smith_g1(ci, m.a2) * oh / (co * ch);
+            wg = adiv(smith_g1(co, m.a2) * smith_g1(ci, m.a2) * oh, co * ch);
             const float om = 1.0f - oh;
             const float f5 = om * om * om * om * om;
             W = v3(wg * (m.f0.x + (1.0f - m.f0.x) * f5), wg * (m.f0.y + (1.0f - m.f0.y) * f5),
@@ -171,17 +181,18 @@ __device__ Adj reverse_vertex(const DevScene& S, int L, int j, const VState& s, 
         const DevTri Tn = S.tris[rec_slot(recn)];
         const V3 ngn = normalize(cross(xyz(Tn.e1), xyz(Tn.e2)));
         const float Dn = dot(ngn, wi);
-        const float tp = dot(ngn, xyz(Tn.v0) - s.x) / Dn;
+        const float iDn = arcp(Dn);
+        const float tp = dot(ngn, xyz(Tn.v0) - s.x) * iDn;
         // x' = x + tp wi with tp = ngn.(v0 - x)/(ngn.wi)
-        const float sc = dot(an.gx, wi) / Dn;
+        const float sc = dot(an.gx, wi) * iDn;
         const V3 gproj = an.gx - ngn * sc;
         gx = gx + gproj;
         V3 gwi = gproj * tp + an.gd;
         gb = gb + mul(an.gb, W);
         const V3 gW = mul(an.gb, s.beta);
         if (m.kind == 0) {
-            const float ir = 0.5f / r;
-            gu += dot(gwi, tt * (cp * ir) + bb * (sp * ir) - n * (0.5f / lz));
+            const float ir = 0.5f * arcp(r);
+            gu += dot(gwi, tt * (cp * ir) + bb * (sp * ir) - n * (0.5f * arcp(lz)));
             gv += dot(gwi, bb * cp - tt * sp) * (r * 2.0f * DR_PI);
         } else {
             // W_c = F_c(oh) wg, wg = G1(co) G1(ci) oh / (co ch)
@@ -193,10 +204,10 @@ __device__ Adj reverse_vertex(const DevScene& S, int L, int j, const VState& s, 
                              -5.0f * (1.0f - m.f0.z) * om4);
             const float gwg = dot(gW, F);                 // d/d wg
             const float g_oh_F = dot(gW, dF) * wg;        // through F(oh)
-            float g_oh = g_oh_F + gwg * wg / oh;
-            const float g_co = gwg * wg * (smith_dlog(co, m.a2) - 1.0f / co);
+            float g_oh = g_oh_F + adiv(gwg * wg, oh);
+            const float g_co = gwg * wg * (smith_dlog(co, m.a2) - arcp(co));
             const float g_ci = gwg * wg * smith_dlog(ci, m.a2);
-            const float g_ch = -gwg * wg / ch;
+            const float g_ch = adiv(-gwg * wg, ch);
             gwi = gwi + n * g_ci;
             // wi = 2 oh h - wo
             g_oh += 2.0f * dot(gwi, h);
@@ -206,8 +217,8 @@ __device__ Adj reverse_vertex(const DevScene& S, int L, int j, const VState& s, 
             gwo = gwo + h * g_oh + n * g_co;
             g_h = g_h + wo * g_oh;
             // h = tt (sh cos) + bb (sh sin) + n ch ; ch, sh functions of uu
-            const float dch = -m.a2 / (2.0f * ch * den * den);
-            const float dsh = m.a2 / (2.0f * sh * den * den);
+            const float dch = adiv(-m.a2, 2.0f * ch * den * den);
+            const float dsh = adiv(m.a2, 2.0f * sh * den * den);
             gu += dot(g_h, tt * cp + bb * sp) * dsh + (dot(g_h, n) + g_ch) * dch;
             gv += dot(g_h, bb * cp - tt * sp) * (sh * 2.0f * DR_PI);
         }
@@ -225,12 +236,13 @@ __device__ Adj reverse_vertex(const DevScene& S, int L, int j, const VState& s, 
         const V3 y = xyz(l0) + E1 * ap + E2 * b;
         const V3 w = y - s.x;
         const float r2 = dot(w, w);
-        const float r = sqrtf(r2);
-        const V3 wl = w * (1.0f / r);
+        const float r = asqrt(r2);
+        const V3 wl = w * arcp(r);
         const float cx = dot(n, wl);
         const float cy = -dot(NL, wl);
         const float Cc = (float)nl * l3.w;
-        const float g = cx * cy / r2 * Cc;
+        const float ir2 = arcp(r2);
+        const float g = cx * cy * ir2 * Cc;
         const V3 K = v3(0.2126f * Le.x, 0.7152f * Le.y, 0.0722f * Le.z);  // d p / d T
         float g_g, g_cx = 0.f;
         V3 g_wl = v3(0.f, 0.f, 0.f);
@@ -241,11 +253,12 @@ __device__ Adj reverse_vertex(const DevScene& S, int L, int j, const VState& s, 
         } else {
             const float co = dot(n, wo);
             const V3 hs = wo + wl;
-            const float hl = sqrtf(dot(hs, hs));
-            const V3 h = hs * (1.0f / hl);
+            const float hl = asqrt(dot(hs, hs));
+            const float ihl = arcp(hl);
+            const V3 h = hs * ihl;
             const float chh = dot(n, h);
             const float den = chh * chh * (m.a2 - 1.0f) + 1.0f;
-            const float D = m.a2 / (DR_PI * den * den);
+            const float D = adiv(m.a2, DR_PI * den * den);
             const float G = smith_g1(co, m.a2) * smith_g1(cx, m.a2);
             const float oh = dot(wl, h);
             const float om = 1.0f - oh;
@@ -260,21 +273,21 @@ __device__ Adj reverse_vertex(const DevScene& S, int L, int j, const VState& s, 
             const float fsum = kk * dot(Kb, F);
             g_g = fsum;
             const float gl = g * fsum;  // this vertex's share of p
-            const float g_chh = gl * (-4.0f * chh * (m.a2 - 1.0f) / den);
-            const float g_co = gl * (smith_dlog(co, m.a2) - 1.0f / co);
-            g_cx = gl * (smith_dlog(cx, m.a2) - 1.0f / cx);
+            const float g_chh = gl * adiv(-4.0f * chh * (m.a2 - 1.0f), den);
+            const float g_co = gl * (smith_dlog(co, m.a2) - arcp(co));
+            g_cx = gl * (smith_dlog(cx, m.a2) - arcp(cx));
             const float g_oh = g * kk * dot(Kb, dF);
             const V3 g_h = n * g_chh + wl * g_oh;
             g_wl = h * g_oh;
-            const V3 g_hs = (g_h - h * dot(h, g_h)) * (1.0f / hl);
+            const V3 g_hs = (g_h - h * dot(h, g_h)) * ihl;
             gwo = gwo + g_hs + n * g_co;
             g_wl = g_wl + g_hs;
         }
-        g_cx += g_g * cy / r2 * Cc;
-        const float g_cy = g_g * cx / r2 * Cc;
-        const float g_r2 = -g_g * g / r2;
+        g_cx += g_g * cy * ir2 * Cc;
+        const float g_cy = g_g * cx * ir2 * Cc;
+        const float g_r2 = -g_g * g * ir2;
         g_wl = g_wl + n * g_cx - NL * g_cy;
-        const V3 g_w = w * (2.0f * g_r2) + (g_wl - wl * dot(wl, g_wl)) * (1.0f / r);
+        const V3 g_w = w * (2.0f * g_r2) + (g_wl - wl * dot(wl, g_wl)) * arcp(r);
         gx = gx - g_w;
         ga = (float)nl * dot(g_w, E1);
         gbl = dot(g_w, E2);
@@ -309,7 +322,7 @@ __device__ void path_score(const DevScene& S, const U& u, const uint32_t* rec, i
         for (int i = 0; i < 4 * V; ++i) out[(size_t)i * os] = 0.0f;
         return;
     }
-    const float inv_pe = 1.0f / (p + eps);
+    const float inv_pe = arcp(p + eps);
     const Cam Cm = load_cam(S);
     uint32_t R[V + 1];
 #pragma unroll
@@ -367,15 +380,17 @@ __device__ void path_score(const DevScene& S, const U& u, const uint32_t* rec, i
     {
         const float u0 = u(0), u1 = u(1);
         const V3 D = Cm.cw + Cm.cu * (2.0f * u0 - 1.0f) + Cm.cv * (1.0f - 2.0f * u1);
-        const float Dl = sqrtf(dot(D, D));
-        const V3 d = D * (1.0f / Dl);
+        const float Dl = asqrt(dot(D, D));
+        const float iDl = arcp(Dl);
+        const V3 d = D * iDl;
         const DevTri T1 = S.tris[rec_slot(R[1])];
         const V3 ng = normalize(cross(xyz(T1.e1), xyz(T1.e2)));
         const float Dn = dot(ng, d);
-        const float t1 = dot(ng, xyz(T1.v0) - Cm.eye) / Dn;
-        const float sc = dot(a.gx, d) / Dn;
+        const float iDn = arcp(Dn);
+        const float t1 = dot(ng, xyz(T1.v0) - Cm.eye) * iDn;
+        const float sc = dot(a.gx, d) * iDn;
         const V3 gd = a.gd + (a.gx - ng * sc) * t1;
-        const V3 gD = (gd - d * dot(d, gd)) * (1.0f / Dl);
+        const V3 gD = (gd - d * dot(d, gd)) * iDl;
         float g0 = 2.0f * dot(gD, Cm.cu) * inv_pe, g1 = -2.0f * dot(gD, Cm.cv) * inv_pe;
         if (!isfinite(g0)) g0 = 0.0f;
         if (!isfinite(g1)) g1 = 0.0f;

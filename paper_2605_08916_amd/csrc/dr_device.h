@@ -136,7 +136,10 @@ __device__ __forceinline__ float safe_rcp(float d) {
 // the interval from below (the low plane when inv_a >= 0, else the high one)
 // takes c - E_a, the other c + E_a.  With the far distance also widened
 // relatively (the final FMA's own rounding), no box a ray truly enters
-// within (tmin, tmax) is ever culled.
+// within (tmin, tmax) is ever culled.  The reciprocal itself is the
+// hardware one (within a few ulp): its error scales an axis's whole
+// interval by one factor, which the far distance's relative widening
+// (4e-7) also covers.
 struct RaySlab {
     V3 inv, clo, chi;  // clo / chi: constants of the low / high plane per axis
 };
