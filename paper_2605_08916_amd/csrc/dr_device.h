@@ -189,19 +189,33 @@ __device__ __forceinline__ bool tri_test(const DevTri& T, V3 o, V3 d, float tmin
 
 // The first S.n_top nodes (the top levels: nodes are stored breadth-first)
 // may sit at the start of the kernel's dynamic LDS, copied there by the
-// kernel; every ray starts at the root, so its first visits read LDS.
+// kernel; every ray starts at the root, so its first visits read LDS.  The
+// two sources are separate branches (LDS reads and global loads) rather than
+// one generic pointer, which would compile to flat loads.
 __device__ __forceinline__ DevNode load_node(const DevScene& S, int i) {
     extern __shared__ float4 s_dyn[];
-    const float4* p = i < S.n_top ? s_dyn + 8 * i : reinterpret_cast<const float4*>(S.nodes + i);
     DevNode n;
-    n.lox = p[0];
-    n.loy = p[1];
-    n.loz = p[2];
-    n.hix = p[3];
-    n.hiy = p[4];
-    n.hiz = p[5];
-    n.child = reinterpret_cast<const int4*>(p)[6];
-    n.count = reinterpret_cast<const int4*>(p)[7];
+    if (i < S.n_top) {
+        const float4* p = s_dyn + 8 * i;
+        n.lox = p[0];
+        n.loy = p[1];
+        n.loz = p[2];
+        n.hix = p[3];
+        n.hiy = p[4];
+        n.hiz = p[5];
+        n.child = reinterpret_cast<const int4*>(p)[6];
+        n.count = reinterpret_cast<const int4*>(p)[7];
+    } else {
+        const float4* p = reinterpret_cast<const float4*>(S.nodes + i);
+        n.lox = p[0];
+        n.loy = p[1];
+        n.loz = p[2];
+        n.hix = p[3];
+        n.hiy = p[4];
+        n.hiz = p[5];
+        n.child = reinterpret_cast<const int4*>(p)[6];
+        n.count = reinterpret_cast<const int4*>(p)[7];
+    }
     return n;
 }
 
