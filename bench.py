@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--config", default=None,
                     help="measure a named larger configuration instead of the headline line (instances, "
                          "spheres_1080p_L16, interior, spheres_specular); prints its own JSON line")
+    ap.add_argument("--config-chains", type=int, default=None,
+                    help="with --config: run the configuration with this many chains instead of its own")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates the FETCH_SIZE/WRITE_SIZE counters)")
     ap.add_argument("--traffic-summary", nargs="+", metavar="DIR",
@@ -335,6 +337,8 @@ def run_config(a, torch, dr, inputs):
     captured frame graph replayed along the camera path, one reference per
     sampled frame."""
     fac, L, N = inputs.CONFIGS[a.config]
+    if a.config_chains:
+        N = a.config_chains
     sc = fac()
     d = 4 * (L - 1)
     scene = dr.Scene(sc)
@@ -368,7 +372,14 @@ def run_config(a, torch, dr, inputs):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             ch.reinit(1)
             torch.cuda.synchronize()
-            n = max(1, int((33.3 - 2.0) / ms))
+            e0.record()
+            ch.reinit(2)
+            e1.record()
+            torch.cuda.synchronize()
+            reinit_ms = e0.elapsed_time(e1)
+            # as many steps as fit the 33.3 ms frame after the re-initialisation
+            # (1 ms kept for the resolve); at least one
+            n = max(1, int((33.3 - 1.0 - reinit_ms) / ms))
             with torch.cuda.stream(stream):
                 frame = ch.capture_frame(n, True, img, stream)
             frames = []
@@ -385,7 +396,7 @@ def run_config(a, torch, dr, inputs):
                                "mrse": mrse(img.cpu().numpy().astype(np.float64),
                                             ref.cpu().numpy().astype(np.float64))})
             frame.close()
-            res["realtime_loop"] = {"steps_per_frame": n, "frames": frames,
+            res["realtime_loop"] = {"steps_per_frame": n, "reinit_ms": reinit_ms, "frames": frames,
                                     "reference": "independent path tracing, 64 spp per pixel"}
         else:
             ref = scene.pt_render(L, 777, 64)

@@ -273,8 +273,10 @@ dr_status dr_stats(dr_chains* c, dr_counters* out, void* hip_stream);
  * over sort_by_length; 2: off), and node_cache (the number of top BVH nodes,
  * stored breadth-first, each block of the straight-line fused kernel copies
  * into LDS at start, 128 bytes each, at most 512; 1 caches only the root;
- * DR_NODE_CACHE_AUTO: 341 (five levels) with two lanes per chain, 85 (four
- * levels) with one; fewer when they would not fit beside the stacks).
+ * DR_NODE_CACHE_AUTO: up to 341 (five levels) with two lanes per chain, up to
+ * 85 (four levels) with one, fewer when the stacks of a deep tree leave too
+ * little LDS for two (paired) or three (one lane) wavefronts per SIMD to stay
+ * resident; explicit values are cut only to what fits one block).
  * Zeros keep the current
  * value.  Defaults: 256 threads, 4 blocks per compute unit, 1 chain per pop,
  * 2 lanes per chain when n_chains is below two wavefronts per SIMD

@@ -876,6 +876,7 @@ struct dr_chains {
     dr_launch_cfg launch{256, 2, 1, 2, 0, 0, 50, 50, 0, DR_NODE_CACHE_AUTO};
     int n_cu = 256;
     int lds_limit = 65536;             // bytes of LDS one block may use
+    int lds_per_cu = 163840;           // bytes of LDS one compute unit holds
     int rows_move = 0, rows_all = 0;  // state rows moved per sorted launch / restored before host access
     bool permuted = false;            // chains may sit outside the slot of their id
 };
@@ -1004,12 +1005,21 @@ static void enqueue_steps(dr_chains* c, uint32_t n_steps, hipStream_t st) {
         int blocks = (int)(c->n_cu * c->launch.blocks_per_cu);
         blocks = (int)std::max(1L, std::min((long)blocks, (lanes + blk - 1) / blk));
         DevScene S = c->scene->ds;
-        // automatic: five levels with paired lanes (two blocks per compute
-        // unit hold the chains), four with one lane (three blocks must fit)
-        const uint32_t nc = c->launch.node_cache == DR_NODE_CACHE_AUTO ? (pair ? 341u : 85u) : c->launch.node_cache;
+        const size_t stack_b = stack_bytes(S, blk);
+        // automatic: up to five levels with paired lanes, four with one lane,
+        // and no more than leaves room for the wavefronts the kernel keeps
+        // resident (two per SIMD paired, three with one lane, the register
+        // limit): the stacks of a deep tree take most of the LDS themselves
+        uint32_t nc = c->launch.node_cache;
+        if (nc == DR_NODE_CACHE_AUTO) {
+            const int waves_cu = 4 * (pair ? 2 : 3), waves_block = std::max(1, blk / 64);
+            const int blocks_cu = (waves_cu + waves_block - 1) / waves_block;
+            const size_t budget = ((size_t)c->lds_per_cu / (size_t)blocks_cu) & ~(size_t)1023;
+            const size_t room = budget > stack_b ? budget - stack_b : 0;
+            nc = (uint32_t)std::min<size_t>(pair ? 341u : 85u, room / sizeof(DevNode));
+        }
         S.n_top = (int)std::min<uint32_t>(nc, c->scene->n_nodes);
         // the cached nodes and the stacks share the block's LDS: fewer nodes if they would not fit
-        const size_t stack_b = stack_bytes(S, blk);
         if (stack_b + (size_t)S.n_top * sizeof(DevNode) > (size_t)c->lds_limit)
             S.n_top = (int)(((size_t)c->lds_limit > stack_b ? (size_t)c->lds_limit - stack_b : 0) / sizeof(DevNode));
         DR_DISPATCH_L(P.L, launch_fused, dim3(blocks), dim3(blk), st, P, S, c->kb, n_steps, c->launch.grab, pair,
@@ -1198,6 +1208,9 @@ dr_status dr_scene_create(const dr_scene_desc* desc, int device, dr_scene** out)
         }
         return k;
     };
+    // nodes laid out breadth-first before the depth-first rest (at least the
+    // largest LDS node cache, 512 nodes)
+    constexpr int DR_BFS_TOP = 512;
     std::vector<DevNode> dn;
     std::vector<int> need;  // worst-case traversal stack entries below each device node
     {
@@ -1219,11 +1232,21 @@ dr_status dr_scene_create(const dr_scene_desc* desc, int device, dr_scene** out)
         } else {
             dn.emplace_back();
             kids.emplace_back();
-            // breadth-first: node indices grow level by level, so the top
-            // levels are the first nodes (the kernels keep those in LDS)
+            // breadth-first for the first nodes (indices grow level by level,
+            // so the top levels come first: the kernels keep those in LDS),
+            // depth-first below them, so that each deeper subtree's nodes lie
+            // together in memory and a ray descending it stays on nearby lines
+            std::vector<Item> deep;  // depth-first stack
             work.push_back({0, 0});
-            for (size_t w = 0; w < work.size(); ++w) {
-                const Item it = work[w];
+            size_t w = 0;
+            while (w < work.size() || !deep.empty()) {
+                Item it;
+                if (w < work.size()) {
+                    it = work[w++];
+                } else {
+                    it = deep.back();
+                    deep.pop_back();
+                }
                 int ch[4];
                 const int k = gather(it.bin, ch);
                 float lo[3][4], hi[3][4];
@@ -1246,9 +1269,12 @@ dr_status dr_scene_create(const dr_scene_desc* desc, int device, dr_scene** out)
                         dn.emplace_back();
                         kids.emplace_back();
                         kids[it.dev].push_back(cidx[q]);
-                        work.push_back({c, cidx[q]});
+                        if (cidx[q] < DR_BFS_TOP) work.push_back({c, cidx[q]});
                     }
                 }
+                // deeper children go on the depth-first stack, first child on top
+                for (int q = k - 1; q >= 0; --q)
+                    if (nodes[ch[q]].a >= 0 && cidx[q] >= DR_BFS_TOP) deep.push_back({ch[q], cidx[q]});
                 DevNode& r = dn[it.dev];
                 r.lox = make_float4(lo[0][0], lo[0][1], lo[0][2], lo[0][3]);
                 r.loy = make_float4(lo[1][0], lo[1][1], lo[1][2], lo[1][3]);
@@ -1438,6 +1464,10 @@ dr_status dr_chains_init(dr_scene* s, const dr_params* p, uint64_t seed, uint32_
         int lim = 0;
         if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, s->device) == hipSuccess && lim > 0)
             c->lds_limit = lim;
+        lim = 0;
+        if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, s->device) == hipSuccess &&
+            lim > 0)
+            c->lds_per_cu = lim;
     }
     // two lanes per chain while chains alone cannot fill two wavefronts per
     // SIMD (4 SIMDs per compute unit, 64 lanes per wavefront); one otherwise
