@@ -564,7 +564,7 @@ def _mixture_closed_form(w, m, s, c0):
     return np.array(out)
 
 
-@pytest.mark.parametrize("d,s,c0", [(2, [0.15, 0.2], 0.3), (4, [0.2, 0.25, 0.2], 0.2)])
+@pytest.mark.parametrize("d,s,c0", [(2, [0.15, 0.2], 0.3), (4, [0.2, 0.25, 0.2], 0.2), (8, [0.2, 0.25, 0.2, 0.25], 0.2)])
 def test_restore_estimator_closed_forms(orc, d, s, c0):
     """Wrapped Gaussian mixture on T^d, f = p g with g = (1, cos 2 pi x_i,
     sin 2 pi x_i): k0 accum / tourCount -> lambda(p g) =
