@@ -41,6 +41,8 @@ MUTANTS = [
      "test_glass_slab_branches"),
     ("mirror_schlick", "T one_m = 1.0 - ci;", "T one_m = ci;", "test_mirror_lobe"),
     ("delta_emission", "if (is_delta(m) && dot(nw2, vald(d)) < 0.0) {", "if (false) {", "test_mirror_plane_closed_form"),
+    ("sampled_weight_max", "else w = std::min(Ea * C.P.dt, Eb / k);", "else w = std::max(Ea * C.P.dt, Eb / k);",
+     "test_sampled_holding_weight_has_the_rao_blackwell_mean"),
     ("estimator_scale", "(double)npx * C->k0 / (double)C->tour_count", "C->k0 / (double)C->tour_count",
      "test_restore_image_tends_to_path_tracing"),
 ]

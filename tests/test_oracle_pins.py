@@ -532,6 +532,29 @@ def test_constant_target_tours(orc):
     assert np.all(np.abs(img[1:]) < 0.03)
 
 
+def test_sampled_holding_weight_has_the_rao_blackwell_mean(orc):
+    """Competing exponential clocks (reading A8): the sampled weight
+    min(dt E_a, E_b / k) of a step is the minimum of independent Exp(h) and
+    Exp(k) times, itself Exp(h + k) with mean 1/(h + k) = dt/(1 + k dt) and
+    standard deviation equal to its mean; the Rao-Blackwellised weight is
+    that mean exactly.  p constant, so every chain has the same k."""
+    N, dt, eps = 40000, 1e-5, 1e-8
+    k0 = 1.0 / (3 * dt)  # k dt = 1/3: both clocks matter
+    k = k0 / (1.0 + eps)  # p = 1 everywhere
+    want = 1.0 / (1.0 / dt + k)
+    Cs = orc.Chains.mixture(2, [], np.zeros((0, 2)), [], 1.0, N, seed=8, k0=k0, rao_blackwell=0)
+    Cs.init()
+    Cs.step(1)
+    ws = Cs.state()["w"]
+    Cr = orc.Chains.mixture(2, [], np.zeros((0, 2)), [], 1.0, N, seed=8, k0=k0, rao_blackwell=1)
+    Cr.init()
+    Cr.step(1)
+    wr = Cr.state()["w"]
+    assert np.allclose(wr, want, rtol=1e-12, atol=0)
+    assert abs(ws.mean() - want) < 5 * want / math.sqrt(N)
+    assert abs(ws.std() - want) < 0.05 * want
+
+
 def test_local_dynamics_lyapunov(orc):
     """Killing off, Gaussian target N(c, s^2 I2): the Euler-Maruyama move with
     rotation is AR(1), x' - c = A (x - c) + stddev xi, A = alpha I - beta U,
