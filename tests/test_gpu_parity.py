@@ -184,14 +184,14 @@ def test_autograd_matches_finite_differences_and_oracle(orc, scenes):
     assert bad <= 0.01 * checked
 
 
-def _onestep(orc, sc, L, N, mode, seed, k0, gamma=0.5, sigma=None, sample=None, state_seed=3):
+def _onestep(orc, sc, L, N, mode, seed, k0, gamma=0.5, sigma=None, sample=None, state_seed=3, rao_blackwell=1):
     """Write one generated state to the device and the oracle, take one step,
     return both states (device state restricted to `sample`)."""
     d = 4 * (L - 1)
     st = inputs.random_state(d, N, seed=state_seed, killed_frac=0.15, score_scale=40.0)
     S = dr.Scene(sc)
     sig_t = None if sigma is None else torch.from_numpy(sigma).cuda()
-    ch = dr.Chains(S, N, L, seed, k0=k0, gamma=gamma, mode=mode, sigma=sig_t)
+    ch = dr.Chains(S, N, L, seed, k0=k0, gamma=gamma, mode=mode, sigma=sig_t, rao_blackwell=rao_blackwell)
     ch.set_record(True)
     step0 = (7 << 32) + 11
     ch.write_state(x=st["x"], score=st["score"], killed=st["killed"], step=step0, k0=k0)
@@ -200,7 +200,7 @@ def _onestep(orc, sc, L, N, mode, seed, k0, gamma=0.5, sigma=None, sample=None, 
     idx = np.arange(N) if sample is None else np.asarray(sample)
     O = orc.Scene(sc)
     oc = orc.Chains.scene(O, L, len(idx), seed=seed, k0=k0, gamma=gamma,
-                          sigma=None if sigma is None else sigma[:, idx])
+                          sigma=None if sigma is None else sigma[:, idx], rao_blackwell=rao_blackwell)
     oc.set_ids(idx.astype(np.uint32))
     score_in = st["score"][:, idx]
     if mode == dr.DR_MODE_PLAIN:
@@ -287,6 +287,20 @@ def test_one_step_matches_oracle(orc, scenes, which, L, N, mode):
     # the plain form computes the score at the start of the next step
     _compare_step(orc, scenes[which], L, st, gs, os_, idx, 21, step0, k0, check_score=(mode == dr.DR_MODE_FUSED),
                   plain=(mode == dr.DR_MODE_PLAIN))
+
+
+@pytest.mark.parametrize("mode", [dr.DR_MODE_FUSED, dr.DR_MODE_PLAIN])
+def test_one_step_sampled_holding_weight(orc, scenes, mode):
+    """The literal Alg. 4.1 weight (rao_blackwell = 0: the sampled holding
+    time min(dt E_a, E_b / k)) against the oracle's, with the same clocks."""
+    say(f"[one step, sampled weight] scene=specular L=8 N=1500 mode={mode}")
+    k0 = 300.0
+    st, gs, os_, idx, step0 = _onestep(orc, scenes["specular"], 8, 1500, mode, seed=23, k0=k0, rao_blackwell=0)
+    _compare_step(orc, scenes["specular"], 8, st, gs, os_, idx, 23, step0, k0, check_score=(mode == dr.DR_MODE_FUSED),
+                  plain=(mode == dr.DR_MODE_PLAIN))
+    # the sampled weights differ from chain to chain (the RB weight depends on p only)
+    live = os_["p"] > 0
+    assert np.unique(np.round(os_["w"][live] / 1e-12)).size > 10
 
 
 @pytest.mark.parametrize("mode", [dr.DR_MODE_FUSED, dr.DR_MODE_PLAIN])
