@@ -23,9 +23,12 @@ LUMW = np.array([0.2126, 0.7152, 0.0722])
 
 
 def say(*a):
+    """Progress and error statistics: to stderr, and appended to the file
+    named by DR_PARITY_LOG when that is set."""
     print(*a, file=sys.stderr, flush=True)
-    if os.path.isdir("gpurun_out"):
-        with open(os.path.join("gpurun_out", "parity_stats.txt"), "a") as f:
+    path = os.environ.get("DR_PARITY_LOG")
+    if path:
+        with open(path, "a") as f:
             print(*a, file=f)
 
 
