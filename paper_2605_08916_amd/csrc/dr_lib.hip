@@ -9,7 +9,7 @@
 //    yields the score used by the next move.  One traversal per chain-step.
 //  * plain: the paper's pass structure as separate kernels with the state
 //    round-tripping through HBM: score (a forward trace plus the adjoint at the
-//    current state, Alg. 5.1 line 1), move/regenerate, forward trace at the new
+//    current state, which Alg. 5.1 starts from), move/regenerate, forward trace at the new
 //    state (Accumulate), hold/kill/splat.  Two traversals per chain-step.
 #include <hip/hip_runtime.h>
 

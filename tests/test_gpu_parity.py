@@ -208,7 +208,7 @@ def _onestep(orc, sc, L, N, mode, seed, k0, gamma=0.5, sigma=None, sample=None, 
     score_in = st["score"][:, idx]
     if mode == dr.DR_MODE_PLAIN:
         # the plain form recomputes the score of the current state at the start
-        # of its step (Alg. 5.1 line 1): give the oracle its own score at x
+        # of its step (Alg. 5.1 starts from it): give the oracle its own score at x
         _, _, sc_o, _ = O.path_eval(L, st["x"][:, idx].T.astype(np.float64))
         score_in = sc_o.T.astype(np.float32)
     oc.set_state(st["x"][:, idx], score_in, st["killed"][idx], step0, k0=k0)
