@@ -89,6 +89,7 @@ def lib():
         L.orc_chains_new_mixture.argtypes = [C.c_int, C.c_int, D, D, D, C.c_double, C.c_int, D, C.c_uint64]
         L.orc_chains_new_mixture.restype = P
         L.orc_chains_free.argtypes = [P]
+        L.orc_chains_set_sigma.argtypes = [P, F]
         L.orc_chains_init.argtypes = [P, C.c_uint32, C.c_int]
         L.orc_chains_step.argtypes = [P, C.c_int, C.c_int, D]
         L.orc_chains_set_ids.argtypes = [P, U32]
@@ -334,6 +335,11 @@ class Chains:
         s = np.ascontiguousarray(score, np.float32).reshape(self.d, self.N)
         k = np.ascontiguousarray(killed, np.uint32).reshape(self.N)
         lib().orc_chains_set_state(self.h, _p(x, C.c_float), _p(s, C.c_float), _p(k, C.c_uint32), step, k0)
+
+    def set_sigma(self, sigma):
+        """Per-chain diagonal stddev, d x N (None: the scalar stddev)."""
+        self._sigma = None if sigma is None else np.ascontiguousarray(sigma, np.float32).reshape(self.d, self.N)
+        lib().orc_chains_set_sigma(self.h, _p(self._sigma, C.c_float))
 
     def set_ids(self, ids):
         """Slot c draws the random streams of chain ids[c]."""

@@ -1071,6 +1071,14 @@ void* orc_chains_new_mixture(int d, int nm, const double* w, const double* means
     return C;
 }
 
+// Give every chain its own diagonal stddev (d x N planar), as for a scene's
+// chains (reading A16).
+void orc_chains_set_sigma(void* c, const float* sigma) {
+    Chains* C = (Chains*)c;
+    if (sigma) C->sigma.assign(sigma, sigma + (size_t)C->d * C->N);
+    else C->sigma.clear();
+}
+
 void orc_chains_free(void* c) {
     Chains* C = (Chains*)c;
     delete C->mix;

@@ -43,6 +43,9 @@ MUTANTS = [
     ("delta_emission", "if (is_delta(m) && dot(nw2, vald(d)) < 0.0) {", "if (false) {", "test_mirror_plane_closed_form"),
     ("sampled_weight_max", "else w = std::min(Ea * C.P.dt, Eb / k);", "else w = std::max(Ea * C.P.dt, Eb / k);",
      "test_sampled_holding_weight_has_the_rao_blackwell_mean"),
+    ("p_lambda_mean", "C.p_lambda_hat = sum / C.N;", "C.p_lambda_hat = sum;", "test_estimated_killing_constant"),
+    ("sigma_coordinate", "C.sigma.empty() ? C.P.stddev : C.sigma[ii[k]]", "C.sigma.empty() ? C.P.stddev : C.sigma[i0]",
+     "test_per_chain_diagonal_sigma_lyapunov"),
     ("estimator_scale", "(double)npx * C->k0 / (double)C->tour_count", "C->k0 / (double)C->tour_count",
      "test_restore_image_tends_to_path_tracing"),
 ]

@@ -532,6 +532,71 @@ def test_constant_target_tours(orc):
     assert np.all(np.abs(img[1:]) < 0.03)
 
 
+def test_estimated_killing_constant(orc):
+    """k0 left to the initialise pass (Eq. killing-rate-constant, reading A6):
+    p_lambda_hat is the mean of p over the N initial states and k0 =
+    p_lambda_hat/(m dt).  On a constant target every state has p = c, so
+    p_lambda_hat = c exactly and each step kills with probability 1/(m+1);
+    on a wrapped Gaussian mixture the mean over uniform states estimates
+    lambda(p) = c0 + sum w within its standard error."""
+    N, steps, c, m, dt = 2000, 600, 0.37, 64.0, 1e-5
+    C = orc.Chains.mixture(2, [], np.zeros((0, 2)), [], c, N, seed=5, m=m, k0=0.0)
+    C.init()
+    a0 = C.accum()
+    assert a0["p_lambda_hat"] == pytest.approx(c, rel=1e-12)
+    assert a0["k0"] == pytest.approx(c / (m * dt), rel=1e-12)
+    C.step(steps)
+    a = C.accum()
+    n = N * (steps + 1)
+    q = 1 / (m + 1)
+    assert abs(a["tour_count"] / n - q) < 5 * math.sqrt(q * (1 - q) / n)
+    # a non-constant target: the estimate is the sample mean of p(x), x ~ U(T^d)
+    rng = np.random.default_rng(12)
+    d, c0 = 2, 0.1
+    w = np.array([0.7, 0.3])
+    means = rng.uniform(size=(2, d))
+    s = np.array([0.08, 0.12])
+    Nm = 20000
+    Cm = orc.Chains.mixture(d, w, means, s, c0, Nm, seed=6, k0=0.0)
+    Cm.init()
+    am = Cm.accum()
+    # the sample variance of p over uniform states, from the same draws
+    p0 = Cm.state()["p"]
+    assert am["p_lambda_hat"] == pytest.approx(p0.mean(), rel=1e-12)
+    se = p0.std(ddof=1) / math.sqrt(Nm)
+    assert abs(am["p_lambda_hat"] - (c0 + w.sum())) < 5 * se
+    assert am["k0"] == pytest.approx(am["p_lambda_hat"] / (64 * dt), rel=1e-12)
+
+
+def test_per_chain_diagonal_sigma_lyapunov(orc):
+    """Per-chain diagonal Sigma (reading A16), killing off, no rotation,
+    Gaussian target N(c, s^2 I2): coordinate i of a chain is its own AR(1),
+    x'_i - c = a_i (x_i - c) + sd_i xi with a_i = 1 - sd_i^2/(2 s^2), whose
+    stationary variance is sd_i^2/(1 - a_i^2).  Two groups of chains with
+    different stddevs in the two coordinates, both orders.  The steps are
+    large against the target (sd_i^2/(2 s^2) = 1/8 and 1/2), so the
+    discretised chain's variance 2 s^2/(2 - sd_i^2/(2 s^2)) depends on sd_i:
+    a stddev taken from the wrong coordinate changes it by 20%."""
+    dt, s, N = 1e-5, 0.1, 400
+    sd_a, sd_b = 0.05, 0.1
+    sig = np.empty((2, N), np.float32)
+    sig[0, : N // 2], sig[1, : N // 2] = sd_a, sd_b
+    sig[0, N // 2:], sig[1, N // 2:] = sd_b, sd_a
+    C = orc.Chains.mixture(2, [1.0], np.array([[0.5, 0.5]]), [s], 0.0, N, seed=9, stddev=0.02, dt=dt, gamma=0.0,
+                           k0=1e-30)
+    C.set_sigma(sig)
+    C.init()
+    C.step(100)
+    x = C.step(2000, trace=True) - 0.5
+    for grp, (s0, s1) in ((slice(0, N // 2), (sd_a, sd_b)), (slice(N // 2, N), (sd_b, sd_a))):
+        for i, sd in ((0, s0), (1, s1)):
+            sd = float(np.float32(sd))
+            a = 1 - sd ** 2 / (2 * s ** 2)
+            q = sd ** 2 / (1 - a ** 2)
+            v = x[:, i, grp].var()
+            assert abs(v / q - 1) < 0.03, (i, sd, v, q)
+
+
 def test_sampled_holding_weight_has_the_rao_blackwell_mean(orc):
     """Competing exponential clocks (reading A8): the sampled weight
     min(dt E_a, E_b / k) of a step is the minimum of independent Exp(h) and
