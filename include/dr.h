@@ -206,7 +206,10 @@ dr_status dr_step(dr_chains* c, uint32_t n_steps, void* hip_stream);
  * synchronisation, so it can sit in a captured graph. */
 dr_status dr_resolve(dr_chains* c, float* image_dev, void* hip_stream);
 
-/* Resolve, copy to host_rgb (3*W*H planar floats) and synchronise the stream. */
+/* Resolve pass (Alg. 4.3, as dr_resolve) into the library's own image
+ * buffer, copy it to host_rgb (3*W*H planar floats, host, caller-owned) and
+ * the tour count to *tour_count (nullable), then synchronise hip_stream.
+ * Errors: DR_ERR_INVALID_ARG (null chains or host_rgb), DR_ERR_DEVICE. */
 dr_status dr_image_read(dr_chains* c, float* host_rgb, uint64_t* tour_count, void* hip_stream);
 
 dr_status dr_chains_destroy(dr_chains* c);
@@ -328,7 +331,9 @@ dr_status dr_frame_destroy(dr_frame* f);
 /* For n points u_dev (n x d row-major, d = 4(L-1), device) evaluate f (n x 3),
  * log(p + eps) (n) and, if grad_dev is non-NULL, the score grad_u log(p + eps)
  * (n x d) by the reverse-mode adjoint over the taken path (discrete choices
- * held fixed).  rec_dev (n x (L-1), nullable) receives the path record as in
+ * held fixed).  The score is the gradient the Langevin drift of Sec. 5
+ * (Eq. langevin-drift, with p penalised by eps) moves a chain along; p is the
+ * luminance of f (Sec. 3, the target density proportional to f).  rec_dev (n x (L-1), nullable) receives the path record as in
  * dr_state.path_rec.  f_dev and logp_dev are nullable too.  Without grad_dev
  * the points are evaluated by the ray-refill form (lanes take the next point
  * or ray as theirs finish), with results bit-identical to the form that also

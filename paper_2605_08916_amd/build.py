@@ -11,8 +11,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdr.so")
 SOURCES = [os.path.join(CSRC, "dr_lib.hip"), os.path.join(CSRC, "bvh_build.cpp")]
-DEPS = SOURCES + [os.path.join(CSRC, "dr_device.h"), os.path.join(CSRC, "dr_adjoint.h"), os.path.join(CSRC, "dr_chain.h"),
-                  os.path.join(ROOT, "include", "dr.h")]
+DEPS = SOURCES + [os.path.join(CSRC, h) for h in ("dr_device.h", "dr_adjoint.h", "dr_chain.h", "dr_machine.h")] + [
+    os.path.join(ROOT, "include", "dr.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -25,7 +25,9 @@ FLAGS = [
     # keep private arrays out of LDS: the traversal stack owns the dynamic LDS
     "-mllvm", "-disable-promote-alloca-to-lds",
     # packed FP32 instructions stay off (they are not needed and some forms
-    # have given wrong results on this hardware)
+    # have given wrong results on this hardware).  The device pass honours the
+    # feature (a float2 multiply-add compiles to v_pk_fma_f32 without it and to
+    # two v_fma_f32 with it); only the host pass warns that it does not know it
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I" + os.path.join(ROOT, "include"),
 ]
