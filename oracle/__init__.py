@@ -70,6 +70,7 @@ def lib():
         L.orc_trace.argtypes = [P, C.c_int, D, D, C.c_double, I, D]
         L.orc_occluded.argtypes = [P, C.c_int, D, D, D, I]
         L.orc_path_eval.argtypes = [P, C.c_int, C.c_int, D, C.c_double, D, D, D, U32, C.c_int]
+        L.orc_path_cond.argtypes = [P, C.c_int, C.c_int, D, C.c_double, D, C.c_int]
         L.orc_bsdf_sample.argtypes = [F, D, D, C.c_double, C.c_double, D, D]
         L.orc_bsdf_sample.restype = C.c_int
         L.orc_bsdf_eval.argtypes = [F, D, D, D, D]
@@ -194,6 +195,19 @@ class Scene:
         lib().orc_path_eval(self.h, L, n, _p(u, C.c_double), eps, _p(f, C.c_double), _p(p, C.c_double),
                             _p(sc, C.c_double), _p(rec, C.c_uint32), nthreads or default_threads())
         return f, p, sc, rec
+
+    def path_cond(self, L: int, u, eps: float = 1e-8, nthreads: int | None = None) -> np.ndarray:
+        """Condition measure of the score (n x d): for each coordinate, the
+        sum over dependency paths of the magnitudes of the terms that make up
+        d p / d u_i, divided by p + eps (>= |score_i|; large where terms
+        cancel).  FP32 evaluation of the score errs by at most a small
+        multiple of the unit roundoff times this."""
+        d = 4 * (L - 1)
+        u = np.ascontiguousarray(u, np.float64).reshape(-1, d)
+        kappa = np.zeros((u.shape[0], d))
+        lib().orc_path_cond(self.h, L, u.shape[0], _p(u, C.c_double), eps, _p(kappa, C.c_double),
+                            nthreads or default_threads())
+        return kappa
 
     def pt_render(self, L: int, seed: int, spp: int, nthreads: int | None = None) -> np.ndarray:
         img = np.zeros((3, self.H * self.W))

@@ -128,6 +128,39 @@ static inline Dual operator/(double a, const Dual& b) { Dual r; r.v = a / b.v; f
 static inline Dual sqrt(const Dual& a) { Dual r; r.v = std::sqrt(a.v); for (int i = 0; i < g_nd; ++i) r.g[i] = a.g[i] / (2.0 * r.v); return r; }
 static inline Dual sin(const Dual& a) { Dual r; r.v = std::sin(a.v); double c = std::cos(a.v); for (int i = 0; i < g_nd; ++i) r.g[i] = c * a.g[i]; return r; }
 static inline Dual cos(const Dual& a) { Dual r; r.v = std::cos(a.v); double s = -std::sin(a.v); for (int i = 0; i < g_nd; ++i) r.g[i] = s * a.g[i]; return r; }
+
+// Forward mode with a running magnitude (a conditioning measure, not part of
+// the method): besides the derivative g, a[i] accumulates, for input i, the
+// sum over the computation's dependency paths of the products of the
+// magnitudes of the local partial derivatives, so a >= |g|.  Evaluating the
+// derivative in a lower precision, in forward or reverse mode, rounds every
+// intermediate term; to first order the error is at most (roundings along a
+// path) x (unit roundoff) x a, and a / |g| is the derivative's condition
+// number (large where terms cancel).
+struct DualA {
+    double v;
+    double g[DMAX], a[DMAX];
+    DualA() : v(0) { for (int i = 0; i < g_nd; ++i) g[i] = a[i] = 0; }
+    DualA(double x) : v(x) { for (int i = 0; i < g_nd; ++i) g[i] = a[i] = 0; }
+    static DualA var(double x, int slot) { DualA r(x); r.g[slot] = 1.0; r.a[slot] = 1.0; return r; }
+};
+static inline double val(const DualA& x) { return x.v; }
+static inline DualA operator+(const DualA& x, const DualA& y) { DualA r; r.v = x.v + y.v; for (int i = 0; i < g_nd; ++i) { r.g[i] = x.g[i] + y.g[i]; r.a[i] = x.a[i] + y.a[i]; } return r; }
+static inline DualA operator-(const DualA& x, const DualA& y) { DualA r; r.v = x.v - y.v; for (int i = 0; i < g_nd; ++i) { r.g[i] = x.g[i] - y.g[i]; r.a[i] = x.a[i] + y.a[i]; } return r; }
+static inline DualA operator*(const DualA& x, const DualA& y) { DualA r; r.v = x.v * y.v; for (int i = 0; i < g_nd; ++i) { r.g[i] = x.g[i] * y.v + x.v * y.g[i]; r.a[i] = x.a[i] * std::fabs(y.v) + std::fabs(x.v) * y.a[i]; } return r; }
+static inline DualA operator/(const DualA& x, const DualA& y) { DualA r; r.v = x.v / y.v; const double y2 = y.v * y.v; for (int i = 0; i < g_nd; ++i) { r.g[i] = (x.g[i] * y.v - x.v * y.g[i]) / y2; r.a[i] = (x.a[i] * std::fabs(y.v) + std::fabs(x.v) * y.a[i]) / y2; } return r; }
+static inline DualA operator+(const DualA& x, double y) { DualA r = x; r.v += y; return r; }
+static inline DualA operator+(double x, const DualA& y) { return y + x; }
+static inline DualA operator-(const DualA& x, double y) { DualA r = x; r.v -= y; return r; }
+static inline DualA operator-(double x, const DualA& y) { DualA r; r.v = x - y.v; for (int i = 0; i < g_nd; ++i) { r.g[i] = -y.g[i]; r.a[i] = y.a[i]; } return r; }
+static inline DualA operator-(const DualA& x) { DualA r; r.v = -x.v; for (int i = 0; i < g_nd; ++i) { r.g[i] = -x.g[i]; r.a[i] = x.a[i]; } return r; }
+static inline DualA operator*(const DualA& x, double y) { DualA r; r.v = x.v * y; for (int i = 0; i < g_nd; ++i) { r.g[i] = x.g[i] * y; r.a[i] = x.a[i] * std::fabs(y); } return r; }
+static inline DualA operator*(double x, const DualA& y) { return y * x; }
+static inline DualA operator/(const DualA& x, double y) { DualA r; r.v = x.v / y; for (int i = 0; i < g_nd; ++i) { r.g[i] = x.g[i] / y; r.a[i] = x.a[i] / std::fabs(y); } return r; }
+static inline DualA operator/(double x, const DualA& y) { DualA r; r.v = x / y.v; const double y2 = y.v * y.v; for (int i = 0; i < g_nd; ++i) { r.g[i] = -x * y.g[i] / y2; r.a[i] = std::fabs(x) * y.a[i] / y2; } return r; }
+static inline DualA sqrt(const DualA& x) { DualA r; r.v = std::sqrt(x.v); for (int i = 0; i < g_nd; ++i) { r.g[i] = x.g[i] / (2.0 * r.v); r.a[i] = x.a[i] / (2.0 * r.v); } return r; }
+static inline DualA sin(const DualA& x) { DualA r; r.v = std::sin(x.v); const double c = std::cos(x.v); for (int i = 0; i < g_nd; ++i) { r.g[i] = c * x.g[i]; r.a[i] = std::fabs(c) * x.a[i]; } return r; }
+static inline DualA cos(const DualA& x) { DualA r; r.v = std::cos(x.v); const double sn = -std::sin(x.v); for (int i = 0; i < g_nd; ++i) { r.g[i] = sn * x.g[i]; r.a[i] = std::fabs(sn) * x.a[i]; } return r; }
 using std::sqrt; using std::sin; using std::cos;
 
 template <class T> struct V3 {
@@ -145,6 +178,7 @@ template <class T> static inline V3<T> cross(const V3<T>& a, const V3<T>& b) {
 template <class T> static inline V3<T> normalize(const V3<T>& a) { T l = sqrt(dot(a, a)); return {a.x / l, a.y / l, a.z / l}; }
 template <class T> static inline V3<T> lift(const V3<double>& a) { return {T(a.x), T(a.y), T(a.z)}; }
 static inline V3<double> vald(const V3<Dual>& a) { return {a.x.v, a.y.v, a.z.v}; }
+static inline V3<double> vald(const V3<DualA>& a) { return {a.x.v, a.y.v, a.z.v}; }
 static inline V3<double> vald(const V3<double>& a) { return a; }
 
 // ----------------------------------------------------------------------------
@@ -590,6 +624,22 @@ static void path_eval(const Scene& S, int L, const T* u, PathRec& rec, bool repl
     }
 }
 
+// Condition measure of the score at one point: kappa[i] = a_i / (p + eps),
+// the running magnitude of d p / d u_i (DualA) over the same taken path.
+static void cond_point(const Scene& S, int L, const double* u, double eps, double* kappa) {
+    const int d = 4 * (L - 1);
+    g_nd = d;
+    double f[3];
+    PathRec rec;
+    path_eval<double>(S, L, u, rec, false, f);  // the taken path, replayed below
+    std::vector<DualA> ud(d);
+    for (int i = 0; i < d; ++i) ud[i] = DualA::var(u[i], i);
+    DualA fd[3];
+    path_eval<DualA>(S, L, ud.data(), rec, true, fd);
+    const DualA pd = LUM[0] * fd[0] + LUM[1] * fd[1] + LUM[2] * fd[2];
+    for (int i = 0; i < d; ++i) kappa[i] = pd.a[i] / (pd.v + eps);
+}
+
 // f, p and optionally the score grad ln(p + eps) at one point.
 static void eval_point(const Scene& S, int L, const double* u, double eps, double f[3], double& p, double* score,
                        PathRec& rec) {
@@ -973,6 +1023,14 @@ void orc_path_eval(void* s, int L, int n, const double* u, double eps, double* f
                     rec[(size_t)i * 2 * (L - 1) + 2 * j + 1] = pr.nee[j];
                 }
         }
+    });
+}
+
+void orc_path_cond(void* s, int L, int n, const double* u, double eps, double* kappa, int nthreads) {
+    Scene* S = (Scene*)s;
+    const int d = 4 * (L - 1);
+    parallel_chains(n, nthreads, [&](int, int b, int e) {
+        for (int i = b; i < e; ++i) cond_point(*S, L, u + (size_t)i * d, eps, kappa + (size_t)i * d);
     });
 }
 

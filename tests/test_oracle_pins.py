@@ -845,3 +845,30 @@ def test_oracle_reproduces_its_golden_fixture(orc):
         np.testing.assert_allclose(f, np.asarray(case["f"]), rtol=1e-12, atol=0, err_msg=case["name"])
         np.testing.assert_allclose(p, np.asarray(case["p"]), rtol=1e-12, atol=0, err_msg=case["name"])
         np.testing.assert_allclose(score, np.asarray(case["score"]), rtol=1e-9, atol=1e-12, err_msg=case["name"])
+
+
+def test_score_condition_measure_bounds_the_score(orc):
+    """The condition measure the GPU parity tests allow rounding by (the
+    running magnitude of the score's terms, Scene.path_cond) is at least the
+    score's magnitude in every coordinate, equals it where the score has a
+    single term (the film coordinates of a camera ray that hits an emitter
+    directly on a Lambertian box: p there does not depend on the film
+    coordinates, so both are zero), and exceeds it where terms cancel."""
+    for sc, L in ((inputs.cornell_tiny(), 4), (inputs.specular_box(), 8)):
+        S = orc.Scene(sc)
+        u = inputs.random_points(4 * (L - 1), 1500, 7).astype(np.float64)
+        _, p, g, _ = S.path_eval(L, u)
+        k = S.path_cond(L, u)
+        assert np.all(np.isfinite(k)) and np.all(k >= np.abs(g) * (1 - 1e-12))
+        live = p > 1e-6
+        ratio = k[live] / np.maximum(np.abs(g[live]), 1e-300)
+        assert np.median(ratio[np.abs(g[live]) > 0]) < 10      # most coordinates: few terms
+        assert ratio[np.abs(g[live]) > 0].max() > 100          # some cancel strongly
+    # a point whose camera ray ends on the light at vertex 1 with no bounce
+    # taken: f = Le, independent of every coordinate
+    sc = inputs.white_furnace(albedo=0.0, Le=2.0)
+    S = orc.Scene(sc)
+    u = inputs.random_points(4, 50, 3).astype(np.float64)
+    f, p, g, _ = S.path_eval(2, u)
+    k = S.path_cond(2, u)
+    assert np.allclose(f, 2.0) and np.all(g == 0) and np.all(k == 0)
