@@ -347,6 +347,53 @@ dr_status dr_eval_logp_grad(dr_scene* s, uint32_t L, const float* u_dev, uint32_
  * (3 x W*H planar, device).  Asynchronous. */
 dr_status dr_pt_render(dr_scene* s, uint32_t L, uint64_t seed, uint32_t spp, float* img_dev, void* hip_stream);
 
+/* ------------------------------------------------------------------------
+ * Analytic target: the chain step on a wrapped Gaussian mixture
+ * ------------------------------------------------------------------------ */
+/* p(x) = c0 + sum_j w_j prod_i N_wrap(x_i; m_ji, s_j^2) on the torus T^d, and
+ * f = p g with the test functions g = (1, cos 2 pi x_0, sin 2 pi x_0, ...,
+ * cos 2 pi x_{d-1}, sin 2 pi x_{d-1}) (1 + 2d of them).  The Restore
+ * estimator k0 accum / tourCount of Alg. 4.3 converges to lambda(p g), whose
+ * components are c0 + sum_j w_j and sum_j w_j exp(-2 pi^2 s_j^2)
+ * cos / sin(2 pi m_ji) (Sec. 3: the ergodic and importance identities behind
+ * Restore; Sec. 5 for the drift).  The chains use the same regeneration,
+ * Euler-Maruyama move, hold/kill draws and random streams as dr_step. */
+typedef struct {
+    uint32_t d;            /* even, 2..16 */
+    uint32_t n_modes;      /* 0..16 */
+    const float* weights;  /* host, n_modes, finite, >= 0 */
+    const float* means;    /* host, n_modes x d, on [0,1) */
+    const float* stds;     /* host, n_modes, in (0, 0.25] */
+    float c0;              /* constant floor, >= 0; c0 + sum of weights > 0 */
+} dr_mixture_desc;
+
+/* Initialise pass of frame `frame` (Alg. 4.1: x ~ uniform, p_lambda
+ * estimate and k0 = p_lambda/(m dt) unless p->k0 > 0, hold/kill/splat,
+ * scores) and n_steps evolve steps (Alg. 4.2 with Alg. 5.1) of
+ * p->n_chains chains (p->max_path_len and p->mode are ignored;
+ * p->sigma_diag, if set, is a device d x N per-chain stddev).  Chains are
+ * grouped into n_batches batches (the chains of each 256-chain block go to
+ * batch block % n_batches); batch_accum (host, n_batches x (1 + 2d) doubles)
+ * receives each batch's sum of (w/dt) g over all its accumulate events and
+ * batch_tours (host, n_batches) its completed tours, so the estimate is
+ * k0 dt sum(accum) / sum(tours) and the batches give its spread.  *k0_out and
+ * *p_lambda_out (nullable) receive k0 and p_lambda.  Allocates its working
+ * buffers with hipMalloc per call; synchronous on hip_stream.  Errors:
+ * DR_ERR_INVALID_ARG (ranges above, n_batches = 0, null outputs),
+ * DR_ERR_DEVICE. */
+dr_status dr_mixture_run(const dr_mixture_desc* m, const dr_params* p, uint64_t seed, uint32_t frame,
+                         uint32_t n_steps, uint32_t n_batches, double* batch_accum, uint64_t* batch_tours,
+                         double* k0_out, double* p_lambda_out, void* hip_stream);
+
+/* One evolve step at global step index `step` with killing constant k0 (> 0)
+ * from the host state x, score (d x N planar floats) and killed (N, 0/1),
+ * all updated in place (score only for surviving chains); p_out and w_out
+ * (host, N) receive p at the new state and the splat weight (time units).
+ * Synchronous; allocates with hipMalloc per call.  Errors as
+ * dr_mixture_run, and a killed entry other than 0/1. */
+dr_status dr_mixture_step(const dr_mixture_desc* m, const dr_params* p, uint64_t seed, uint64_t step, double k0,
+                          float* x, float* score, uint32_t* killed, float* p_out, float* w_out, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

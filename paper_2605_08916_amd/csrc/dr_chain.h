@@ -11,7 +11,9 @@
 
 namespace dr {
 
-// x ~ uniform on the torus.
+// x ~ uniform on the torus.  Coordinate i takes word i & 3 of block i >> 2;
+// d need only be even (a path's d = 4(L-1) is a multiple of 4; an analytic
+// target may end on a half block).
 __device__ __forceinline__ void regen(uint64_t seed, int d, size_t N, float* x, int c, uint64_t s) {
     for (int b = 0; b < d / 4; ++b) {
         const uint4 r = rng_block(seed, (uint32_t)c, s, TAG_REGEN, (uint32_t)b);
@@ -19,6 +21,12 @@ __device__ __forceinline__ void regen(uint64_t seed, int d, size_t N, float* x, 
         x[(size_t)(4 * b + 1) * N] = u24(r.y);
         x[(size_t)(4 * b + 2) * N] = u24(r.z);
         x[(size_t)(4 * b + 3) * N] = u24(r.w);
+    }
+    if (d & 2) {
+        const int b = d / 4;
+        const uint4 r = rng_block(seed, (uint32_t)c, s, TAG_REGEN, (uint32_t)b);
+        x[(size_t)(4 * b + 0) * N] = u24(r.x);
+        x[(size_t)(4 * b + 1) * N] = u24(r.y);
     }
 }
 
@@ -28,14 +36,17 @@ __device__ __forceinline__ float wrap01(float y) {
 }
 
 // Euler-Maruyama move with rotational drift, per 2-D block (Alg. 5.1):
-// x += (sd^2/2) s + gt (s2, -s1) + sd xi, then wrap to the torus.
+// x += (sd^2/2) s + gt (s2, -s1) + sd xi, then wrap to the torus.  Pair i
+// takes its normals from words 2i, 2i+1 (block i >> 1); d must be even.
 __device__ __forceinline__ void move(uint64_t seed, int d, size_t N, float stddev, float gt, float* x, const float* score,
                                      const float* sigma, int c, uint64_t s) {
-    for (int b = 0; b < d / 4; ++b) {
+    for (int b = 0; b < (d + 2) / 4; ++b) {
         const uint4 r = rng_block(seed, (uint32_t)c, s, TAG_GAUSS, (uint32_t)b);
         const float uu[4] = {u24(r.x), u24(r.y), u24(r.z), u24(r.w)};
+        const int npair = 4 * b + 2 < d ? 2 : 1;  // a trailing half block holds one pair
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
+            if (q >= npair) break;
             const int i0 = 4 * b + 2 * q, i1 = i0 + 1;
             const float rad = sqrtf(-2.0f * logf(1.0f - uu[2 * q]));
             float sn, cs;

@@ -400,18 +400,42 @@ __device__ __forceinline__ void pop_entry(int& node, int& pleaf, int& sp, const 
 // leaf.  The closest hit and the tie rule do not depend on the order of the
 // tests (a postponed leaf only means fewer boxes culled meanwhile), and an
 // any-hit query only reports whether a hit exists.
+//
+// hint (a triangle slot, or -1): a candidate tested before the traversal.
+// A chain's consecutive states lie close together, so the triangle its
+// previous path hit with this ray, or the one that blocked its previous
+// shadow ray, is usually hit again.  A closest-hit query that hits the
+// candidate starts with it as the best hit, so the traversal culls every box
+// beyond it from the first visit; the result is the same closest hit (the
+// box tests are conservative, so every triangle at or before the candidate's
+// distance is still tested, and the tie rule does not depend on order).  An
+// any-hit query that hits the candidate is done.
 __device__ int trace(const DevScene& S, V3 o, V3 d, float tmax, bool anyhit, float& t_hit, uint32_t* stk, int stride,
-                     Counters& ctr) {
+                     Counters& ctr, int hint = -1) {
     t_hit = tmax;
     if (!(tmax > S.tmin)) return -1;
-    const RaySlab rs = ray_slab(o, d);
     float bt = tmax;
     int best = -1;
     uint32_t best_prim = 0xFFFFFFFFu;
+    ctr.rays++;
+    if (hint >= 0 && hint < S.n_tris) {
+        const DevTri T = S.tris[hint];
+        float t;
+        ctr.tris++;
+        if (tri_test(T, o, d, S.tmin, t) && t <= bt) {
+            if (anyhit) {
+                if (t < tmax) return hint;
+            } else {
+                bt = t;
+                best = hint;
+                best_prim = __float_as_uint(T.v0.w);
+            }
+        }
+    }
+    const RaySlab rs = ray_slab(o, d);
     int sp = 0, node = 0, pleaf = 0;
     bool found = false;
     const int cap = S.stack_cap;
-    ctr.rays++;
     while (true) {
         const bool has_leaf = pleaf != 0, can_visit = node >= 0;
         const uint64_t ml = __ballot(has_leaf), mv = __ballot(can_visit);
@@ -686,26 +710,34 @@ __device__ __forceinline__ uint32_t pixel_of(const DevScene& S, float u0, float 
 __device__ __forceinline__ int swap_pair(int v) { return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false); }
 __device__ __forceinline__ float swap_pair(float v) { return __int_as_float(swap_pair(__float_as_int(v))); }
 
+// The shadow ray (any hit, up to smax) and the continuation ray (closest
+// hit) of a vertex; hint_s / hint_c: candidate triangles for each (-1: none).
+// occluder: the slot that blocked the shadow ray (-1 if none).
 template <bool PAIR>
 __device__ __forceinline__ void trace_vertex_rays(const DevScene& S, V3 x, bool shadow, V3 wl, float smax, bool cont,
-                                                  V3 wi, bool& occluded, int& nslot, float& tn, uint32_t* stk,
-                                                  int stride, Counters& ctr) {
+                                                  V3 wi, bool& occluded, int& occluder, int& nslot, float& tn,
+                                                  uint32_t* stk, int stride, Counters& ctr, int hint_s, int hint_c) {
     if (PAIR) {
         const bool odd = (threadIdx.x & 1) != 0;
         float tt;
         const int r = trace(S, x, odd ? wl : wi, odd ? (shadow ? smax : -1.0f) : (cont ? INFINITY : -1.0f), odd, tt,
-                            stk, stride, ctr);
+                            stk, stride, ctr, odd ? hint_s : hint_c);
         const int ro = swap_pair(r);
         const float to = swap_pair(tt);
-        occluded = shadow && (odd ? r : ro) >= 0;
+        occluder = shadow ? (odd ? r : ro) : -1;
+        occluded = occluder >= 0;
         nslot = cont ? (odd ? ro : r) : -1;
         tn = odd ? to : tt;
     } else {
         float ts;
-        occluded = shadow && trace(S, x, wl, smax, true, ts, stk, stride, ctr) >= 0;
-        nslot = cont ? trace(S, x, wi, INFINITY, false, tn, stk, stride, ctr) : -1;
+        occluder = shadow ? trace(S, x, wl, smax, true, ts, stk, stride, ctr, hint_s) : -1;
+        occluded = occluder >= 0;
+        nslot = cont ? trace(S, x, wi, INFINITY, false, tn, stk, stride, ctr, hint_c) : -1;
     }
 }
+
+// Candidate slot from a record entry (rec or occ), -1 if it holds none.
+__device__ __forceinline__ int hint_slot(uint32_t r) { return r == DR_NO_VERTEX ? -1 : (int)(r >> 8); }
 
 // True when every coordinate of the point is finite (accessors over generated
 // coordinates skip the check).
@@ -720,9 +752,14 @@ __device__ __forceinline__ bool point_finite(const U& u, int d) {
     }
 }
 
+// occ (nullable, same layout as rec): per vertex, the slot that blocked its
+// shadow ray (<< 8) or DR_NO_VERTEX, written when the shadow ray is traced.
+// hint: the record rec and occ of this point hold the path of a nearby point
+// (the chain's previous state); their triangles are tried first by the ray
+// queries (results do not depend on it).
 template <bool PAIR, bool DELTA = true, class U>
 __device__ V3 path_forward(const DevScene& S, int L, const U& u, uint32_t* rec, int rs, uint32_t* stk, int stride,
-                           Counters& ctr, int* nverts = nullptr) {
+                           Counters& ctr, int* nverts = nullptr, uint32_t* occ = nullptr, bool hint = false) {
     V3 f = v3(0.f, 0.f, 0.f);
     // a point with a non-finite coordinate (a state that left the torus) has
     // f = 0: its tour is killed and regenerates
@@ -736,15 +773,16 @@ __device__ V3 path_forward(const DevScene& S, int L, const U& u, uint32_t* rec, 
     V3 d = camera_dir(C, u(0), u(1));
     float t;
     int slot;
+    const int hint0 = hint && rec ? hint_slot(rec[0]) : -1;
     if (PAIR) {
         const bool odd = (threadIdx.x & 1) != 0;
-        const int r = trace(S, C.eye, d, odd ? -1.0f : INFINITY, false, t, stk, stride, ctr);
+        const int r = trace(S, C.eye, d, odd ? -1.0f : INFINITY, false, t, stk, stride, ctr, hint0);
         slot = swap_pair(r);
         const float to = swap_pair(t);
         if (!odd) slot = r;
         else t = to;
     } else {
-        slot = trace(S, C.eye, d, INFINITY, false, t, stk, stride, ctr);
+        slot = trace(S, C.eye, d, INFINITY, false, t, stk, stride, ctr, hint0);
     }
     int j = 1;
     if (slot >= 0) {
@@ -787,10 +825,13 @@ __device__ V3 path_forward(const DevScene& S, int L, const U& u, uint32_t* rec, 
                 else cont = bsdf_sample(m, n, wo, u(4 * j), u(4 * j + 1), wi, wt);
             }
             bool occluded;
-            int ns;
+            int occluder, ns;
             float tn;
-            trace_vertex_rays<PAIR>(S, x, shadow, wl, (1.0f - 1e-4f) * r, cont, wi, occluded, ns, tn, stk, stride,
-                                    ctr);
+            const int hs = hint && occ && shadow ? hint_slot(occ[(j - 1) * rs]) : -1;
+            const int hc = hint && rec && cont ? hint_slot(rec[j * rs]) : -1;
+            trace_vertex_rays<PAIR>(S, x, shadow, wl, (1.0f - 1e-4f) * r, cont, wi, occluded, occluder, ns, tn, stk,
+                                    stride, ctr, hs, hc);
+            if (occ && shadow) occ[(j - 1) * rs] = occluder >= 0 ? ((uint32_t)occluder << 8) : DR_NO_VERTEX;
             const bool contrib = shadow && !occluded;
             if (rec)
                 rec[(j - 1) * rs] = ((uint32_t)slot << 8) | ((uint32_t)(delta ? max(lobe, 0) : li) << 1) |

@@ -26,7 +26,7 @@ EXPORTED = [
     "dr_chains_init", "dr_chains_reinit", "dr_step", "dr_resolve", "dr_image_read", "dr_chains_destroy",
     "dr_chains_read_state", "dr_chains_write_state", "dr_chains_set_record", "dr_chains_set_counters", "dr_stats",
     "dr_chains_set_launch", "dr_chains_get_launch", "dr_eval_logp_grad", "dr_pt_render",
-    "dr_frame_capture", "dr_frame_launch", "dr_frame_destroy",
+    "dr_frame_capture", "dr_frame_launch", "dr_frame_destroy", "dr_mixture_run", "dr_mixture_step",
 ]
 
 
@@ -124,6 +124,11 @@ class dr_state(C.Structure):
                 ("k0", C.c_double), ("p_lambda_hat", C.c_double)]
 
 
+class dr_mixture_desc(C.Structure):
+    _fields_ = [("d", C.c_uint32), ("n_modes", C.c_uint32), ("weights", C.POINTER(C.c_float)),
+                ("means", C.POINTER(C.c_float)), ("stds", C.POINTER(C.c_float)), ("c0", C.c_float)]
+
+
 class dr_counters(C.Structure):
     _fields_ = [("chain_steps", C.c_uint64), ("rays", C.c_uint64), ("node_visits", C.c_uint64),
                 ("tri_tests", C.c_uint64), ("kills", C.c_uint64), ("tours", C.c_uint64), ("adjoints", C.c_uint64),
@@ -179,6 +184,12 @@ def lib():
         "dr_frame_capture": ([P, C.c_uint32, C.c_int, P, P, pp], st),
         "dr_frame_launch": ([P, P], st),
         "dr_frame_destroy": ([P], st),
+        "dr_mixture_run": ([C.POINTER(dr_mixture_desc), C.POINTER(dr_params), C.c_uint64, C.c_uint32, C.c_uint32,
+                            C.c_uint32, C.POINTER(C.c_double), C.POINTER(C.c_uint64), C.POINTER(C.c_double),
+                            C.POINTER(C.c_double), P], st),
+        "dr_mixture_step": ([C.POINTER(dr_mixture_desc), C.POINTER(dr_params), C.c_uint64, C.c_uint64, C.c_double,
+                             C.POINTER(C.c_float), C.POINTER(C.c_float), C.POINTER(C.c_uint32), C.POINTER(C.c_float),
+                             C.POINTER(C.c_float), P], st),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -471,3 +482,46 @@ class Frame:
             self.close()
         except Exception:
             pass
+
+
+class Mixture:
+    """Analytic target of the chain step (dr_mixture_run / dr_mixture_step):
+    a wrapped Gaussian mixture on T^d with floor c0; f = p g with the test
+    functions (1, cos 2 pi x_i, sin 2 pi x_i)."""
+
+    def __init__(self, d: int, weights, means, stds, c0: float):
+        self.d = int(d)
+        self.w = np.ascontiguousarray(weights, np.float32).reshape(-1)
+        self.m = np.ascontiguousarray(means, np.float32).reshape(-1, self.d) if self.w.size else np.zeros((0, self.d),
+                                                                                                          np.float32)
+        self.s = np.ascontiguousarray(stds, np.float32).reshape(-1)
+        self.desc = dr_mixture_desc(self.d, self.w.size, _fp(self.w), _fp(self.m), _fp(self.s), float(c0))
+
+    def run(self, n_chains: int, seed: int, n_steps: int, n_batches: int = 32, frame: int = 0, sigma=None,
+            stream=None, **kw) -> dict:
+        """Initialise + n_steps steps; returns per-batch accumulators (units of
+        dt), tours, k0, p_lambda and the estimate k0 dt accum / tours."""
+        p = make_params(n_chains, 2, sigma=sigma, **kw)
+        nf = 1 + 2 * self.d
+        acc = np.zeros((n_batches, nf))
+        tours = np.zeros(n_batches, np.uint64)
+        k0, pl = C.c_double(0), C.c_double(0)
+        _check(lib().dr_mixture_run(C.byref(self.desc), C.byref(p), seed, frame, n_steps, n_batches,
+                                    _fp(acc, C.c_double), _fp(tours, C.c_uint64), C.byref(k0), C.byref(pl),
+                                    _stream(stream)))
+        est = k0.value * p.dt * acc.sum(0) / max(1, int(tours.sum()))
+        return dict(batch_accum=acc, batch_tours=tours, k0=k0.value, p_lambda=pl.value, estimate=est, dt=p.dt)
+
+    def step(self, x, score, killed, seed: int, step: int, k0: float, sigma=None, stream=None, **kw) -> dict:
+        """One evolve step from a host state (x, score: d x N; killed: N)."""
+        x = np.array(x, np.float32, order="C", copy=True)
+        score = np.array(score, np.float32, order="C", copy=True)
+        killed = np.array(killed, np.uint32, order="C", copy=True)
+        n = killed.shape[0]
+        assert x.shape == (self.d, n) and score.shape == (self.d, n)
+        p = make_params(n, 2, sigma=sigma, **kw)
+        pv = np.zeros(n, np.float32)
+        wv = np.zeros(n, np.float32)
+        _check(lib().dr_mixture_step(C.byref(self.desc), C.byref(p), seed, step, k0, _fp(x), _fp(score),
+                                     _fp(killed, C.c_uint32), _fp(pv), _fp(wv), _stream(stream)))
+        return dict(x=x, score=score, killed=killed, p=pv, w=wv)
