@@ -1,11 +1,16 @@
 """Parity of the HIP chain step with the FP64 oracle on identical seeded inputs.
 
 Tolerances follow from FP32 arithmetic on the device against FP64 on the
-host: values of smooth quantities within 1e-4 relative, decisions (kill,
-pixel) identical except where the FP64 value lies within the FP32 rounding
-band of the threshold, and paths whose discrete choices (hit triangle, light,
-visibility) differ between the two precisions excluded from value checks (the
-fraction of such flips is itself bounded).
+host.  Every value of a smooth quantity (f, log p, p, f/p, the holding
+weight, each score coordinate, x') is held to 1e-4 relative, except where
+the oracle itself shows that the sample is ill-conditioned for FP32: its
+value moves by more than 1e-4 / COND_C when every coordinate of the point is
+perturbed by one FP32 ulp (`_sens`).  Such a sample may err by up to COND_C
+times that sensitivity, and by no more.  Decisions (kill, pixel) are
+identical except where the FP64 value lies within the FP32 rounding band of
+the threshold.  Paths whose discrete choices (hit triangle, light,
+visibility, lobe) differ between the two precisions are excluded from value
+checks, and their share is bounded.
 """
 import math
 import os
@@ -53,16 +58,112 @@ def _rel(a, b, floor):
     return np.abs(a - b) / np.maximum(np.abs(b), floor)
 
 
-def _bulk_and_bound(err, tol, bound, frac=0.999):
-    """FP32 against FP64: at least `frac` of the samples within `tol`; the
-    rest, ill-conditioned geometry (e.g. a light point very close to the
-    shading point, where position rounding is amplified by 1/r^2), within
-    `bound`."""
-    err = np.asarray(err)
+# The device's FP32 path evaluation rounds at about a dozen stages per vertex
+# (ray direction, hit point, light vector, r^2, cosines, throughput), each an
+# error of the size a one-ulp perturbation of the point causes; a value may
+# err by this many times the sensitivity `_sens` measures.
+COND_C = 8.0
+TOL = 1e-4
+ULP = 2.0 ** -24
+
+
+def _vec_rel(a, b, floor):
+    """Relative error of each row vector: max |a - b| over the row / max(max |b|, floor)."""
+    return np.abs(a - b).max(axis=1) / np.maximum(np.abs(b).max(axis=1), floor)
+
+
+def _coord_rel(g, go):
+    """Relative error of each score coordinate, against its own size or 1e-2
+    of the sample's largest coordinate, whichever is larger.  Quantities the
+    adjoint shares between coordinates (the path's throughput, distances and
+    cosines, computed once) carry the FP32 rounding of the largest terms into
+    every coordinate: a few ulps of the largest coordinate whatever a
+    coordinate's own size (1e-4 of the floor is 1e-6 of the largest, 17
+    ulps)."""
+    fl = np.maximum(1e-2 * np.abs(go).max(axis=1, keepdims=True), 1e-6)
+    return np.abs(g - go) / np.maximum(np.abs(go), fl)
+
+
+def _fop(f, p):
+    return np.where(p[:, None] > 0, f / np.where(p > 0, p, 1.0)[:, None], 0.0)
+
+
+def _round_allow(L):
+    """Multiple of the unit roundoff times the score's condition measure that
+    the reverse sweep may err by: a dependency path from a coordinate to p
+    passes about 16 roundings per vertex (ray direction, hit point, light
+    vector, r^2 and its root, cosines, BSDF value, throughput), at most L - 1
+    vertices plus the camera ray."""
+    return 16.0 * L * 2.0 ** -24
+
+
+def _sens(O, L, u, K=6, seed=12345):
+    """Conditioning of each point for FP32: the largest relative change of the
+    oracle's f, p, f/p and score (max over coordinates) when every coordinate
+    of the point moves by one FP32 ulp at 1 (2^-24, random signs), over K
+    draws that keep the discrete path; measured with the same error norms the
+    tests use.  Returns (sensitivities, oracle values at u)."""
+    u = np.ascontiguousarray(u, np.float64)
+    f0, p0, g0, r0 = O.path_eval(L, u)
+    fscale = max(1e-6, float(np.abs(f0).mean()))
+    pscale = max(1e-6, float(p0.mean()))
+    fop0 = _fop(f0, p0)
+    n = u.shape[0]
+    s = {k: np.zeros(n) for k in ("f", "p", "fop", "g")}
+    rng = np.random.default_rng(seed)
+    for _ in range(K):
+        u1 = np.clip(u + rng.choice([-1.0, 1.0], size=u.shape) * ULP, 0.0, 1.0 - ULP)
+        f1, p1, g1, r1 = O.path_eval(L, u1)
+        same = np.all(r1 == r0, axis=1)
+        s["f"] = np.maximum(s["f"], np.where(same, _vec_rel(f1, f0, 1e-3 * fscale), 0.0))
+        s["p"] = np.maximum(s["p"], np.where(same, np.abs(p1 - p0) / np.maximum(p0, 1e-3 * pscale), 0.0))
+        s["fop"] = np.maximum(s["fop"], np.where(same, (np.abs(_fop(f1, p1) - fop0) /
+                                                         np.maximum(1.0, np.abs(fop0))).max(axis=1), 0.0))
+        s["g"] = np.maximum(s["g"], np.where(same, _coord_rel(g1, g0).max(axis=1), 0.0))
+    # the score's condition measure per coordinate (terms' magnitudes / (p + eps))
+    s["kappa"] = O.path_cond(L, u)
+    return s, (f0, p0, g0, r0)
+
+
+def _score_within(name, g, go, sens, L):
+    """Every score coordinate within TOL of its size (floored, `_coord_rel`),
+    or within COND_C times the point's sensitivity; plus the reverse sweep's
+    rounding, `_round_allow(L)` times the coordinate's condition measure
+    (where terms cancel, FP32 keeps fewer digits of the sum)."""
+    fl = np.maximum(1e-2 * np.abs(go).max(axis=1, keepdims=True), 1e-6)
+    scale = np.maximum(np.abs(go), fl)
+    err = np.abs(g - go) / scale
+    allow = np.maximum(TOL, COND_C * sens["g"])[:, None] + _round_allow(L) * sens["kappa"] / scale
+    bad = ~(err <= allow)
+    beyond = err > TOL
+    say(f"  {name}: max err {err.max():.2e}, beyond {TOL:g} {int(beyond.sum())} (within the conditioning "
+        f"allowance: {int((beyond & ~bad).sum())}), failing {int(bad.sum())}")
+    if bad.any():
+        i = np.argsort(-(err - allow).ravel())[:5]
+        r, c = np.unravel_index(i, err.shape)
+        detail = [f"(sample {a}, coord {b}: oracle {go[a, b]:.6e} device {g[a, b]:.6e} max|score| "
+                  f"{np.abs(go[a]).max():.3e} kappa {sens['kappa'][a, b]:.3e} sens {sens['g'][a]:.2e})"
+                  for a, b in zip(r, c)]
+        raise AssertionError(f"{name}: {int(bad.sum())} coordinates beyond the allowance; worst err "
+                             f"{err.ravel()[i]} allowance {allow.ravel()[i]} " + " ".join(detail))
+
+
+def _within(name, err, sens):
+    """Every sample within TOL, or within COND_C times its sensitivity."""
+    err, sens = np.asarray(err, np.float64), np.asarray(sens, np.float64)
     if err.size == 0:
         return
-    assert (err <= tol).mean() >= frac, ((err <= tol).mean(), np.sort(err)[-5:])
-    assert err.max() <= bound, err.max()
+    if err.ndim == 2:  # per coordinate, against the sample's sensitivity
+        sens = np.broadcast_to(sens[:, None], err.shape)
+    allow = np.maximum(TOL, COND_C * sens)
+    bad = ~(err <= allow)
+    cond = (err > TOL) & ~bad
+    say(f"  {name}: max err {err.max():.2e}, beyond {TOL:g} {int((err > TOL).sum())} "
+        f"(all within {COND_C:g} x sensitivity: {int(cond.sum())}), failing {int(bad.sum())}")
+    if bad.any():
+        i = np.argsort(-(err - allow).ravel())[:5]
+        raise AssertionError(f"{name}: {int(bad.sum())} beyond the allowance; worst err {err.ravel()[i]} "
+                             f"allowance {allow.ravel()[i]}")
 
 
 def _eval_both(orc, sc, L, n, seed):
@@ -87,28 +188,31 @@ def _eval_both(orc, sc, L, n, seed):
     return u, (f, logp, g), (fo, po, go), match
 
 
-@pytest.mark.parametrize("which,L,n", [("tiny", 4, 4000), ("spheres_small", 8, 3000), ("specular", 8, 4000)])
-def test_eval_matches_oracle(orc, scenes, which, L, n):
-    say(f"[eval parity] scene={which} L={L} n={n}")
-    u, (f, logp, g), (fo, po, go), match = _eval_both(orc, scenes[which], L, n, seed=5)
-    say(f"  path-signature match {match.mean():.5f}")
-    assert match.mean() > 0.995
+def _check_eval(O, L, u, dev, match, name=""):
+    """f, log(p + eps) and every score coordinate of the device evaluation
+    against the oracle, per sample (conditioning allowance as in `_within`),
+    on the samples whose discrete path matches."""
+    f, logp, g = dev
+    sens, (fo, po, go, _) = _sens(O, L, u)
     m = match
     fscale = max(1e-6, float(np.abs(fo).mean()))
-    ferr = _rel(f[m], fo[m], 1e-3 * fscale).max(axis=1)
-    say(f"  f rel err median {np.median(ferr):.2e} p99.9 {np.quantile(ferr, 0.999):.2e} max {ferr.max():.2e}")
-    _bulk_and_bound(ferr, 1e-4, 1e-2)
+    _within(f"{name}f", _vec_rel(f[m], fo[m], 1e-3 * fscale), sens["f"][m])
     pos = m & (po > 1e-3 * po.mean())
-    _bulk_and_bound(np.abs(logp[pos] - np.log(po[pos] + 1e-8)), 1e-4, 1e-2)
-    # score: relative error of the score vector of each sample
-    live = pos
-    err = np.linalg.norm(g[live] - go[live], axis=1) / np.maximum(np.linalg.norm(go[live], axis=1), 1e-6)
-    say(f"  score rel err: median {np.median(err):.2e} p99 {np.quantile(err, 0.99):.2e} max {err.max():.2e}")
-    assert np.median(err) < 1e-5
-    assert np.quantile(err, 0.99) < 1e-3
+    # |d log p| = |dp| / p: the relative error of p
+    _within(f"{name}log p", np.abs(logp[pos] - np.log(po[pos] + 1e-8)), sens["p"][pos])
+    _score_within(f"{name}score", g[pos], go[pos], {k: v[pos] for k, v in sens.items()}, L)
     # p == 0 paths have a zero score on both sides
     zero = m & (po == 0)
     assert np.all(g[zero] == 0)
+
+
+@pytest.mark.parametrize("which,L,n", [("tiny", 4, 4000), ("spheres_small", 8, 3000), ("specular", 8, 4000)])
+def test_eval_matches_oracle(orc, scenes, which, L, n):
+    say(f"[eval parity] scene={which} L={L} n={n}")
+    u, dev, _, match = _eval_both(orc, scenes[which], L, n, seed=5)
+    say(f"  path-signature match {match.mean():.5f}")
+    assert match.mean() > 0.995
+    _check_eval(orc.Scene(scenes[which]), L, u.astype(np.float64), dev, match)
 
 
 @pytest.mark.parametrize("which,L,n", [("tiny", 4, 3000), ("spheres_small", 8, 20000), ("specular", 8, 20000)])
@@ -197,7 +301,10 @@ def _onestep(orc, sc, L, N, mode, seed, k0, gamma=0.5, sigma=None, sample=None, 
     ch = dr.Chains(S, N, L, seed, k0=k0, gamma=gamma, mode=mode, sigma=sig_t, rao_blackwell=rao_blackwell)
     ch.set_record(True)
     step0 = (7 << 32) + 11
-    ch.write_state(x=st["x"], score=st["score"], killed=st["killed"], step=step0, k0=k0)
+    # the frame buffer starts empty, so after the step it holds that step's splats only
+    npx = int(sc["width"]) * int(sc["height"])
+    ch.write_state(x=st["x"], score=st["score"], killed=st["killed"], accum=np.zeros((3, npx), np.float32),
+                   step=step0, k0=k0)
     ch.step(1)
     gs = ch.read_state()
     idx = np.arange(N) if sample is None else np.asarray(sample)
@@ -206,30 +313,37 @@ def _onestep(orc, sc, L, N, mode, seed, k0, gamma=0.5, sigma=None, sample=None, 
                           sigma=None if sigma is None else sigma[:, idx], rao_blackwell=rao_blackwell)
     oc.set_ids(idx.astype(np.uint32))
     score_in = st["score"][:, idx]
+    aux = {}
     if mode == dr.DR_MODE_PLAIN:
         # the plain form recomputes the score of the current state at the start
-        # of its step (Alg. 5.1 starts from it): give the oracle its own score at x
-        _, _, sc_o, _ = O.path_eval(L, st["x"][:, idx].T.astype(np.float64))
+        # of its step (Alg. 5.1 starts from it): give the oracle its own score
+        # at x, and keep that score's FP32 conditioning for the x' check
+        sens_x, (_, _, sc_o, _) = _sens(O, L, st["x"][:, idx].T.astype(np.float64))
         score_in = sc_o.T.astype(np.float32)
+        aux = {"score_x": sc_o, "score_x_sens": sens_x["g"], "score_x_kappa": sens_x["kappa"].max(axis=1)}
     oc.set_state(st["x"][:, idx], score_in, st["killed"][idx], step0, k0=k0)
     oc.step(1, nthreads=16)
     os_ = oc.state()
-    gsel = {k: (v[..., idx] if isinstance(v, np.ndarray) and v.shape[-1] == N else v) for k, v in gs.items()}
+    os_.update(aux)
+    os_["accum"] = oc.accum()["accum"].T  # 3 x W*H, sum of w f/p
+    gsel = {k: (v[..., idx] if isinstance(v, np.ndarray) and v.shape[-1] == N and k != "accum" else v)
+            for k, v in gs.items()}
     return st, gsel, os_, idx, step0
 
 
 def _compare_step(orc, sc, L, st, gs, os_, idx, seed, step0, k0, dt=1e-5, eps=1e-8, check_score=True,
-                  plain=False):
+                  plain=False, stddev=5e-3, gamma=0.5):
     W, H = sc["width"], sc["height"]
-    n = len(idx)
-    V = L - 1
     prim = os_["rec"][0::2].astype(np.int64)
     nee = os_["rec"][1::2].astype(np.uint64)
     rec_o = np.where(prim.astype(np.int32) >= 0, (prim.astype(np.uint64) << 8) | (nee & 0xFF), 0xFFFFFFFF)
     match = np.all(rec_o.astype(np.uint32) == gs["path_rec"], axis=0)
     say(f"  path-signature match {match.mean():.5f}")
     assert match.mean() > 0.99
-    # x' on the torus: step-relative error
+    # FP32 conditioning of the new state (the oracle at its own x')
+    O = orc.Scene(sc)
+    sens, _ = _sens(O, L, os_["x"].T)
+    # x' on the torus: error relative to the step
     dx = gs["x"].astype(np.float64) - os_["x"]
     dx = np.abs(dx - np.round(dx))
     step = np.abs(os_["x"] - st["x"][:, idx].astype(np.float64))
@@ -237,11 +351,20 @@ def _compare_step(orc, sc, L, st, gs, os_, idx, seed, step0, k0, dt=1e-5, eps=1e
     xerr = dx / np.maximum(step, 5e-3)
     say(f"  x' step-relative err max {xerr.max():.2e}")
     if plain:
-        # the plain form's own score at x can take a different discrete path
-        # from the oracle's on the rare flipped chains
-        assert (xerr.max(0) < 1e-4).mean() > 0.99
+        # the plain form computes its own FP32 score at x; its error moves x'
+        # by the drift's factor (stddev^2/2 + gamma~) times the score error,
+        # which the conditioning of that score bounds
+        gx = np.abs(os_["score_x"]).max(axis=1)
+        allow_dx = (stddev ** 2 / 2 + dt * gamma / 2) * (COND_C * os_["score_x_sens"] * gx +
+                                                         _round_allow(L) * os_["score_x_kappa"])
+        live = st["killed"][idx] == 0
+        allow = TOL + np.where(live, allow_dx, 0.0)[None, :] / np.maximum(step, 5e-3)
+        bad = xerr > allow
+        say(f"  x' beyond {TOL:g}: {int((xerr > TOL).sum())}, beyond the score-conditioning allowance: "
+            f"{int(bad.sum())}")
+        assert not bad.any(), (xerr[bad][:5], allow[bad][:5])
     else:
-        assert xerr.max() < 1e-4
+        assert xerr.max() < TOL
     # pixel: identical except within 1e-3 pixel of an edge
     fx = os_["x"][0] * W
     fy = os_["x"][1] * H
@@ -260,23 +383,53 @@ def _compare_step(orc, sc, L, st, gs, os_, idx, seed, step0, k0, dt=1e-5, eps=1e
     assert kill_bad.sum() == 0
     m = match
     pscale = max(1e-6, float(os_["p"].mean()))
-    perr = _rel(gs["p"][m], os_["p"][m], 1e-3 * pscale)
-    say(f"  p rel err median {np.median(perr):.2e} p99.9 {np.quantile(perr, 0.999):.2e} max {perr.max():.2e}")
-    _bulk_and_bound(perr, 1e-4, 1e-2)
+    _within("p", _rel(gs["p"][m], os_["p"][m], 1e-3 * pscale), sens["p"][m])
     fop_err = (np.abs(gs["f_over_p"][:, m] - os_["f_over_p"][:, m]) / np.maximum(1, np.abs(os_["f_over_p"][:, m]))).max(0)
-    _bulk_and_bound(fop_err, 1e-4, 1e-2)
+    _within("f/p", fop_err, sens["fop"][m])
     # w = dt/(1 + k dt) with k = k0/(p + eps): its error follows p's
     praw = np.abs(gs["p"][m] - os_["p"][m]) / np.maximum(os_["p"][m] + eps, 1e-30)
     werr = _rel(gs["weight"][m], os_["w"][m], 1e-30)
     assert np.all(werr <= 2 * praw + 1e-5), np.max(werr - 2 * praw)
+    if len(idx) == gs["x"].shape[1] and np.array_equal(idx, np.arange(len(idx))):
+        _check_accum(gs, os_, sens, match, dt)
     if check_score:
         live = m & (os_["killed"] == 0) & (gs["killed"] == 0) & (os_["p"] > 1e-3 * pscale)
         if not live.any():  # e.g. a single chain that was killed: no score to compare
             return
-        go, gg = os_["score"][:, live], gs["score"][:, live].astype(np.float64)
-        err = np.linalg.norm(gg - go, axis=0) / np.maximum(np.linalg.norm(go, axis=0), 1e-6)
-        say(f"  score rel err median {np.median(err):.2e} p99 {np.quantile(err, 0.99):.2e}")
-        assert np.median(err) < 1e-5 and np.quantile(err, 0.99) < 1e-3
+        go, gg = os_["score"][:, live].T, gs["score"][:, live].T.astype(np.float64)
+        _score_within("score", gg, go, {k: v[live] for k, v in sens.items()}, L)
+
+
+def _check_accum(gs, os_, sens, match, dt):
+    """The frame buffer after one step from an empty one, pixel by pixel: the
+    device's sum of (w/dt) f/p times dt against the oracle's sum of w f/p.
+    Each chain's splat may err by its allowances for f/p and for the weight
+    (twice p's), the atomics' summation order adds a rounding of the pixel's
+    sum per contribution; pixels that a chain with a different discrete path
+    or pixel reaches are left out."""
+    dev = gs["accum"].astype(np.float64) * dt
+    orc_acc = os_["accum"]
+    npx = orc_acc.shape[1]
+    pix = os_["pixel"].astype(np.int64)
+    live = os_["p"] > 0
+    fop = np.abs(os_["f_over_p"])  # 3 x n
+    w = os_["w"]
+    a_fop = np.maximum(TOL, COND_C * sens["fop"])
+    a_w = 2 * np.maximum(TOL, COND_C * sens["p"])
+    err_c = w * (a_fop * np.maximum(1.0, fop.max(axis=0)) + a_w * fop.max(axis=0) + 1e-6)
+    bound = np.bincount(pix[live], weights=err_c[live], minlength=npx)
+    count = np.bincount(pix[live], minlength=npx)
+    off = ~match | (gs["pixel"] != os_["pixel"])
+    skip = np.zeros(npx, bool)
+    skip[pix[off & live]] = True
+    skip[gs["pixel"][off].astype(np.int64)] = True
+    bound = bound[None, :] + count[None, :] * 2.0 ** -22 * orc_acc
+    diff = np.abs(dev - orc_acc)
+    bad = (diff > bound) & ~skip[None, :]
+    say(f"  accum: {int(live.sum())} splats over {int((count > 0).sum())} pixels, left out {int(skip.sum())}, "
+        f"max rel {float((diff / np.maximum(orc_acc, 1e-30))[:, ~skip].max()):.2e}, failing {int(bad.sum())}")
+    assert skip.mean() < 0.01
+    assert not bad.any(), (diff[bad][:5], bound[bad][:5])
 
 
 @pytest.mark.parametrize("mode", [dr.DR_MODE_FUSED, dr.DR_MODE_PLAIN])
@@ -356,6 +509,11 @@ def test_init_matches_oracle(orc, scenes):
 
 
 def test_fused_and_plain_agree(scenes):
+    """The fused persistent form and the plain multi-kernel form draw the same
+    streams and compile the same arithmetic, so 20 steps from the same
+    initial state leave bit-identical chains (the plain form's score at the
+    start of a step is the one the fused form computed after the previous
+    one); the frame buffers differ only by the atomics' summation order."""
     sc = scenes["tiny"]
     L, N, seed = 4, 1024, 17
     say(f"[fused vs plain] L={L} N={N}")
@@ -367,11 +525,12 @@ def test_fused_and_plain_agree(scenes):
         s = ch.read_state()
         out.append(s)
     a, b = out
-    agree = (a["killed"] == b["killed"]).mean()
-    close = np.abs(a["x"] - b["x"]).max()
-    say(f"  kill agreement {agree:.5f}, max |dx| {close:.2e}, tours {a['tour_count']} {b['tour_count']}")
-    assert agree > 0.99
-    assert abs(a["tour_count"] - b["tour_count"]) <= 0.01 * a["tour_count"] + 5
+    say(f"  kill agreement {(a['killed'] == b['killed']).mean():.5f}, max |dx| {np.abs(a['x'] - b['x']).max():.2e}, "
+        f"tours {a['tour_count']} {b['tour_count']}")
+    assert np.array_equal(a["x"], b["x"])
+    assert np.array_equal(a["killed"], b["killed"])
+    assert a["tour_count"] == b["tour_count"]
+    assert np.allclose(a["accum"], b["accum"], rtol=1e-5, atol=0)
 
 
 def test_pt_render_matches_oracle(orc, scenes):
@@ -389,15 +548,15 @@ def test_pt_render_matches_oracle(orc, scenes):
 
 def test_image_statistics_match_oracle(orc, scenes):
     """The tiny configuration (256 chains x 1000 steps): device and oracle
-    images over 8 seeds each; their MRSE against a path-traced reference must
-    lie in each other's 95% band, and their means agree within the
-    seed-to-seed spread."""
+    images over 32 seeds each (the same seeds on both sides); their MRSE
+    against a path-traced reference must lie in each other's 95% band, and
+    their means agree within the seed-to-seed spread."""
     sc = scenes["tiny"]
-    L, N, steps, R = 4, 256, 1000, 8
+    L, N, steps, R = 4, 256, 1000, 32
     say(f"[image stats] L={L} N={N} steps={steps} R={R}")
     S = dr.Scene(sc)
-    ref = S.pt_render(L, 12345, 1024).cpu().numpy().astype(np.float64)
     O = orc.Scene(sc)
+    ref = O.pt_render(L, 12345, 1024, nthreads=16)
 
     def mrse(img):
         return float(((img - ref) ** 2 / (ref ** 2 + 1e-2)).mean())
@@ -407,7 +566,8 @@ def test_image_statistics_match_oracle(orc, scenes):
         ch = dr.Chains(S, N, L, 1000 + r)
         ch.step(steps)
         img, _ = ch.image_read()
-        g_m.append(mrse(img))
+        ch.close()
+        g_m.append(mrse(img.astype(np.float64)))
         g_means.append(img.mean())
         oc = orc.Chains.scene(O, L, N, seed=1000 + r)
         oc.init(nthreads=16)
@@ -415,12 +575,13 @@ def test_image_statistics_match_oracle(orc, scenes):
         oi = oc.resolve()
         o_m.append(mrse(oi))
         o_means.append(oi.mean())
+        say(f"  seed {r}: MRSE device {g_m[-1]:.4f} oracle {o_m[-1]:.4f}")
     g_m, o_m = np.array(g_m), np.array(o_m)
     say(f"  MRSE device {g_m.mean():.4f}+-{g_m.std():.4f}  oracle {o_m.mean():.4f}+-{o_m.std():.4f}")
     se = math.sqrt(g_m.var(ddof=1) / R + o_m.var(ddof=1) / R)
-    assert abs(g_m.mean() - o_m.mean()) < 2.5 * se + 1e-3
+    assert abs(g_m.mean() - o_m.mean()) < 1.96 * se + 1e-4
     sm = math.sqrt(np.var(g_means, ddof=1) / R + np.var(o_means, ddof=1) / R)
-    assert abs(np.mean(g_means) - np.mean(o_means)) < 3 * sm + 1e-4
+    assert abs(np.mean(g_means) - np.mean(o_means)) < 1.96 * sm + 1e-5
 
 
 def test_resume_is_bit_identical(scenes):
@@ -634,16 +795,23 @@ def test_node_cache_does_not_change_results(scenes, lanes):
         assert a["tour_count"] == b["tour_count"]
 
 
-def test_captured_frames_replay_like_eager(scenes):
+@pytest.mark.parametrize("order", ["none", "length", "tile"])
+def test_captured_frames_replay_like_eager(scenes, order):
     """A captured frame (re-init + n steps + resolve) replayed several times,
     with a camera change between replays and eager work in between, gives the
-    chains and image the same calls give eagerly."""
+    chains and image the same calls give eagerly.  With chain ordering on, the
+    frame's steps move chains between slots: host reads and writes of the
+    state between replays must still see every chain in its own slot."""
     sc = scenes["spheres_small"]
     L, N, n = 8, 4096, 5
-    say(f"[frame graph] L={L} N={N} steps/frame={n}")
+    say(f"[frame graph] L={L} N={N} steps/frame={n} order={order}")
     S1, S2 = dr.Scene(sc), dr.Scene(sc)
     a = dr.Chains(S1, N, L, 41, frame=3)
     b = dr.Chains(S2, N, L, 41, frame=3)
+    if order != "none":
+        cfg = {"sort_by_length": 1} if order == "length" else {"sort_by_tile": 1}
+        a.set_launch(**cfg)
+        b.set_launch(**cfg)
     stream = torch.cuda.Stream()
     img_a = torch.zeros((3, S1.W * S1.H), device="cuda")
     with torch.cuda.stream(stream):
@@ -662,11 +830,19 @@ def test_captured_frames_replay_like_eager(scenes):
         sa, sb = a.read_state(), b.read_state()
         assert sa["step"] == sb["step"] == ((4 + k) << 32) + 1 + n
         assert np.array_equal(sa["x"], sb["x"]) and np.array_equal(sa["killed"], sb["killed"])
+        assert np.array_equal(sa["score"], sb["score"])
         assert sa["tour_count"] == sb["tour_count"]
         ia, ib = img_a.cpu().numpy(), img_b.cpu().numpy()
         assert np.allclose(ia, ib, rtol=1e-4, atol=1e-6), np.abs(ia - ib).max()
-        a.step(1)   # eager work between replays on the captured chain set
+        # a host write between replays (the state read back unchanged) must
+        # land every chain in its own slot, then eager work continues
+        a.write_state(x=sa["x"], score=sa["score"], killed=sa["killed"])
+        b.write_state(x=sb["x"], score=sb["score"], killed=sb["killed"])
+        a.step(1)
         b.step(1)
+        torch.cuda.synchronize()
+        sa, sb = a.read_state(), b.read_state()
+        assert np.array_equal(sa["x"], sb["x"]) and np.array_equal(sa["killed"], sb["killed"])
     frame.close()
 
 
@@ -705,9 +881,7 @@ def test_adjoint_long_paths_with_segment_recompute(orc, which):
     say(f"  path-signature match {match.mean():.5f}")
     assert match.mean() > 0.99
     live = match & (po > 1e-3 * po.mean())
-    err = np.linalg.norm(g[live] - go[live], axis=1) / np.maximum(np.linalg.norm(go[live], axis=1), 1e-6)
-    say(f"  score rel err median {np.median(err):.2e} p99 {np.quantile(err, 0.99):.2e}")
-    assert np.median(err) < 1e-5 and np.quantile(err, 0.99) < 1e-3
+    _check_eval(orc.Scene(sc), L, u.astype(np.float64), (f, logp, g), match)
     S = dr.Scene(sc)
     ut = torch.from_numpy(u).cuda()
     _, lp0, _, r0 = S.eval_logp_grad(L, ut, grad=False, rec=True)
@@ -769,7 +943,7 @@ def test_delta_closed_forms_on_device():
     assert np.allclose(f[0], 1.5 ** 2 * Le, rtol=1e-5)
 
 
-def test_device_matches_stored_oracle_values():
+def test_device_matches_stored_oracle_values(orc):
     """The device against the oracle values stored in tests/golden (written by
     the oracle from seeded points on the tiny box, the specular box and the
     mirror plane): path records equal, f and the score within the FP32
@@ -791,10 +965,13 @@ def test_device_matches_stored_oracle_values():
         rec_o = np.where(prim >= 0, (prim << 8) | (nee & 0xFF), 0xFFFFFFFF).astype(np.uint32)
         assert np.array_equal(rec_o, rec), case["name"]
         fo, po, go = np.asarray(case["f"]), np.asarray(case["p"]), np.asarray(case["score"])
-        _bulk_and_bound(_rel(f, fo, 1e-3 * max(1e-6, np.abs(fo).mean())).max(axis=1), 1e-4, 1e-2, frac=0.95)
+        u64 = np.asarray(case["u"], np.float32).astype(np.float64)
+        sens, (fl, pl, gl, _) = _sens(orc.Scene(getattr(inputs, case["scene"])()), L, u64)
+        # the stored values are the oracle's own at these points
+        assert np.allclose(fl, fo, rtol=1e-12, atol=0) and np.allclose(gl, go, rtol=1e-9, atol=1e-12)
+        _within(f"{case['name']} f", _vec_rel(f, fo, 1e-3 * max(1e-6, np.abs(fo).mean())), sens["f"])
         live = po > 1e-3 * po.mean()
-        err = np.linalg.norm(g[live] - go[live], axis=1) / np.maximum(np.linalg.norm(go[live], axis=1), 1e-6)
-        assert np.median(err) < 1e-5 and err.max() < 1e-2, (case["name"], np.median(err), err.max())
+        _score_within(f"{case['name']} score", g[live], go[live], {k: v[live] for k, v in sens.items()}, L)
 
 
 def test_torch_allocator_serves_library_buffers(scenes):
@@ -848,8 +1025,11 @@ def test_autotune_restores_chains(scenes, tmp_path, monkeypatch):
     applied = {k: (int(v == 1) if k in flags else v) for k, v in entry["cfg"].items()}
     got = a.get_launch()
     assert {k: got[k] for k in applied} == applied
-    assert len(entry["sweep"]) == len(autotune.candidates()) == 2 * 2 * len(autotune.ORDERS) * (
-        len(autotune.GRABS) * len(autotune.LANES) + len(autotune.REFILL_PCTS))
+    # staged search: block x blocks per CU, then lanes, orderings, queue batch
+    # depth (grab), node cache and the refill form, each from the best so far
+    assert len(entry["sweep"]) == 2 * 2 + len(autotune.LANES) + (len(autotune.ORDERS) - 1) + (
+        len(autotune.GRABS) - 1) + (len(autotune.NODE_CACHES) - 1) + len(autotune.REFILL_PCTS)
+    assert entry["ms"] == min([ms for ms, _ in entry["sweep"]] + [entry["current_ms"]])
     a.step(3)
     b.step(3)
     sa, sb = a.read_state(), b.read_state()
