@@ -1,19 +1,25 @@
 """Benchmark of the Diffusion Restore chain step on one MI355X.
 
-Workload: the procedural 50k-triangle scene (noise-displaced icospheres with
-GGX conductors on a ground plane, two partly occluded quad lights), 512x512
-frame buffer, path length <= 8 (d = 28), 65,536 chains, FP32, scores from the
-reverse-mode adjoint.
+Default workload: the real-time loop on the procedural interior (a closed
+room of 2,048,020 triangles: instanced noise-displaced meshes, two ceiling
+quad lights and one partly occluded light), 1920x1080 frame buffer, path
+length <= 8 (d = 28), 4,194,304 chains resident in HBM, FP32, scores from the
+reverse-mode adjoint, the camera moving along a 60-frame path.
 
-One timed step = one evolve pass over every chain (move or regenerate,
-forward path trace, hold/kill, splat, adjoint for survivors).  Steps are
-issued as frames, as the real-time loop issues them: one frame = F steps
-(one dr_step(F) launch) followed by the resolve pass of the frame buffer.
-`value` = chains x steps / time (chain-steps/s) of the fused persistent form.
-The plain multi-kernel form is timed on the same frames, the single-step
-dispatch (dr_step(1) + resolve per step) is reported beside them, and the
-image quality after 33.3 ms of fused steps is reported as MRSE against a
-path-traced reference.
+One timed step of this benchmark is one displayed frame of that loop: the
+camera changes (a scene change), so the frame re-initialises every chain
+(Alg. 4.1), runs as many evolve steps as a 33.3 ms frame leaves room for
+(at least one), and resolves the image (Alg. 4.3); the frame is one captured
+HIP graph, replayed once per frame.  `value` = chains x evolve steps per
+frame x frames / wall time of the timed frames (chain-steps/s; the
+initialise pass, which also evaluates f and the score of every chain, is not
+counted as a step).  Also reported: the steady-state evolve rate of the same
+chains, the plain multi-kernel form on the same workload, MRSE of the frame
+images along the camera path against path-traced references with their own
+noise subtracted (split halves), the same loop at 1,048,576 chains, equal-time
+path tracing, the roofline of the dominant kernel, and the oracle on the
+host's cores.  The procedural 53k-triangle scene (512x512, 65,536 chains) is
+reported beside it as a secondary line.
 
 Prints one JSON line.
 """
@@ -37,36 +43,55 @@ HBM_PEAK_GBS = 8000.0
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=60)
+    ap.add_argument("--steps", type=int, default=20,
+                    help="timed frames of the real-time loop (secondary lines: evolve steps)")
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-mrse", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the 53k-triangle secondary line and the 1,048,576-chain loop")
     ap.add_argument("--no-scaling", action="store_true",
-                    help="skip the larger chain counts reported beside the headline line")
+                    help="skip the larger chain counts reported beside the 53k-triangle line")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--chains", type=int, default=65536)
-    ap.add_argument("--steps-per-frame", type=int, default=8)
+    ap.add_argument("--no-tune", action="store_true", help="skip the launch autotuner (default launch rule)")
+    ap.add_argument("--chains", type=int, default=None,
+                    help="chains of the measured workload (default: the workload's own count)")
+    ap.add_argument("--steps-per-frame", type=int, default=8,
+                    help="53k-triangle line and --config: evolve steps per launch")
+    ap.add_argument("--frame-steps", type=int, default=None,
+                    help="real-time loop: evolve steps per frame (default: as many as fit 33.3 ms, at least 1)")
     ap.add_argument("--profile-only", action="store_true",
-                    help="only run warmup + steps of the fused form (for hardware-counter runs)")
+                    help="only run warmup + steps launches of the measured workload's dominant kernel (for "
+                         "hardware-counter runs; with --config, that configuration's fused launches)")
+    ap.add_argument("--headline-spheres", action="store_true",
+                    help="print the 53k-triangle line (512x512, 65,536 chains) as the main line instead")
     ap.add_argument("--config", default=None,
-                    help="measure a named larger configuration instead of the headline line (instances, "
-                         "spheres_1080p_L16, interior, spheres_specular); prints its own JSON line")
+                    help="measure a named larger configuration (instances, spheres_1080p_L16, spheres_specular); "
+                         "prints its own JSON line")
     ap.add_argument("--config-chains", type=int, default=None,
                     help="with --config: run the configuration with this many chains instead of its own")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates the FETCH_SIZE/WRITE_SIZE counters)")
     ap.add_argument("--traffic-summary", nargs="+", metavar="DIR",
-                    help="no GPU: write the HBM traffic summary of the fused kernel from rocprofv3 --pmc output "
-                         "folders: FETCH_SIZE and WRITE_SIZE of --profile-only, then of --copy-probe, optionally "
-                         "followed by TCC_HIT_sum/TCC_MISS_sum and SQ_WAVE_CYCLES/SQ_ACTIVE_INST_VALU folders")
+                    help="no GPU: write the HBM traffic summary of the dominant kernel from rocprofv3 --pmc "
+                         "output folders: FETCH_SIZE and WRITE_SIZE of --profile-only, then of --copy-probe, "
+                         "optionally followed by TCC_HIT_sum/TCC_MISS_sum and SQ_WAVE_CYCLES/SQ_ACTIVE_INST_VALU "
+                         "folders (with --headline-spheres: the 53k-triangle kernel)")
     return ap.parse_args()
 
 
-# ---- HBM traffic of the fused kernel, from hardware counters.  The summary
-# records a digest of the kernel sources; a bench run whose sources differ
-# reports traffic as null.
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_fused_spheres53k_traffic.txt")
+# ---- HBM traffic of the dominant kernel, from hardware counters.  Each
+# summary records a digest of the kernel sources and the launch shape; a bench
+# run whose sources or shape differ reports traffic as null.
+TRAFFIC_FILES = {
+    "interior": os.path.join(ROOT, "profiles", "k_step_fused_interior2M_4Mchains_traffic.txt"),
+    "spheres": os.path.join(ROOT, "profiles", "k_step_fused_spheres53k_traffic.txt"),
+}
+TRAFFIC_TITLES = {
+    "interior": "k_step_fused<8, false>: procedural interior 2,048,020 triangles, 1920x1080, L = 8, one lane per chain",
+    "spheres": "k_step_fused_pair<8, false>: procedural spheres 53k triangles, 512x512, L = 8",
+}
 KERNEL_SOURCES = ["paper_2605_08916_amd/csrc/dr_lib.hip", "paper_2605_08916_amd/csrc/dr_device.h",
                   "paper_2605_08916_amd/csrc/dr_adjoint.h", "paper_2605_08916_amd/csrc/dr_chain.h",
                   "paper_2605_08916_amd/csrc/dr_machine.h", "include/dr.h", "paper_2605_08916_amd/build.py"]
@@ -95,7 +120,7 @@ def _pmc_rows(folder, counter):
     return rows
 
 
-def write_traffic_summary(dirs, chains, per_launch):
+def write_traffic_summary(dirs, workload, chains, per_launch, cmd):
     fetch_dir, write_dir, cfetch_dir, cwrite_dir = dirs[:4]
 
     def fused_mean(folder, counter):
@@ -113,12 +138,12 @@ def write_traffic_summary(dirs, chains, per_launch):
     fs = copy_bytes / (copy_kib(cfetch_dir, "FETCH_SIZE") * 1024.0)
     ws = copy_bytes / (copy_kib(cwrite_dir, "WRITE_SIZE") * 1024.0)
     rd, wr = fk * 1024.0 * fs, wk * 1024.0 * ws
-    cmd = f"python3 bench.py --profile-only --steps 8 --warmup 2 --chains {chains} --steps-per-frame {per_launch}"
     lines = [
-        "# HBM traffic of k_step_fused_pair<8, false>: procedural spheres 53k triangles, 512x512, L = 8",
+        f"# HBM traffic of {TRAFFIC_TITLES[workload]}",
         f"# counters: rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) -d <out> -- {cmd}",
         "# calibration: rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) -d <out> -- python3 bench.py --copy-probe",
-        "# written by: python3 bench.py --traffic-summary <fetch> <write> <copy_fetch> <copy_write> [<tcc> <sq2>]",
+        "# written by: python3 bench.py --traffic-summary <fetch> <write> <copy_fetch> <copy_write> [<tcc> <sq2>]"
+        + (" --headline-spheres" if workload == "spheres" else ""),
         "# tcc: --pmc TCC_HIT_sum TCC_MISS_sum; sq2: --pmc SQ_WAVE_CYCLES SQ_WAIT_ANY SQ_ACTIVE_INST_ANY "
         "SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_VMEM SQ_ACTIVE_INST_LDS SQ_ACTIVE_INST_SCA SQ_INST_CYCLES_VMEM_RD "
         "(same --profile-only command); valu_issue_frac is per wavefront",
@@ -142,38 +167,36 @@ def write_traffic_summary(dirs, chains, per_launch):
         valu, _ = fused_mean(dirs[5], "SQ_ACTIVE_INST_VALU")
         wc, _ = fused_mean(dirs[5], "SQ_WAVE_CYCLES")
         lines += [f"l2_hit_rate: {hit / (hit + miss):.4f}", f"valu_issue_frac: {valu / wc:.4f}"]
-    with open(TRAFFIC_FILE, "w") as f:
+    with open(TRAFFIC_FILES[workload], "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
 
-def read_counters(chains, per_launch):
-    """L2 hit rate and VALU issue fraction of the fused kernel from the same
-    committed counter summary (empty when it does not match the sources)."""
+def _traffic_kv(workload, chains, per_launch):
+    """The committed counter summary of the workload's dominant kernel, or {}
+    when it is missing, was taken on another launch shape, or the kernel
+    sources changed since."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(TRAFFIC_FILES[workload]) as f:
             kv = dict(l.split(": ", 1) for l in f.read().splitlines() if l and not l.startswith("#"))
     except OSError:
         return {}
     if (kv.get("sources_digest") != sources_digest() or int(kv.get("chains", -1)) != chains
             or int(kv.get("steps_per_launch", -1)) != per_launch):
         return {}
+    return kv
+
+
+def read_counters(workload, chains, per_launch):
+    """L2 hit rate and VALU issue fraction from the counter summary."""
+    kv = _traffic_kv(workload, chains, per_launch)
     return {k: float(kv[k]) for k in ("l2_hit_rate", "valu_issue_frac") if k in kv}
 
 
-def read_traffic(chains, per_launch):
-    """HBM bytes per launch from the committed counter summary, or None when
-    the summary is missing, was taken on another launch shape, or the kernel
-    sources changed since."""
-    try:
-        with open(TRAFFIC_FILE) as f:
-            kv = dict(l.split(": ", 1) for l in f.read().splitlines() if l and not l.startswith("#"))
-    except OSError:
-        return None
-    if (kv.get("sources_digest") != sources_digest() or int(kv.get("chains", -1)) != chains
-            or int(kv.get("steps_per_launch", -1)) != per_launch):
-        return None
-    return float(kv["hbm_bytes_per_launch"])
+def read_traffic(workload, chains, per_launch):
+    """HBM bytes per launch from the counter summary, or None."""
+    kv = _traffic_kv(workload, chains, per_launch)
+    return float(kv["hbm_bytes_per_launch"]) if "hbm_bytes_per_launch" in kv else None
 
 
 def alg_bytes_per_chain_step(rays, nodes, tris, d, L):
@@ -308,13 +331,23 @@ def time_kernel_only(ch, torch, launches, per_launch):
     return float(np.mean([a.elapsed_time(b) for a, b in evs]))
 
 
-def cpu_baseline(sc, L, seconds, k0):
+def host_threads():
+    """Threads for the oracle: the CPUs this process may run on (at most 16,
+    the host share a one-GPU job gets on the GPU machines), and what nproc
+    reports."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return max(1, min(16, avail)), avail, os.cpu_count() or 1
+
+
+def cpu_baseline(sc, L, seconds, k0, n=256, label="the same scene and parameters"):
     """The oracle as it stands on this host's cores, on a bounded sample of the
     same workload: a subset of the chains for a few steps."""
     import oracle
-    nthreads = max(1, min(16, os.cpu_count() or 1))
+    nthreads, avail, nproc = host_threads()
     S = oracle.Scene(sc)
-    n = 256
     C = oracle.Chains.scene(S, L, n, seed=1, k0=k0)
     C.init(nthreads=nthreads)
     t0 = time.perf_counter()
@@ -325,8 +358,9 @@ def cpu_baseline(sc, L, seconds, k0):
     C.step(steps, nthreads=nthreads)
     dt = time.perf_counter() - t0
     return dict(value=n * steps / dt, unit="chain-steps/s", cores=nthreads, kind="oracle",
-                sample=f"{n} chains x {steps} evolve steps of the same scene and parameters (FP64 oracle, "
-                       f"{dt:.1f} s)")
+                sample=f"{n} chains x {steps} evolve steps of {label} (FP64 oracle, {dt:.1f} s, "
+                       f"{nthreads} threads; {avail} CPUs available to the process, nproc {nproc})",
+                host_cpus_available=avail, nproc=nproc)
 
 
 def run_config(a, torch, dr, inputs):
@@ -406,10 +440,323 @@ def run_config(a, torch, dr, inputs):
     print(json.dumps(res))
 
 
+def mrse_split(img, r1, r2):
+    """MRSE of img against the mean R of two independent path-traced
+    references r1, r2, with the references' own noise subtracted: the
+    expected squared difference of img and R is img's own error plus var(R),
+    and (r1 - r2)/2 has exactly var(R) as its expected square (split
+    halves).  Returns (corrected, raw, reference-noise term)."""
+    R = 0.5 * (r1 + r2)
+    den = R ** 2 + 1e-2
+    raw = float((((img - R) ** 2) / den).mean())
+    noise = float(((0.25 * (r1 - r2) ** 2) / den).mean())
+    return raw - noise, raw, noise
+
+
+class Refs:
+    """Split-half path-traced references of frames of the camera path,
+    rendered once and shared by every loop that is scored."""
+
+    def __init__(self, torch, scene, sc, L, spp, cams):
+        self.torch, self.scene, self.sc, self.L, self.spp, self.cams = torch, scene, sc, L, spp, cams
+        self.cache = {}
+
+    def get(self, f):
+        if f not in self.cache:
+            self.scene.set_camera(self.cams[f])
+            r1 = self.scene.pt_render(self.L, 100000 + f, self.spp)
+            r2 = self.scene.pt_render(self.L, 200000 + f, self.spp)
+            self.torch.cuda.synchronize()
+            self.cache[f] = (r1.cpu().numpy().astype(np.float64), r2.cpu().numpy().astype(np.float64))
+        return self.cache[f]
+
+
+def realtime_loop(torch, dr, scene, cams, N, L, K, W, mode, frame_steps=None, refs=None, mrse_frames=(),
+                  seed=2024, budget_ms=33.3, tune=True):
+    """The real-time loop: one captured frame graph (re-initialise for the
+    new camera, n evolve steps, resolve), replayed once per displayed frame
+    along the camera path.  n = frame_steps, or as many steps as fit the
+    frame budget after the re-initialisation and the resolve (at least 1).
+    Everything runs on one stream of its own (the library calls take torch's
+    current stream)."""
+    stream = torch.cuda.Stream()
+    img = torch.zeros((3, scene.W * scene.H), device="cuda", dtype=torch.float32)
+    scene.set_camera(cams[0])
+    tuned = None
+    with torch.cuda.stream(stream):
+        ch = dr.Chains(scene, N, L, seed, mode=mode)
+        if tune and mode == dr.DR_MODE_FUSED:
+            # the launch autotuner on the live chains (they are re-initialised next)
+            from paper_2605_08916_amd import autotune
+            t = autotune.tune(ch, reps=2, use_cache=False, per_launch=frame_steps or 1, restore=False,
+                              keep_within=0.03)
+            tuned = {"cfg": t["cfg"], "ms_per_step": t["ms"], "default_ms_per_step": t["current_ms"],
+                     "candidates": len(t["sweep"])}
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        for rep in range(2):  # the second pass is the calibration
+            ev[0].record(stream)
+            ch.reinit(1 + rep)
+            ev[1].record(stream)
+            ch.step(1)
+            ev[2].record(stream)
+            ch.resolve(img)
+            ev[3].record(stream)
+            stream.synchronize()
+        reinit_ms, step_ms, resolve_ms = (ev[i].elapsed_time(ev[i + 1]) for i in range(3))
+        n = frame_steps or max(1, int((budget_ms - reinit_ms - resolve_ms) / step_ms))
+        frame = ch.capture_frame(n, True, img, stream)
+    for i in range(W):
+        scene.set_camera(cams[i % len(cams)])
+        frame.launch(stream)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    t0 = time.perf_counter()
+    for i in range(K):
+        scene.set_camera(cams[(W + i) % len(cams)])   # waits for the frame in flight
+        evs[i][0].record(stream)
+        frame.launch(stream)
+        evs[i][1].record(stream)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    fms = [x.elapsed_time(y) for x, y in evs]
+    out = {"chains": N, "steps_per_frame": n, "frames": K, "wall_s": wall,
+           "ms_per_frame": wall * 1e3 / K, "gpu_ms_per_frame_median": float(np.median(fms)),
+           "gpu_ms_per_frame_max": float(np.max(fms)),
+           "chain_steps_per_s": N * n * K / wall, "evaluations_per_s": N * (n + 1) * K / wall,
+           "calibration_ms": {"reinit": reinit_ms, "step": step_ms, "resolve": resolve_ms},
+           "within_budget": bool(np.max(fms) <= budget_ms), "autotune": tuned}
+    if refs is not None and mrse_frames:
+        per = []
+        for f in mrse_frames:
+            r1, r2 = refs.get(f)
+            scene.set_camera(cams[f])
+            frame.launch(stream)
+            stream.synchronize()
+            im = img.cpu().numpy().astype(np.float64)
+            m, raw, noise = mrse_split(im, r1, r2)
+            per.append({"frame": f, "mrse": m, "mrse_raw": raw, "reference_noise": noise})
+        out["mrse_per_frame"] = per
+        out["mrse_mean"] = float(np.mean([p["mrse"] for p in per]))
+    frame.close()
+    return out, ch, stream
+
+
+def realtime_line(a, torch, dr, inputs):
+    """The default JSON line: the real-time loop on the 2M-triangle interior
+    at 1920x1080 with 4,194,304 chains."""
+    fac, L, N_def = inputs.CONFIGS["interior"]
+    N = a.chains or a.config_chains or N_def
+    d = 4 * (L - 1)
+    sc = fac()
+    scene = dr.Scene(sc)
+    cams = [inputs.camera_path(sc, f) for f in range(60)]
+    K, W = max(1, a.steps), max(0, a.warmup)
+    mrse_frames = [] if a.no_mrse else list(range(0, 60, 4)) + [59]
+    refs = None if a.no_mrse else Refs(torch, scene, sc, L, 32, cams)
+
+    rt, ch, stream = realtime_loop(torch, dr, scene, cams, N, L, K, W, dr.DR_MODE_FUSED, a.frame_steps, refs,
+                                   mrse_frames, tune=not a.no_tune)
+    n = rt["steps_per_frame"]
+    # steady-state evolve rate of the same chains (no re-initialisation):
+    # frames of 4 steps + resolve
+    scene.set_camera(cams[0])
+    with torch.cuda.stream(stream):
+        ch.reinit(3)
+        ms_ss, _, _ = time_steps(ch, torch, 12, 4, 4)
+        # the dominant kernel: the evolve launch of the frame, n steps per launch
+        ms_launch = time_kernel_only(ch, torch, 3, n)
+        # counters pass (not timed): rays and traversal work per chain-step
+        rays, nodes, tris, adj = traversal_work(ch, warm=0, n=1)
+        launch_cfg = ch.get_launch()
+        k0 = ch.read_state()["k0"]
+    torch.cuda.synchronize()
+    ch.close()
+
+    bytes_step = alg_bytes_per_chain_step(rays, nodes, tris, d, L)
+    achieved = bytes_step * N * n / (ms_launch * 1e-3) / 1e9
+    traffic = read_traffic("interior", N, n)
+    counters = read_counters("interior", N, n)
+    hbm_copy = achievable_bandwidth(torch)
+    res = {
+        "metric": "chain-steps/s (f+∇log f) and MRSE at 33 ms/frame, fused vs plain",
+        "value": rt["chain_steps_per_s"],
+        "unit": "chain-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": rt["ms_per_frame"],
+        "step_is": "one displayed frame of the real-time loop: re-initialise (camera change) + "
+                   f"{n} evolve step(s) + resolve, one captured HIP graph",
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "realtime_loop_procedural_interior_2M_tris_1920x1080_L8_d28_4194304chains",
+                   "triangles": int(sc["indices"].shape[0]), "width": scene.W, "height": scene.H, "path_len": L,
+                   "chains": N, "stddev": 5e-3, "dt": 1e-5, "gamma": 0.5, "m": 64, "form": "fused",
+                   "frame_budget_ms": 33.3, "camera_path_frames": 60, "launch": launch_cfg,
+                   "scene": scene.stats()},
+        "realtime": rt,
+        "steady_state_evolve": {"value": N / (ms_ss * 1e-3), "ms_per_step": ms_ss,
+                                "issue": "frames of dr_step(4) + resolve, no re-initialisation"},
+        "rays_per_s": rays * rt["chain_steps_per_s"],
+        "per_chain_step": {"rays": rays, "node_visits": nodes, "tri_tests": tris, "adjoint_fraction": adj,
+                           "alg_bytes": bytes_step},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "hbm_measured_GBs": None if traffic is None else traffic / (ms_launch * 1e-3) / 1e9,
+                     "achievable_copy_GBs": hbm_copy, "frac_of_achievable": achieved / hbm_copy,
+                     "l2_hit_rate": counters.get("l2_hit_rate"), "valu_issue_frac": counters.get("valu_issue_frac"),
+                     "alg_bytes_per_launch": bytes_step * N * n,
+                     "kernel": f"k_step_fused{'_pair' if launch_cfg['lanes_per_chain'] == 2 else ''}<{L}, false>",
+                     "launch_ms": ms_launch, "steps_per_launch": n,
+                     "note": "achieved = algorithmic bytes / launch time; most node and triangle bytes are "
+                             "served by the L2 and the MALL, hbm_measured_GBs is what reaches HBM"},
+    }
+    # ---- plain multi-kernel form: the same frames with the same step count
+    # (identical decisions from identical streams, so the same image: the
+    # frame-time ratio is the speed ratio at equal MRSE)
+    if not a.no_plain:
+        pr, cp, _ = realtime_loop(torch, dr, scene, cams, N, L, min(K, 4), 1, dr.DR_MODE_PLAIN, n, refs,
+                                  mrse_frames[:2])
+        cp.close()
+        res["plain"] = pr
+        res["fused_over_plain"] = pr["ms_per_frame"] / rt["ms_per_frame"]
+    # ---- equal-time path tracing: the samples per pixel that fit 33.3 ms
+    if refs is not None:
+        scene.set_camera(cams[0])
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        scene.pt_render(L, 5, 1)
+        e0.record()
+        scene.pt_render(L, 5, 1)
+        e1.record()
+        torch.cuda.synchronize()
+        spp = max(1, int(33.3 / e0.elapsed_time(e1)))
+        pm = []
+        for f in mrse_frames[:4]:
+            scene.set_camera(cams[f])
+            e0.record()
+            im = scene.pt_render(L, 900 + f, spp)
+            e1.record()
+            torch.cuda.synchronize()
+            r1, r2 = refs.get(f)
+            pm.append({"frame": f, "mrse": mrse_split(im.cpu().numpy().astype(np.float64), r1, r2)[0],
+                       "frame_ms": e0.elapsed_time(e1)})
+        res["pt_equal_time_33ms"] = {"spp": spp, "frames": pm, "mrse_mean": float(np.mean([p["mrse"] for p in pm]))}
+        res["mrse_reference"] = ("independent path tracing, two 32-spp halves per frame (seeds 100000+f, "
+                                 "200000+f); MRSE against their mean minus the halves' own noise")
+    # ---- the same loop with 1,048,576 chains (one GPU's share at 4 GPUs)
+    if not a.no_secondary and N > (1 << 20):
+        r1m, c1, _ = realtime_loop(torch, dr, scene, cams, 1 << 20, L, min(K, 10), 2, dr.DR_MODE_FUSED, None, refs,
+                                   mrse_frames, tune=not a.no_tune)
+        c1.close()
+        res["realtime_1M_chains"] = r1m
+    if not a.no_secondary:
+        res["procedural_spheres_53k"] = spheres_line(a, torch, dr, inputs, secondary=True)
+    if not a.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(sc, L, a.cpu_seconds, k0, n=256,
+                                           label="the interior scene (2,048,020 triangles, L = 8) with the same "
+                                                 "parameters")
+    scene.close()
+    return res
+
+
+def spheres_line(a, torch, dr, inputs, secondary=False):
+    """The procedural 53k-triangle scene (512x512, L = 8, 65,536 chains):
+    evolve steps in frames of F steps + resolve, fused and plain forms; with
+    secondary=False the full line (roofline, chain-count scaling, MRSE at
+    33 ms, equal-time path tracing, oracle baseline)."""
+    sc = inputs.procedural_spheres(seed=1)
+    L, N = 8, (a.chains if (a.chains and not secondary) else 65536)
+    d = 4 * (L - 1)
+    seed = 2024
+    scene = dr.Scene(sc)
+    F = max(1, a.steps_per_frame)
+    steps = max(16, a.steps) if secondary else a.steps
+    ch = dr.Chains(scene, N, L, seed, mode=dr.DR_MODE_FUSED)
+    torch.cuda.synchronize()
+    ms_fused, steps_done, ms_median = time_steps(ch, torch, steps, a.warmup, F)
+    value = N / (ms_fused * 1e-3)
+    launch_cfg = ch.get_launch()
+    rays, nodes, tris, adj = traversal_work(ch, warm=0, n=4)
+    out = {"workload": "procedural_spheres_53k_tris_512x512_L8_d28_65536chains", "value": value,
+           "unit": "chain-steps/s", "ms_per_step": ms_fused, "steps": steps_done, "steps_per_frame": F,
+           "rays_per_s": rays * value, "per_chain_step": {"rays": rays, "node_visits": nodes, "tri_tests": tris,
+                                                          "adjoint_fraction": adj}, "launch": launch_cfg}
+    if not a.no_plain:
+        cp = dr.Chains(scene, N, L, seed, mode=dr.DR_MODE_PLAIN)
+        ms_plain, _, _ = time_steps(cp, torch, max(2 * F, steps // 2), a.warmup, F)
+        out["plain"] = {"value": N / (ms_plain * 1e-3), "ms_per_step": ms_plain}
+        out["fused_over_plain"] = ms_plain / ms_fused
+        cp.close()
+    if secondary:
+        ch.close()
+        scene.close()
+        return out
+    # full line (--headline-spheres)
+    ms_single, _, _ = time_steps(ch, torch, max(8, a.steps // 4), 2, 1)
+    ms_launch = time_kernel_only(ch, torch, max(4, a.steps // (4 * F)), F)
+    k0 = ch.read_state()["k0"]
+    bytes_step = alg_bytes_per_chain_step(rays, nodes, tris, d, L)
+    achieved = bytes_step * N * F / (ms_launch * 1e-3) / 1e9
+    traffic = read_traffic("spheres", N, F)
+    counters = read_counters("spheres", N, F)
+    hbm_copy = achievable_bandwidth(torch)
+    res = {
+        "metric": "chain-steps/s (f+∇log f) and MRSE at 33 ms/frame, fused vs plain",
+        "value": value, "unit": "chain-steps/s", "n_gpus": 1, "steps": steps_done, "warmup": a.warmup,
+        "ms_per_step": ms_fused, "ms_per_step_median_frame": ms_median, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": out["workload"], "triangles": int(sc["indices"].shape[0]), "width": 512,
+                   "height": 512, "path_len": L, "chains": N, "stddev": 5e-3, "dt": 1e-5, "gamma": 0.5, "m": 64,
+                   "form": "fused", "steps_per_frame": F, "launch": launch_cfg},
+        "single_step_dispatch": {"value": N / (ms_single * 1e-3), "ms_per_step": ms_single},
+        "rays_per_s": out["rays_per_s"],
+        "per_chain_step": dict(out["per_chain_step"], alg_bytes=bytes_step),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "hbm_measured_GBs": None if traffic is None else traffic / (ms_launch * 1e-3) / 1e9,
+                     "achievable_copy_GBs": hbm_copy, "frac_of_achievable": achieved / hbm_copy,
+                     "l2_hit_rate": counters.get("l2_hit_rate"), "valu_issue_frac": counters.get("valu_issue_frac"),
+                     "traffic_unit": "HBM bytes per launch", "alg_bytes_per_launch": bytes_step * N * F,
+                     "kernel": f"k_step_fused{'_pair' if launch_cfg['lanes_per_chain'] == 2 else ''}<{L}, false>",
+                     "launch_ms": ms_launch, "steps_per_launch": F},
+        "chain_count_scaling": [] if a.no_scaling else chain_count_scaling(torch, dr, scene, L, F, hbm_copy),
+    }
+    for k in ("plain", "fused_over_plain"):
+        if k in out:
+            res[k] = out[k]
+    if not a.no_mrse:
+        ref = scene.pt_render(L, 777, 256)
+        torch.cuda.synchronize()
+        ref = ref.cpu().numpy().astype(np.float64)
+        res["mrse_33ms"] = dict(frame_mrse(ch, torch, ms_fused, ref),
+                                reference="independent path tracing, 256 spp per pixel (seed 777)")
+    ch.close()
+    if not a.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(sc, L, a.cpu_seconds, k0)
+    scene.close()
+    return res
+
+
 def main():
     a = parse()
     if a.traffic_summary:
-        write_traffic_summary(a.traffic_summary, a.chains, max(1, a.steps_per_frame))
+        if a.headline_spheres:
+            n = a.chains or 65536
+            F = max(1, a.steps_per_frame)
+            cmd = (f"python3 bench.py --headline-spheres --profile-only --steps 8 --warmup 2 --chains {n} "
+                   f"--steps-per-frame {F}")
+            write_traffic_summary(a.traffic_summary, "spheres", n, F, cmd)
+        else:
+            n = a.chains or (1 << 22)
+            F = a.frame_steps or 1
+            cmd = f"python3 bench.py --profile-only --steps 4 --warmup 1 --frame-steps {F}"
+            write_traffic_summary(a.traffic_summary, "interior", n, F, cmd)
         return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the chain step has no multi-GPU path in this "
@@ -420,22 +767,6 @@ def main():
     from paper_2605_08916_amd import dr, inputs
 
     torch.cuda.set_device(0)
-    if a.config and a.profile_only:
-        fac, L, N = inputs.CONFIGS[a.config]
-        scene = dr.Scene(fac())
-        sigma = None
-        if a.config == "spheres_1080p_L16":
-            sigma = torch.from_numpy(inputs.per_chain_sigma(4 * (L - 1), N, seed=4)).cuda()
-        ch = dr.Chains(scene, N, L, 2024, sigma=sigma)
-        F = max(1, a.steps_per_frame)
-        for _ in range(a.warmup + a.steps):
-            ch.step(F)
-        torch.cuda.synchronize()
-        print(json.dumps({"profile_only_launches": a.warmup + a.steps, "steps_per_launch": F, "config": a.config}))
-        return
-    if a.config:
-        run_config(a, torch, dr, inputs)
-        return
     if a.copy_probe:
         n = 1 << 28
         src = torch.ones(n, device="cuda", dtype=torch.float32)
@@ -445,132 +776,37 @@ def main():
         print(json.dumps({"copy_probe_bytes": 4 * n}))
         return
     if a.profile_only:
-        sc = inputs.procedural_spheres(seed=1)
+        if a.config:
+            fac, L, N = inputs.CONFIGS[a.config]
+            N = a.config_chains or N
+            F = max(1, a.steps_per_frame)
+        elif a.headline_spheres:
+            fac, L, N = inputs.CONFIGS["spheres"]
+            N = a.chains or N
+            F = max(1, a.steps_per_frame)
+        else:
+            fac, L, N = inputs.CONFIGS["interior"]
+            N = a.chains or N
+            F = a.frame_steps or 1
+        sc = fac()
         scene = dr.Scene(sc)
-        ch = dr.Chains(scene, a.chains, 8, 2024, mode=dr.DR_MODE_FUSED)
-        F = max(1, a.steps_per_frame)
+        sigma = None
+        if a.config == "spheres_1080p_L16":
+            sigma = torch.from_numpy(inputs.per_chain_sigma(4 * (L - 1), N, seed=4)).cuda()
+        ch = dr.Chains(scene, N, L, 2024, sigma=sigma)
         for _ in range(a.warmup + a.steps):
             ch.step(F)
         torch.cuda.synchronize()
-        print(json.dumps({"profile_only_launches": a.warmup + a.steps, "steps_per_launch": F}))
+        print(json.dumps({"profile_only_launches": a.warmup + a.steps, "steps_per_launch": F, "chains": N,
+                          "config": a.config or ("spheres" if a.headline_spheres else "interior")}))
         return
-    sc = inputs.procedural_spheres(seed=1)
-    L, N = 8, a.chains
-    d = 4 * (L - 1)
-    seed = 2024
-    scene = dr.Scene(sc)
-
-    F = max(1, a.steps_per_frame)
-    # ---- fused persistent form: throughput
-    ch = dr.Chains(scene, N, L, seed, mode=dr.DR_MODE_FUSED)
-    torch.cuda.synchronize()
-    ms_fused, steps_done, ms_median = time_steps(ch, torch, a.steps, a.warmup, F)
-    value = N / (ms_fused * 1e-3)
-    ms_single, _, _ = time_steps(ch, torch, max(8, a.steps // 4), 2, 1)
-    ms_launch = time_kernel_only(ch, torch, max(4, a.steps // (4 * F)), F)
-    ms_kernel = ms_launch / F
-    launch_cfg = ch.get_launch()
-    k0 = ch.read_state()["k0"]
-
-    # ---- counters pass (separate, not timed): rays and traversal work per chain-step
-    cc = dr.Chains(scene, N, L, seed + 1, mode=dr.DR_MODE_FUSED)
-    for _ in range(3):
-        cc.step(1)
-    cc.set_counters(True)
-    base = cc.stats()
-    nstat = 5
-    cc.step(nstat)
-    st = cc.stats()
-    cc.set_counters(False)
-    csteps = st["chain_steps"] - base["chain_steps"]
-    rays = (st["rays"] - base["rays"]) / csteps
-    nodes = (st["node_visits"] - base["node_visits"]) / csteps
-    tris = (st["tri_tests"] - base["tri_tests"]) / csteps
-    adj = (st["adjoints"] - base["adjoints"]) / csteps
-    cc.close()
-
-    bytes_step = alg_bytes_per_chain_step(rays, nodes, tris, d, L)
-    achieved = bytes_step * N * F / (ms_launch * 1e-3) / 1e9
-    traffic = read_traffic(N, F)
-    counters = read_counters(N, F)
-    hbm_copy = achievable_bandwidth(torch)
-    scaling_n = [] if a.no_scaling else chain_count_scaling(torch, dr, scene, L, F, hbm_copy)
-
-    res = {
-        "metric": "chain-steps/s (f+∇log f) and MRSE at 33 ms/frame, fused vs plain",
-        "value": value,
-        "unit": "chain-steps/s",
-        "n_gpus": 1,
-        "steps": steps_done,
-        "warmup": a.warmup,
-        "ms_per_step": ms_fused,
-        "ms_per_step_median_frame": ms_median,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "procedural_spheres_53k_tris_512x512_L8_d28_65536chains",
-                   "triangles": int(sc["indices"].shape[0]), "width": 512, "height": 512, "path_len": L,
-                   "chains": N, "stddev": 5e-3, "dt": 1e-5, "gamma": 0.5, "m": 64, "form": "fused",
-                   "steps_per_frame": F, "launch": launch_cfg},
-        "single_step_dispatch": {"value": N / (ms_single * 1e-3), "ms_per_step": ms_single},
-        "rays_per_s": rays * value,
-        "per_chain_step": {"rays": rays, "node_visits": nodes, "tri_tests": tris, "adjoint_fraction": adj,
-                           "alg_bytes": bytes_step},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "achievable_copy_GBs": hbm_copy, "frac_of_achievable": achieved / hbm_copy,
-                     "l2_hit_rate": counters.get("l2_hit_rate"), "valu_issue_frac": counters.get("valu_issue_frac"),
-                     "traffic_unit": "HBM bytes per launch", "alg_bytes_per_launch": bytes_step * N * F,
-                     "kernel": f"k_step_fused{'_pair' if launch_cfg['lanes_per_chain'] == 2 else ''}<{L}, false>",
-                     "launch_ms": ms_launch, "steps_per_launch": F},
-        "chain_count_scaling": scaling_n,
-    }
-
-    ref = None
-    if not a.no_mrse:
-        ref = scene.pt_render(L, 777, 256)
-        torch.cuda.synchronize()
-        ref = ref.cpu().numpy().astype(np.float64)
-
-    # ---- plain multi-kernel form on the same workload
-    if not a.no_plain:
-        cp = dr.Chains(scene, N, L, seed, mode=dr.DR_MODE_PLAIN)
-        ms_plain, _, _ = time_steps(cp, torch, max(2 * F, a.steps // 2), a.warmup, F)
-        res["plain"] = {"value": N / (ms_plain * 1e-3), "ms_per_step": ms_plain}
-        res["fused_over_plain"] = ms_plain / ms_fused
-        if ref is not None:
-            # both forms make the same decisions from the same streams, so at
-            # equal step counts they give the same image; in a 33 ms frame the
-            # plain form fits fewer steps
-            res["plain"]["mrse_33ms"] = frame_mrse(cp, torch, ms_plain, ref)
-        cp.close()
-
-    # ---- MRSE after a 33.3 ms frame of fused steps (re-init + steps + resolve)
-    if ref is not None:
-        res["mrse_33ms"] = dict(frame_mrse(ch, torch, ms_fused, ref),
-                                reference="independent path tracing, 256 spp per pixel (seed 777)")
-        # independent path tracing given the same 33.3 ms (spp that fit), for context
-        stream = torch.cuda.current_stream()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        scene.pt_render(L, 5, 1)
-        e0.record(stream)
-        scene.pt_render(L, 5, 4)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        spp = max(1, int(33.3 / (e0.elapsed_time(e1) / 4)))
-        e0.record(stream)
-        img = scene.pt_render(L, 99, spp)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        res["pt_equal_time_33ms"] = {"spp": spp, "frame_ms": e0.elapsed_time(e1),
-                                     "mrse": mrse(img.cpu().numpy().astype(np.float64), ref)}
-    ch.close()
-
-    if not a.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(sc, L, a.cpu_seconds, k0)
-    print(json.dumps(res))
+    if a.config and a.config != "interior":
+        run_config(a, torch, dr, inputs)
+        return
+    if a.headline_spheres:
+        print(json.dumps(spheres_line(a, torch, dr, inputs)))
+        return
+    print(json.dumps(realtime_line(a, torch, dr, inputs)))
 
 
 if __name__ == "__main__":

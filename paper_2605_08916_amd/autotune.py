@@ -1,13 +1,20 @@
 """Launch-configuration autotuner for the fused persistent chain-step kernel.
 
-It sweeps the kernel form (straight-line or ray-refill), the threads per
+It searches the kernel form (straight-line or ray-refill), the threads per
 block, the resident blocks per compute unit of the persistent grid, the number
-of chains a lane takes per queue pop, lanes per chain, the ordering of chains
-(none, by path length, by screen tile) and the refill thresholds, times
-`dr_step(n)` (n steps per launch, as the caller will issue them) for each
-candidate with HIP events on the launch stream, and caches the fastest configuration in a JSON file keyed by device name, path
-length, chain count and triangle count.  The chain state is saved before and
-restored after the sweep, so tuning does not advance the chains.
+of consecutive chains a lane (or lane pair) takes per pop of the device work
+queue (the queue's batch depth), lanes per chain, the ordering of chains
+(none, by path length, by screen tile), the number of top BVH nodes cached in
+LDS and the refill thresholds.  Each candidate is timed on the live chain set
+as `dr_step(n)` launches (n steps per launch, as the caller will issue them)
+with HIP events on the launch stream.  The default search is staged
+(coordinate descent: block x blocks per CU first, then each other dimension
+in turn from the best so far, about 30 candidates); `exhaustive=True` times
+the full product.  The fastest configuration is cached in a JSON file keyed
+by device name, path length, chain count, triangle count and steps per
+launch.  The chain state is saved before and restored after the sweep
+(unless the caller re-initialises the chains anyway), so tuning does not
+advance the chains.
 """
 from __future__ import annotations
 
@@ -20,7 +27,8 @@ CACHE = os.environ.get("DR_AUTOTUNE_CACHE", os.path.join(os.path.expanduser("~")
 
 BLOCKS = (64, 128, 256)
 BLOCKS_PER_CU = (1, 2, 3, 4, 6, 8)
-GRABS = (1,)
+GRABS = (1, 2, 4)          # chains per lane per queue pop
+NODE_CACHES = (dr.DR_NODE_CACHE_AUTO, 1, 21, 85)
 LANES = (1, 2)
 # chain ordering before a launch: (sort_by_length, sort_by_tile), 1 on, 2 off
 ORDERS = ((2, 2), (1, 2), (2, 1))
@@ -28,8 +36,9 @@ REFILL_PCTS = ((50, 50),)  # (event, advance) thresholds of the ray-refill form
 
 
 def candidates():
-    """Every launch configuration the sweep times: the straight-line form
-    over block x blocks-per-CU x grab x lanes x ordering, and the ray-refill
+    """Every launch configuration the exhaustive sweep times: the
+    straight-line form over block x blocks-per-CU x grab x lanes x node cache
+    x ordering, and the ray-refill
     form (one lane per chain) over block x blocks-per-CU x ordering x
     thresholds."""
     out = []
@@ -38,8 +47,9 @@ def candidates():
             for by_len, by_tile in ORDERS:
                 for grab in GRABS:
                     for lanes in LANES:
-                        out.append(dict(block=block, blocks_per_cu=bpc, grab=grab, lanes_per_chain=lanes,
-                                        sort_by_length=by_len, sort_by_tile=by_tile, refill=2))
+                        for nc in NODE_CACHES:
+                            out.append(dict(block=block, blocks_per_cu=bpc, grab=grab, lanes_per_chain=lanes,
+                                            sort_by_length=by_len, sort_by_tile=by_tile, refill=2, node_cache=nc))
                 for ev, adv in REFILL_PCTS:
                     out.append(dict(block=block, blocks_per_cu=bpc, sort_by_length=by_len, sort_by_tile=by_tile,
                                     refill=1, refill_event_pct=ev, refill_advance_pct=adv))
@@ -73,29 +83,69 @@ def _time(ch: "dr.Chains", reps: int, per_launch: int) -> float:
     return e0.elapsed_time(e1) / (reps * per_launch)
 
 
-def tune(ch: "dr.Chains", reps: int = 3, use_cache: bool = True, verbose: bool = False, per_launch: int = 8) -> dict:
+def staged_candidates(ch: "dr.Chains", timer) -> list:
+    """Coordinate descent over the launch dimensions; timer(cfg) -> ms per
+    step.  Returns [(ms, cfg)] of every configuration timed."""
+    results = []
+
+    def run(cfgs):
+        for c in cfgs:
+            results.append((timer(c), c))
+        return min(results, key=lambda r: r[0])[1]
+
+    base = dict(sort_by_length=2, sort_by_tile=2, refill=2, grab=1, node_cache=dr.DR_NODE_CACHE_AUTO)
+    best = run([dict(base, block=b, blocks_per_cu=k) for b in BLOCKS for k in BLOCKS_PER_CU])
+    best = run([dict(best, lanes_per_chain=n) for n in LANES])
+    best = run([dict(best, sort_by_length=a, sort_by_tile=b) for a, b in ORDERS[1:]])
+    best = run([dict(best, grab=g) for g in GRABS[1:]])
+    best = run([dict(best, node_cache=n) for n in NODE_CACHES[1:]])
+    run([dict(best, refill=1, refill_event_pct=ev, refill_advance_pct=adv) for ev, adv in REFILL_PCTS])
+    return results
+
+
+def tune(ch: "dr.Chains", reps: int = 3, use_cache: bool = True, verbose: bool = False, per_launch: int = 8,
+         exhaustive: bool = False, restore: bool = True, keep_within: float = 0.0) -> dict:
     """Pick and apply the fastest launch configuration for this chain set
-    (time per chain-step with `per_launch` steps per launch)."""
+    (time per chain-step with `per_launch` steps per launch).  restore=False
+    skips saving and restoring the chain state (for callers that
+    re-initialise the chains afterwards).  keep_within: keep the chain set's
+    current configuration unless the best is faster by more than this
+    fraction (timing noise does not flip the choice)."""
     key = _key(ch) + f"|F{per_launch}"
     cache = _load() if use_cache else {}
     if key in cache:
         cfg = cache[key]["cfg"]
         ch.set_launch(**cfg)
         return cache[key]
-    snap = ch.read_state()
-    results = []
-    for cfg in candidates():
-        ch.set_launch(**cfg)
+    snap = ch.read_state() if restore else None
+    full = dict(sort_by_length=2, sort_by_tile=2, refill=2, grab=1, node_cache=dr.DR_NODE_CACHE_AUTO,
+                refill_event_pct=50, refill_advance_pct=50)
+    flags = ("sort_by_length", "sort_by_tile", "refill")  # read back as 1/0, requested as 1 on / 2 off
+    current = {k: ((1 if v else 2) if k in flags else v) for k, v in ch.get_launch().items()}
+    ch.set_launch(**current)
+    current_ms = _time(ch, reps, per_launch)
+
+    def timer(cfg):
+        ch.set_launch(**dict(full, **cfg))
         ms = _time(ch, reps, per_launch)
-        results.append((ms, cfg))
         if verbose:
             print(f"autotune {cfg}: {ms:.3f} ms/step")
+        return ms
+
+    if exhaustive:
+        results = [(timer(c), c) for c in candidates()]
+    else:
+        results = staged_candidates(ch, timer)
     results.sort(key=lambda r: r[0])
     best_ms, best = results[0]
-    ch.set_launch(**best)
-    ch.write_state(x=snap["x"], score=snap["score"], killed=snap["killed"], accum=snap["accum"], step=snap["step"],
-                   tour_count=snap["tour_count"], k0=snap["k0"])
-    entry = {"cfg": best, "ms": best_ms, "sweep": [(ms, c) for ms, c in results]}
+    if best_ms >= current_ms * (1.0 - keep_within):
+        best_ms, best = current_ms, current
+    ch.set_launch(**dict(full, **best))
+    if snap is not None:
+        ch.write_state(x=snap["x"], score=snap["score"], killed=snap["killed"], accum=snap["accum"],
+                       step=snap["step"], tour_count=snap["tour_count"], k0=snap["k0"])
+    entry = {"cfg": dict(full, **best), "ms": best_ms, "current_ms": current_ms,
+             "sweep": [(ms, c) for ms, c in results]}
     cache[key] = entry
     try:
         os.makedirs(os.path.dirname(CACHE), exist_ok=True)
