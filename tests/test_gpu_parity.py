@@ -4,9 +4,10 @@ Tolerances follow from FP32 arithmetic on the device against FP64 on the
 host.  Every value of a smooth quantity (f, log p, p, f/p, the holding
 weight, each score coordinate, x') is held to 1e-4 relative, except where
 the oracle itself shows that the sample is ill-conditioned for FP32: its
-value moves by more than 1e-4 / COND_C when every coordinate of the point is
-perturbed by one FP32 ulp (`_sens`).  Such a sample may err by up to COND_C
-times that sensitivity, and by no more.  Decisions (kill, pixel) are
+value moves by more than 1e-4 / (16 L) when every coordinate of the point is
+perturbed by one FP32 ulp (`_sens`).  Such a sample may err by up to 16 L
+times that sensitivity (the roundings along its path, `_cond`), and by no
+more.  Decisions (kill, pixel) are
 identical except where the FP64 value lies within the FP32 rounding band of
 the threshold.  Paths whose discrete choices (hit triangle, light,
 visibility, lobe) differ between the two precisions are excluded from value
@@ -58,11 +59,17 @@ def _rel(a, b, floor):
     return np.abs(a - b) / np.maximum(np.abs(b), floor)
 
 
-# The device's FP32 path evaluation rounds at about a dozen stages per vertex
-# (ray direction, hit point, light vector, r^2, cosines, throughput), each an
-# error of the size a one-ulp perturbation of the point causes; a value may
-# err by this many times the sensitivity `_sens` measures.
-COND_C = 8.0
+# First-order FP32 error bound used by every parity check: the device's path
+# evaluation rounds at about 16 stages per vertex (ray direction, hit point,
+# light vector, r^2 and its root, cosines, BSDF value, throughput), over the
+# camera ray and at most L - 1 vertices, and each rounding moves the result
+# by about what a one-ulp perturbation of the point does (`_sens`); so a value
+# may err by 16 L times that sensitivity (and the score additionally by 16 L
+# unit roundoffs of its condition measure, `_score_within`).
+def _cond(L):
+    return 16.0 * L
+
+
 TOL = 1e-4
 ULP = 2.0 ** -24
 
@@ -90,11 +97,9 @@ def _fop(f, p):
 
 def _round_allow(L):
     """Multiple of the unit roundoff times the score's condition measure that
-    the reverse sweep may err by: a dependency path from a coordinate to p
-    passes about 16 roundings per vertex (ray direction, hit point, light
-    vector, r^2 and its root, cosines, BSDF value, throughput), at most L - 1
-    vertices plus the camera ray."""
-    return 16.0 * L * 2.0 ** -24
+    the reverse sweep may err by (the roundings along a dependency path from
+    a coordinate to p, as in `_cond`)."""
+    return _cond(L) * 2.0 ** -24
 
 
 def _sens(O, L, u, K=6, seed=12345):
@@ -127,13 +132,13 @@ def _sens(O, L, u, K=6, seed=12345):
 
 def _score_within(name, g, go, sens, L):
     """Every score coordinate within TOL of its size (floored, `_coord_rel`),
-    or within COND_C times the point's sensitivity; plus the reverse sweep's
+    or within _cond(L) times the point's sensitivity; plus the reverse sweep's
     rounding, `_round_allow(L)` times the coordinate's condition measure
     (where terms cancel, FP32 keeps fewer digits of the sum)."""
     fl = np.maximum(1e-2 * np.abs(go).max(axis=1, keepdims=True), 1e-6)
     scale = np.maximum(np.abs(go), fl)
     err = np.abs(g - go) / scale
-    allow = np.maximum(TOL, COND_C * sens["g"])[:, None] + _round_allow(L) * sens["kappa"] / scale
+    allow = np.maximum(TOL, _cond(L) * sens["g"])[:, None] + _round_allow(L) * sens["kappa"] / scale
     bad = ~(err <= allow)
     beyond = err > TOL
     say(f"  {name}: max err {err.max():.2e}, beyond {TOL:g} {int(beyond.sum())} (within the conditioning "
@@ -148,18 +153,16 @@ def _score_within(name, g, go, sens, L):
                              f"{err.ravel()[i]} allowance {allow.ravel()[i]} " + " ".join(detail))
 
 
-def _within(name, err, sens):
-    """Every sample within TOL, or within COND_C times its sensitivity."""
+def _within(name, err, sens, L):
+    """Every sample within TOL, or within _cond(L) times its sensitivity."""
     err, sens = np.asarray(err, np.float64), np.asarray(sens, np.float64)
     if err.size == 0:
         return
-    if err.ndim == 2:  # per coordinate, against the sample's sensitivity
-        sens = np.broadcast_to(sens[:, None], err.shape)
-    allow = np.maximum(TOL, COND_C * sens)
+    allow = np.maximum(TOL, _cond(L) * sens)
     bad = ~(err <= allow)
     cond = (err > TOL) & ~bad
     say(f"  {name}: max err {err.max():.2e}, beyond {TOL:g} {int((err > TOL).sum())} "
-        f"(all within {COND_C:g} x sensitivity: {int(cond.sum())}), failing {int(bad.sum())}")
+        f"(within the conditioning allowance: {int(cond.sum())}), failing {int(bad.sum())}")
     if bad.any():
         i = np.argsort(-(err - allow).ravel())[:5]
         raise AssertionError(f"{name}: {int(bad.sum())} beyond the allowance; worst err {err.ravel()[i]} "
@@ -196,10 +199,10 @@ def _check_eval(O, L, u, dev, match, name=""):
     sens, (fo, po, go, _) = _sens(O, L, u)
     m = match
     fscale = max(1e-6, float(np.abs(fo).mean()))
-    _within(f"{name}f", _vec_rel(f[m], fo[m], 1e-3 * fscale), sens["f"][m])
+    _within(f"{name}f", _vec_rel(f[m], fo[m], 1e-3 * fscale), sens["f"][m], L)
     pos = m & (po > 1e-3 * po.mean())
     # |d log p| = |dp| / p: the relative error of p
-    _within(f"{name}log p", np.abs(logp[pos] - np.log(po[pos] + 1e-8)), sens["p"][pos])
+    _within(f"{name}log p", np.abs(logp[pos] - np.log(po[pos] + 1e-8)), sens["p"][pos], L)
     _score_within(f"{name}score", g[pos], go[pos], {k: v[pos] for k, v in sens.items()}, L)
     # p == 0 paths have a zero score on both sides
     zero = m & (po == 0)
@@ -355,7 +358,7 @@ def _compare_step(orc, sc, L, st, gs, os_, idx, seed, step0, k0, dt=1e-5, eps=1e
         # by the drift's factor (stddev^2/2 + gamma~) times the score error,
         # which the conditioning of that score bounds
         gx = np.abs(os_["score_x"]).max(axis=1)
-        allow_dx = (stddev ** 2 / 2 + dt * gamma / 2) * (COND_C * os_["score_x_sens"] * gx +
+        allow_dx = (stddev ** 2 / 2 + dt * gamma / 2) * (_cond(L) * os_["score_x_sens"] * gx +
                                                          _round_allow(L) * os_["score_x_kappa"])
         live = st["killed"][idx] == 0
         allow = TOL + np.where(live, allow_dx, 0.0)[None, :] / np.maximum(step, 5e-3)
@@ -383,15 +386,15 @@ def _compare_step(orc, sc, L, st, gs, os_, idx, seed, step0, k0, dt=1e-5, eps=1e
     assert kill_bad.sum() == 0
     m = match
     pscale = max(1e-6, float(os_["p"].mean()))
-    _within("p", _rel(gs["p"][m], os_["p"][m], 1e-3 * pscale), sens["p"][m])
+    _within("p", _rel(gs["p"][m], os_["p"][m], 1e-3 * pscale), sens["p"][m], L)
     fop_err = (np.abs(gs["f_over_p"][:, m] - os_["f_over_p"][:, m]) / np.maximum(1, np.abs(os_["f_over_p"][:, m]))).max(0)
-    _within("f/p", fop_err, sens["fop"][m])
+    _within("f/p", fop_err, sens["fop"][m], L)
     # w = dt/(1 + k dt) with k = k0/(p + eps): its error follows p's
     praw = np.abs(gs["p"][m] - os_["p"][m]) / np.maximum(os_["p"][m] + eps, 1e-30)
     werr = _rel(gs["weight"][m], os_["w"][m], 1e-30)
     assert np.all(werr <= 2 * praw + 1e-5), np.max(werr - 2 * praw)
     if len(idx) == gs["x"].shape[1] and np.array_equal(idx, np.arange(len(idx))):
-        _check_accum(gs, os_, sens, match, dt)
+        _check_accum(gs, os_, sens, match, dt, L)
     if check_score:
         live = m & (os_["killed"] == 0) & (gs["killed"] == 0) & (os_["p"] > 1e-3 * pscale)
         if not live.any():  # e.g. a single chain that was killed: no score to compare
@@ -400,7 +403,7 @@ def _compare_step(orc, sc, L, st, gs, os_, idx, seed, step0, k0, dt=1e-5, eps=1e
         _score_within("score", gg, go, {k: v[live] for k, v in sens.items()}, L)
 
 
-def _check_accum(gs, os_, sens, match, dt):
+def _check_accum(gs, os_, sens, match, dt, L):
     """The frame buffer after one step from an empty one, pixel by pixel: the
     device's sum of (w/dt) f/p times dt against the oracle's sum of w f/p.
     Each chain's splat may err by its allowances for f/p and for the weight
@@ -414,8 +417,8 @@ def _check_accum(gs, os_, sens, match, dt):
     live = os_["p"] > 0
     fop = np.abs(os_["f_over_p"])  # 3 x n
     w = os_["w"]
-    a_fop = np.maximum(TOL, COND_C * sens["fop"])
-    a_w = 2 * np.maximum(TOL, COND_C * sens["p"])
+    a_fop = np.maximum(TOL, _cond(L) * sens["fop"])
+    a_w = 2 * np.maximum(TOL, _cond(L) * sens["p"])
     err_c = w * (a_fop * np.maximum(1.0, fop.max(axis=0)) + a_w * fop.max(axis=0) + 1e-6)
     bound = np.bincount(pix[live], weights=err_c[live], minlength=npx)
     count = np.bincount(pix[live], minlength=npx)
@@ -969,7 +972,7 @@ def test_device_matches_stored_oracle_values(orc):
         sens, (fl, pl, gl, _) = _sens(orc.Scene(getattr(inputs, case["scene"])()), L, u64)
         # the stored values are the oracle's own at these points
         assert np.allclose(fl, fo, rtol=1e-12, atol=0) and np.allclose(gl, go, rtol=1e-9, atol=1e-12)
-        _within(f"{case['name']} f", _vec_rel(f, fo, 1e-3 * max(1e-6, np.abs(fo).mean())), sens["f"])
+        _within(f"{case['name']} f", _vec_rel(f, fo, 1e-3 * max(1e-6, np.abs(fo).mean())), sens["f"], L)
         live = po > 1e-3 * po.mean()
         _score_within(f"{case['name']} score", g[live], go[live], {k: v[live] for k, v in sens.items()}, L)
 
