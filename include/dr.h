@@ -342,6 +342,24 @@ dr_status dr_frame_destroy(dr_frame* f);
 dr_status dr_eval_logp_grad(dr_scene* s, uint32_t L, const float* u_dev, uint32_t n, float eps, float* f_dev,
                             float* logp_dev, float* grad_dev, uint32_t* rec_dev, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * evaluation as dr_eval_logp_grad, same arguments and results, with the
+ * scratch taken from a 16 MiB buffer the library holds in device memory on
+ * each GPU it runs on (until the process ends) instead of allocated per call.
+ * Calls no hipMalloc/hipFree or any other allocating routine.  With grad_dev
+ * the scratch holds 4 (L-1) n bytes of path records, so n (L-1) may be at
+ * most 4,194,304 (e.g. n <= 599,186 at L = 8); larger inputs are rejected
+ * with DR_ERR_INVALID_ARG before any device work (forward-only calls need
+ * 4 bytes and have no limit).  Every call on one GPU shares that GPU's
+ * buffer, which keeps the last call's contents: calls that overlap in time
+ * on one GPU (other streams, other threads) race, so the caller serialises
+ * them (one stream, or events between streams).  The buffer's device
+ * address is resolved on the first call on each device.  Asynchronous. */
+dr_status dr_eval_logp_grad_noalloc(dr_scene* s, uint32_t L, const float* u_dev, uint32_t n, float eps,
+                                    float* f_dev, float* logp_dev, float* grad_dev, uint32_t* rec_dev,
+                                    void* hip_stream);
+
 /* Independent path tracing: spp samples per pixel, u0 = (px + U)/W,
  * u1 = (py + U)/H, other coordinates U; img_dev = per-pixel mean of f
  * (3 x W*H planar, device).  Asynchronous. */

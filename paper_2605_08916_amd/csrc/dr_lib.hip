@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1287,6 +1288,33 @@ static size_t eval_scratch_bytes(uint32_t L, uint32_t n, bool grad) {
     return grad ? sizeof(uint32_t) * (L - 1) * (size_t)n : sizeof(uint32_t);
 }
 
+// Scratch of dr_eval_logp_grad_noalloc: a file-scope device array (each GPU
+// the library runs on holds its own copy until the process ends).  Host code
+// never passes the array's name to a kernel: it takes the array's device
+// address from hipGetSymbolAddress once per device (with that device
+// current) and passes that address.
+#define DR_NOALLOC_SCRATCH_BYTES (16u << 20)
+static __device__ __align__(256) uint32_t scratch[DR_NOALLOC_SCRATCH_BYTES / sizeof(uint32_t)];
+namespace {
+std::mutex g_scratch_mu;
+std::vector<uint32_t*> g_scratch_ptr;  // per device, nullptr until resolved
+}  // namespace
+
+static dr_status noalloc_scratch(int device, uint32_t** out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= device) g_scratch_ptr.resize((size_t)device + 1, nullptr);
+    if (!g_scratch_ptr[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(DR_ERR_DEVICE, std::string("dr_eval_logp_grad_noalloc: scratch address: ") +
+                                           hipGetErrorString(e));
+        g_scratch_ptr[device] = static_cast<uint32_t*>(ptr);
+    }
+    *out = g_scratch_ptr[device];
+    return DR_OK;
+}
+
 dr_status dr_eval_logp_grad(dr_scene* s, uint32_t L, const float* u_dev, uint32_t n, float eps, float* f_dev,
                             float* logp_dev, float* grad_dev, uint32_t* rec_dev, void* hip_stream) {
     if (!s || !u_dev) return fail(DR_ERR_INVALID_ARG, "dr_eval_logp_grad: null argument");
@@ -1310,6 +1338,27 @@ dr_status dr_eval_logp_grad(dr_scene* s, uint32_t L, const float* u_dev, uint32_
     if (hooks.alloc) dev_free(rs, rs_bytes, st, hooks);
     else (void)hipFreeAsync(rs, st);
     if (e != hipSuccess) return fail(DR_ERR_DEVICE, std::string("dr_eval_logp_grad: ") + hipGetErrorString(e));
+    g_err.clear();
+    return DR_OK;
+}
+
+dr_status dr_eval_logp_grad_noalloc(dr_scene* s, uint32_t L, const float* u_dev, uint32_t n, float eps, float* f_dev,
+                                    float* logp_dev, float* grad_dev, uint32_t* rec_dev, void* hip_stream) {
+    if (!s || !u_dev) return fail(DR_ERR_INVALID_ARG, "dr_eval_logp_grad_noalloc: null argument");
+    if (L < 2 || L > 16) return fail(DR_ERR_INVALID_ARG, "dr_eval_logp_grad_noalloc: L must be 2..16");
+    if (!(eps > 0)) return fail(DR_ERR_INVALID_ARG, "dr_eval_logp_grad_noalloc: eps must be > 0");
+    if (eval_scratch_bytes(L, n, grad_dev != nullptr) > DR_NOALLOC_SCRATCH_BYTES)
+        return fail(DR_ERR_INVALID_ARG, "dr_eval_logp_grad_noalloc: with a score, 4 (L-1) n bytes of scratch must fit "
+                                        "the library's 16 MiB");
+    if (n == 0) { g_err.clear(); return DR_OK; }
+    HIP_TRY(hipSetDevice(s->device));
+    (void)hipGetLastError();  // drop a stale error left by an earlier, unrelated call
+    uint32_t* rs = nullptr;
+    if (noalloc_scratch(s->device, &rs) != DR_OK) return DR_ERR_DEVICE;
+    enqueue_eval(s, L, u_dev, n, eps, f_dev, logp_dev, grad_dev, rec_dev, rs, (hipStream_t)hip_stream);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return fail(DR_ERR_DEVICE, std::string("dr_eval_logp_grad_noalloc: ") + hipGetErrorString(e));
     g_err.clear();
     return DR_OK;
 }

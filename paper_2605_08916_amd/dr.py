@@ -25,7 +25,7 @@ EXPORTED = [
     "dr_scene_destroy",
     "dr_chains_init", "dr_chains_reinit", "dr_step", "dr_resolve", "dr_image_read", "dr_chains_destroy",
     "dr_chains_read_state", "dr_chains_write_state", "dr_chains_set_record", "dr_chains_set_counters", "dr_stats",
-    "dr_chains_set_launch", "dr_chains_get_launch", "dr_eval_logp_grad", "dr_pt_render",
+    "dr_chains_set_launch", "dr_chains_get_launch", "dr_eval_logp_grad", "dr_eval_logp_grad_noalloc", "dr_pt_render",
     "dr_frame_capture", "dr_frame_launch", "dr_frame_destroy", "dr_mixture_run", "dr_mixture_step",
 ]
 
@@ -180,6 +180,7 @@ def lib():
         "dr_chains_set_launch": ([P, C.POINTER(dr_launch_cfg)], st),
         "dr_chains_get_launch": ([P, C.POINTER(dr_launch_cfg)], st),
         "dr_eval_logp_grad": ([P, C.c_uint32, P, C.c_uint32, C.c_float, P, P, P, P, P], st),
+        "dr_eval_logp_grad_noalloc": ([P, C.c_uint32, P, C.c_uint32, C.c_float, P, P, P, P, P], st),
         "dr_pt_render": ([P, C.c_uint32, C.c_uint64, C.c_uint32, P, P], st),
         "dr_frame_capture": ([P, C.c_uint32, C.c_int, P, P, pp], st),
         "dr_frame_launch": ([P, P], st),
@@ -336,6 +337,18 @@ class Scene:
         _check(lib().dr_eval_logp_grad(self.h, L, _dev_ptr(u), n, eps, _dev_ptr(f), _dev_ptr(logp), _dev_ptr(g),
                                        _dev_ptr(r), _stream(stream)))
         return f, logp, g, r
+
+    def eval_logp_grad_into(self, L: int, u, f, logp, grad=None, rec=None, eps: float = 1e-8, stream=None):
+        """dr_eval_logp_grad_noalloc: the same evaluation into caller-owned
+        CUDA tensors (f (n, 3), logp (n,), grad (n, d) or None, rec (n, L-1)
+        int32 or None), with the library's fixed scratch buffer."""
+        import torch
+        n = u.shape[0]
+        assert u.dtype == torch.float32 and u.is_cuda and u.is_contiguous() and u.shape[1] == 4 * (L - 1)
+        for t, shape in ((f, (n, 3)), (logp, (n,)), (grad, (n, 4 * (L - 1))), (rec, (n, L - 1))):
+            assert t is None or (t.is_cuda and t.is_contiguous() and tuple(t.shape) == shape)
+        _check(lib().dr_eval_logp_grad_noalloc(self.h, L, _dev_ptr(u), n, eps, _dev_ptr(f), _dev_ptr(logp),
+                                               _dev_ptr(grad), _dev_ptr(rec), _stream(stream)))
 
     def pt_render(self, L: int, seed: int, spp: int, stream=None):
         import torch
