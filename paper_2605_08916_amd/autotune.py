@@ -32,7 +32,7 @@ NODE_CACHES = (dr.DR_NODE_CACHE_AUTO, 1, 21, 85)
 LANES = (1, 2)
 # chain ordering before a launch: (sort_by_length, sort_by_tile), 1 on, 2 off
 ORDERS = ((2, 2), (1, 2), (2, 1))
-REFILL_PCTS = ((50, 50),)  # (event, advance) thresholds of the ray-refill form
+REFILL_PCTS = ((50, 50), (75, 50), (75, 75), (90, 75))  # (event, advance) thresholds of the ray-refill form
 
 
 def candidates():

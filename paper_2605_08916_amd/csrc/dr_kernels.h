@@ -350,8 +350,10 @@ __global__ void __launch_bounds__(256) k_step_sm(KParams P, DevScene S, KBufs B,
                     has_path = true;
                 }
             }
-        } else if (state == LS_TRACE) {
-            if (ray_step(S, q, stk, stride, ctr)) state = LS_EVENT;
+        } else {
+            uint64_t ml, mv;
+            ray_masks(q, state == LS_TRACE, ml, mv);
+            if (state == LS_TRACE && ray_step(S, q, stk, stride, ctr, ml, mv)) state = LS_EVENT;
         }
     }
     wave_add(&B.ctr[C_TOURS], kills);
@@ -487,8 +489,10 @@ __global__ void __launch_bounds__(256) k_eval_sm(DevScene S, const float* u, int
                 tracing = sm_event<L>(S, C, uu, P, q, R, ctr);
                 if (!tracing) item = -1;
             }
-        } else if (tracing) {
-            if (ray_step(S, q, stk, stride, ctr)) tracing = false;
+        } else {
+            uint64_t ml, mv;
+            ray_masks(q, tracing, ml, mv);
+            if (tracing && ray_step(S, q, stk, stride, ctr, ml, mv)) tracing = false;
         }
     }
 }

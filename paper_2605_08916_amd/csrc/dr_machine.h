@@ -22,19 +22,21 @@
 namespace dr {
 
 // Resumable ray query over (tmin, tmax): closest hit (ties in t to the lower
-// input triangle index) or, with anyhit, the first hit found.
+// input triangle index) or, with anyhit, the first hit found.  The traversal
+// is trace()'s speculative one: pleaf is the lane's pending leaf, tested in
+// the wavefront's leaf rounds.
 struct RayQ {
     V3 o, d;
     RaySlab rs;
     float tmax, bt;
     int best;
     uint32_t best_prim;
-    int node, sp;
-    bool anyhit;
+    int node, sp, pleaf;
+    bool anyhit, found;
 };
 
 // Starts a query; false when there is no ray (tmax <= tmin), which finishes
-// with no hit at once.
+// with no hit at once (node -1, nothing pending).
 __device__ __forceinline__ bool ray_begin(const DevScene& S, RayQ& q, V3 o, V3 d, float tmax, bool anyhit,
                                           Counters& ctr) {
     q.o = o;
@@ -45,21 +47,96 @@ __device__ __forceinline__ bool ray_begin(const DevScene& S, RayQ& q, V3 o, V3 d
     q.best_prim = 0xFFFFFFFFu;
     q.node = 0;
     q.sp = 0;
+    q.pleaf = 0;
     q.anyhit = anyhit;
-    if (!(tmax > S.tmin)) return false;
+    q.found = false;
+    if (!(tmax > S.tmin)) {
+        q.node = -1;
+        return false;
+    }
     q.rs = ray_slab(o, d);
     ctr.rays++;
     return true;
 }
 
-// One node visit of the query (the same visits and tests as trace()).
-// Returns true when the query has finished: then q.best is the hit slot (or
-// -1) and, for a closest-hit query, q.bt its distance.
-__device__ __forceinline__ bool ray_step(const DevScene& S, RayQ& q, uint32_t* stk, int stride, Counters& ctr) {
-    int kc[4];
-    if (visit_node(S, q.node, q.o, q.d, q.rs, q.tmax, q.anyhit, q.bt, q.best, q.best_prim, kc, ctr)) return true;
-    if (next_node(kc, q.node, q.sp, stk, stride, S.stack_cap)) return false;
-    if (q.anyhit) q.best = -1;
+// Wavefront masks of the lanes whose query holds a pending leaf (ml) or a
+// node to visit (mv); taken by every lane of the wavefront, tracing or not.
+__device__ __forceinline__ void ray_masks(const RayQ& q, bool tracing, uint64_t& ml, uint64_t& mv) {
+    ml = __ballot(tracing && q.pleaf != 0);
+    mv = __ballot(tracing && q.node >= 0);
+}
+
+// One iteration of trace()'s loop for a lane with a query in flight: a leaf
+// round (when enough of the wavefront's busy lanes hold a pending leaf, or
+// none can visit a node) or a node visit; the same tests as trace(), so the
+// result is the same.  Returns true when the query has finished: then q.best
+// is the hit slot (or -1) and, for a closest-hit query, q.bt its distance.
+__device__ __forceinline__ bool ray_step(const DevScene& S, RayQ& q, uint32_t* stk, int stride, Counters& ctr,
+                                         uint64_t ml, uint64_t mv) {
+    const int cap = S.stack_cap;
+    const int nl = __popcll(ml);
+    if (nl && (mv == 0 || 100 * nl >= DR_LEAF_PCT * __popcll(ml | mv))) {
+        if (q.pleaf != 0) {
+            const bool f = S.leaf_batch == 2
+                               ? test_leaf<2>(S, q.pleaf, q.o, q.d, q.tmax, q.anyhit, q.bt, q.best, q.best_prim, ctr)
+                               : test_leaf<4>(S, q.pleaf, q.o, q.d, q.tmax, q.anyhit, q.bt, q.best, q.best_prim, ctr);
+            q.pleaf = 0;
+            if (f) {
+                q.found = true;
+                q.node = -1;
+                q.sp = 0;
+            } else if (q.node < 0) {
+                pop_entry(q.node, q.pleaf, q.sp, stk, stride);
+            }
+        }
+    } else if (q.node >= 0) {
+        const DevNode n = load_node(S, q.node);
+        ctr.nodes++;
+        float tn[4];
+        bool hit[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            hit[k] = slab(f4(n.lox, k), f4(n.loy, k), f4(n.loz, k), f4(n.hix, k), f4(n.hiy, k), f4(n.hiz, k), q.rs,
+                          S.tmin, q.bt, tn[k]) &
+                     (i4(n.count, k) >= 0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (hit[k] && i4(n.count, k) > 0) {
+                const int code = leaf_code(i4(n.child, k), i4(n.count, k));
+                if (q.pleaf == 0) q.pleaf = code;
+                else if (q.sp < cap) stk[(q.sp++) * stride] = (uint32_t)code;
+            }
+        }
+        float kt[4];
+        int kc[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const bool inner = hit[k] && i4(n.count, k) == 0;
+            kt[k] = inner ? tn[k] : INFINITY;
+            kc[k] = inner ? i4(n.child, k) : -1;
+        }
+#define DR_CSWAP(i, j)                                       \
+    if (kt[j] < kt[i]) {                                     \
+        const float tt_ = kt[i]; kt[i] = kt[j]; kt[j] = tt_; \
+        const int cc_ = kc[i]; kc[i] = kc[j]; kc[j] = cc_;   \
+    }
+        DR_CSWAP(0, 1)
+        DR_CSWAP(2, 3)
+        DR_CSWAP(0, 2)
+        DR_CSWAP(1, 3)
+        DR_CSWAP(1, 2)
+#undef DR_CSWAP
+        if (kc[0] >= 0) {
+            if (kc[3] >= 0 && q.sp < cap) stk[(q.sp++) * stride] = (uint32_t)kc[3];
+            if (kc[2] >= 0 && q.sp < cap) stk[(q.sp++) * stride] = (uint32_t)kc[2];
+            if (kc[1] >= 0 && q.sp < cap) stk[(q.sp++) * stride] = (uint32_t)kc[1];
+            q.node = kc[0];
+        } else {
+            pop_entry(q.node, q.pleaf, q.sp, stk, stride);
+        }
+    }
+    if (q.node >= 0 || q.pleaf != 0) return false;
+    if (q.anyhit && !q.found) q.best = -1;
     return true;
 }
 
