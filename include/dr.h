@@ -279,14 +279,20 @@ dr_status dr_stats(dr_chains* c, dr_counters* out, void* hip_stream);
  * DR_NODE_CACHE_AUTO: up to 341 (five levels) with two lanes per chain, up to
  * 85 (four levels) with one, fewer when the stacks of a deep tree leave too
  * little LDS for two (paired) or three (one lane) wavefronts per SIMD to stay
- * resident; explicit values are cut only to what fits one block).
+ * resident; explicit values are cut only to what fits one block), and
+ * wavefront (1: the initialise pass evaluates its paths as ray waves -
+ * alternating launches of a traversal kernel whose persistent lanes take
+ * the next pending ray as theirs finishes, and an event kernel that shades
+ * each path's vertex and issues its next ray - instead of one lane
+ * following one path; 2: off).
  * Zeros keep the current
  * value.  Defaults: 256 threads, 4 blocks per compute unit, 1 chain per pop,
  * 2 lanes per chain when n_chains is below two wavefronts per SIMD
  * (n_cu * 512) else 1, sorting off (it pays only when chains outnumber the
  * resident lanes several times over), refill off, thresholds 50 and 50,
- * tile ordering off, automatic node cache.  The
- * form and the order in which chains are processed never change results. */
+ * tile ordering off, automatic node cache, ray waves off (on the scenes
+ * measured here the state round trips between the two kernels cost more than
+ * the denser traversal saves).  The form, the ray waves and the order in which chains are processed never change results. */
 #define DR_NODE_CACHE_AUTO 0xFFFFFFFFu
 typedef struct {
     uint32_t block;
@@ -299,6 +305,7 @@ typedef struct {
     uint32_t refill_advance_pct;
     uint32_t sort_by_tile;
     uint32_t node_cache;
+    uint32_t wavefront;
 } dr_launch_cfg;
 dr_status dr_chains_set_launch(dr_chains* c, const dr_launch_cfg* cfg);
 dr_status dr_chains_get_launch(dr_chains* c, dr_launch_cfg* cfg);

@@ -120,7 +120,7 @@ def tune(ch: "dr.Chains", reps: int = 3, use_cache: bool = True, verbose: bool =
     snap = ch.read_state() if restore else None
     full = dict(sort_by_length=2, sort_by_tile=2, refill=2, grab=1, node_cache=dr.DR_NODE_CACHE_AUTO,
                 refill_event_pct=50, refill_advance_pct=50)
-    flags = ("sort_by_length", "sort_by_tile", "refill")  # read back as 1/0, requested as 1 on / 2 off
+    flags = ("sort_by_length", "sort_by_tile", "refill", "wavefront")  # read back as 1/0, requested as 1 on / 2 off
     current = {k: ((1 if v else 2) if k in flags else v) for k, v in ch.get_launch().items()}
     ch.set_launch(**current)
     current_ms = _time(ch, reps, per_launch)

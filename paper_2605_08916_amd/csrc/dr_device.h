@@ -680,11 +680,14 @@ __device__ __forceinline__ V3 camera_dir(const Cam& C, float u0, float u1) {
 }
 
 // Pixel of the film block, in FP32: px = min(floor(u0 W), W-1), row 0 at top.
+__device__ __forceinline__ uint32_t pixel_of_wh(int W, int H, float u0, float u1) {
+    int px = (int)floorf(u0 * (float)W), py = (int)floorf(u1 * (float)H);
+    px = min(max(px, 0), W - 1);
+    py = min(max(py, 0), H - 1);
+    return (uint32_t)(py * W + px);
+}
 __device__ __forceinline__ uint32_t pixel_of(const DevScene& S, float u0, float u1) {
-    int px = (int)floorf(u0 * (float)S.W), py = (int)floorf(u1 * (float)S.H);
-    px = min(max(px, 0), S.W - 1);
-    py = min(max(py, 0), S.H - 1);
-    return (uint32_t)(py * S.W + px);
+    return pixel_of_wh(S.W, S.H, u0, u1);
 }
 
 // ---------------------------------------------------------------------------

@@ -58,6 +58,15 @@ struct KBufs {
     uint32_t* order;
     uint32_t* bins;
     uint32_t* state;  // rows: x[d], score[d], rec[L-1], occ[L-1], killed, ids, then the record rows p, w, pix, f[3]
+    // ray waves (the wavefront form of a path pass): per slot the path state
+    // between ray queries (DR_WF_ROWS rows), the pending ray (o, tmax | d,
+    // anyhit), its answer, and two queues of slots with a ray in flight
+    uint32_t* wf;
+    float4* wf_ray;
+    int* wf_hit;
+    float* wf_t;
+    uint32_t* wf_q;    // 2 x N slot queues
+    uint32_t* wf_cnt;  // [0], [1] queue lengths, [2] trace work counter
     uint32_t* alt;    // same shape as state
 };
 
@@ -498,6 +507,201 @@ __global__ void __launch_bounds__(256) k_eval_sm(DevScene S, const float* u, int
 }
 
 // ---------------------------------------------------------------------------
+// Ray waves: a path pass as alternating launches of a traversal kernel (all
+// pending rays, persistent lanes that take the next ray as theirs finishes)
+// and an event kernel (each path whose ray finished shades its vertex and
+// issues its next ray, or ends).  The path arithmetic is the state machine's
+// (dr_machine.h), the same operations as path_forward, so results are
+// bit-identical to the straight-line kernels; the traversal kernel holds no
+// shading code, so its lanes stay busy with traversal.
+// ---------------------------------------------------------------------------
+#define DR_WF_ROWS 33
+
+// Path state of slot c <-> rows of B.wf (planar, coalesced per wavefront).
+__device__ __forceinline__ void wf_store(const KBufs& B, size_t N, int c, const PathSM& P) {
+    uint32_t* w = B.wf + c;
+    int r = 0;
+    auto put = [&](uint32_t v) { w[(size_t)(r++) * N] = v; };
+    auto putf = [&](float v) { put(__float_as_uint(v)); };
+    auto put3 = [&](V3 v) { putf(v.x); putf(v.y); putf(v.z); };
+    put((uint32_t)P.phase); put((uint32_t)P.j); put((uint32_t)P.slot); put((uint32_t)P.li); put((uint32_t)P.nv);
+    put((P.shadow ? 1u : 0u) | (P.cont ? 2u : 0u) | (P.delta ? 4u : 0u));
+    putf(P.cx); putf(P.cy); putf(P.r2);
+    put3(P.x); put3(P.d); put3(P.n); put3(P.beta); put3(P.f); put3(P.wi); put3(P.wt); put3(P.wl);
+}
+__device__ __forceinline__ void wf_load(const KBufs& B, size_t N, int c, PathSM& P) {
+    const uint32_t* w = B.wf + c;
+    int r = 0;
+    auto get = [&]() { return w[(size_t)(r++) * N]; };
+    auto getf = [&]() { return __uint_as_float(get()); };
+    auto get3 = [&]() { const float a = getf(), b = getf(), d = getf(); return v3(a, b, d); };
+    P.phase = (int)get(); P.j = (int)get(); P.slot = (int)get(); P.li = (int)get(); P.nv = (int)get();
+    const uint32_t fl = get();
+    P.shadow = (fl & 1u) != 0; P.cont = (fl & 2u) != 0; P.delta = (fl & 4u) != 0;
+    P.cx = getf(); P.cy = getf(); P.r2 = getf();
+    P.x = get3(); P.d = get3(); P.n = get3(); P.beta = get3(); P.f = get3(); P.wi = get3(); P.wt = get3(); P.wl = get3();
+}
+
+// Appends slot c to a queue with one atomic per wavefront (all lanes call it).
+__device__ __forceinline__ void wf_push(uint32_t* q, uint32_t* cnt, bool push, int c) {
+    const uint64_t m = __ballot(push);
+    if (!m) return;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)m) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(cnt, (uint32_t)__popcll(m));
+    base = __shfl(base, leader);
+    if (push) q[base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)c;
+}
+
+__device__ __forceinline__ void wf_put_ray(const KBufs& B, int c, const RayQ& q) {
+    B.wf_ray[2 * (size_t)c] = make_float4(q.o.x, q.o.y, q.o.z, q.tmax);
+    B.wf_ray[2 * (size_t)c + 1] = make_float4(q.d.x, q.d.y, q.d.z, q.anyhit ? 1.0f : 0.0f);
+}
+
+// Path records of the initialise pass: vertices into the record rows; at the
+// end p, f, the pixel and the vertex count (as k_init_eval stores them).
+template <int L>
+struct InitRec {
+    uint32_t *rec, *pix, *key, *ids;
+    float *p, *f;
+    const float* x;
+    int N, c, W, H;
+    __device__ __forceinline__ void vertex(int j, uint32_t r) const { rec[(size_t)(j - 1) * N + c] = r; }
+    __device__ __forceinline__ void finish(V3 fv, int nv) const {
+        for (int j = nv + 1; j <= L - 1; ++j) rec[(size_t)(j - 1) * N + c] = DR_NO_VERTEX;
+        p[c] = lum(fv);
+        f[c] = fv.x;
+        f[(size_t)N + c] = fv.y;
+        f[(size_t)2 * N + c] = fv.z;
+        pix[c] = pixel_of_wh(W, H, x[c], x[(size_t)N + c]);
+        key[c] = (uint32_t)nv;
+        ids[c] = (uint32_t)c;
+    }
+};
+template <int L>
+__device__ __forceinline__ InitRec<L> init_rec(const KBufs& B, const DevScene& S, int N, int c) {
+    return InitRec<L>{B.rec, B.pix_tmp, B.key, B.ids, B.p_tmp, B.f_tmp, B.x, N, c, S.W, S.H};
+}
+
+// Initialise pass, first wave: x ~ mu and the camera ray of every chain.
+template <int L, bool DELTA>
+__global__ void __launch_bounds__(256) k_wf_init_begin(KParams P, DevScene S, KBufs B) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    Counters ctr = {0, 0, 0};
+    bool ray = false;
+    if (c < P.N) {
+        regen(P.seed, P.d, P.N, B.x + c, c, B.steps[1]);
+        const Cam C = load_cam(S);
+        PathSM ps;
+        ps.phase = PH_NEW;
+        RayQ q;
+        ray = sm_event<L, DELTA>(S, C, SoaU{B.x + c, P.N}, ps, q, init_rec<L>(B, S, P.N, c), ctr);
+        if (ray) {
+            wf_store(B, P.N, c, ps);
+            wf_put_ray(B, c, q);
+        }
+    }
+    wf_push(B.wf_q, &B.wf_cnt[0], ray, c);
+    if (P.count) wave_add(&B.ctr[C_RAYS], ctr.rays);
+}
+
+// Traversal of the pending rays of queue `in` (length B.wf_cnt[in]):
+// persistent lanes take the next slot once enough of the wavefront is idle,
+// run trace()'s speculative traversal and store the answer.
+static __global__ void __launch_bounds__(256) k_wf_trace(KParams P, DevScene S, KBufs B, int in) {
+    extern __shared__ uint32_t s_stack[];
+    cache_top_nodes(S);
+    uint32_t* stk = s_stack + S.n_top * 32 + threadIdx.x;
+    const int stride = blockDim.x;
+    const int lane = threadIdx.x & 63;
+    const uint32_t n = B.wf_cnt[in];
+    const uint32_t* queue = B.wf_q + (size_t)in * P.N;
+    Counters ctr = {0, 0, 0};
+    RayQ q;
+    q.node = -1;
+    q.pleaf = 0;
+    int c = -1;
+    bool drained = false;
+    while (true) {
+        const bool idle = q.node < 0 && q.pleaf == 0;
+        if (idle && c >= 0) {
+            B.wf_hit[c] = q.best;
+            B.wf_t[c] = q.bt;
+            c = -1;
+        }
+        const bool want = idle && !drained;
+        const uint64_t mw = __ballot(want), mb = __ballot(!idle);
+        const int nw = __popcll(mw);
+        // refill once three quarters of the wavefront wait (or none is busy)
+        if (nw && (mb == 0 || 4 * nw >= 3 * 64)) {
+            const int leader = __ffsll((long long)mw) - 1;
+            uint32_t base = 0;
+            if (lane == leader) base = atomicAdd(&B.wf_cnt[2], (uint32_t)nw);
+            base = __shfl(base, leader);
+            if (want) {
+                const uint32_t it = base + (uint32_t)__popcll(mw & ((1ull << lane) - 1ull));
+                if (it < n) {
+                    c = (int)queue[it];
+                    const float4 a = B.wf_ray[2 * (size_t)c], b = B.wf_ray[2 * (size_t)c + 1];
+                    Counters unused = {0, 0, 0};  // rays are counted where they are issued
+                    ray_begin(S, q, v3(a.x, a.y, a.z), v3(b.x, b.y, b.z), a.w, b.w != 0.0f, unused);
+                } else {
+                    drained = true;
+                }
+            }
+        }
+        uint64_t ml, mv;
+        ray_masks(q, true, ml, mv);
+        if (!(ml | mv)) {
+            if (__ballot(!drained || c >= 0) == 0) break;
+            continue;
+        }
+        (void)ray_step(S, q, stk, stride, ctr, ml, mv);
+    }
+    if (P.count) {
+        wave_add(&B.ctr[C_NODES], ctr.nodes);
+        wave_add(&B.ctr[C_TRIS], ctr.tris);
+    }
+}
+
+// Events of the initialise pass: every slot of queue `in` consumes its
+// answer, shades and issues its next ray into queue `out`, or ends its path.
+template <int L, bool DELTA>
+__global__ void __launch_bounds__(256) k_wf_init_event(KParams P, DevScene S, KBufs B, int in) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int out = 1 - in;
+    Counters ctr = {0, 0, 0};
+    bool ray = false;
+    int c = -1;
+    if (i < (int)B.wf_cnt[in]) {
+        c = (int)B.wf_q[(size_t)in * P.N + i];
+        PathSM ps;
+        wf_load(B, P.N, c, ps);
+        RayQ q;
+        q.best = B.wf_hit[c];
+        q.bt = B.wf_t[c];
+        if (ps.phase == PH_SHADOW)  // the blocker is the next step's candidate for this shadow ray
+            B.occ[(size_t)(ps.j - 1) * P.N + c] = q.best >= 0 ? ((uint32_t)q.best << 8) : DR_NO_VERTEX;
+        const Cam C = load_cam(S);
+        ray = sm_event<L, DELTA>(S, C, SoaU{B.x + c, P.N}, ps, q, init_rec<L>(B, S, P.N, c), ctr);
+        if (ray) {
+            wf_store(B, P.N, c, ps);
+            wf_put_ray(B, c, q);
+        }
+    }
+    wf_push(B.wf_q + (size_t)out * P.N, &B.wf_cnt[out], ray, c);
+    if (P.count) wave_add(&B.ctr[C_RAYS], ctr.rays);
+}
+// Clears a queue's length and the traversal work counter before a wave.
+static __global__ void k_wf_reset(KBufs B, int which) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        B.wf_cnt[which] = 0u;
+        B.wf_cnt[2] = 0u;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Host launchers (one instantiation per path length L)
 // ---------------------------------------------------------------------------
 template <int L>
@@ -540,6 +744,28 @@ void launch_eval(dim3 g, dim3 b, hipStream_t st, const DevScene& S, const float*
     hipLaunchKernelGGL(k_eval<L>, g, b, stack_bytes(S, b.x), st, S, u, n, eps, fo, logp, grad, rs, ro);
 }
 
+// The initialise pass's path evaluation as ray waves: the first wave, then
+// 2(L-1) rounds of traversal and events (a path issues at most that many
+// rays after its camera ray).  Graph-capturable: a fixed number of launches,
+// queue lengths in device memory.
+template <int L>
+void launch_wf_init(dim3 g, dim3 b, int trace_blocks, hipStream_t st, const KParams& P, const DevScene& S,
+                    const DevScene& St, const KBufs& B, bool delta) {
+    const size_t lds = stack_bytes(St, b.x) + (size_t)St.n_top * sizeof(DevNode);
+    hipLaunchKernelGGL(k_wf_reset, dim3(1), dim3(64), 0, st, B, 0);
+    hipLaunchKernelGGL(k_wf_reset, dim3(1), dim3(64), 0, st, B, 1);
+    if (delta) hipLaunchKernelGGL((k_wf_init_begin<L, true>), g, b, 0, st, P, S, B);
+    else hipLaunchKernelGGL((k_wf_init_begin<L, false>), g, b, 0, st, P, S, B);
+    int in = 0;
+    for (int r = 0; r < 2 * (L - 1); ++r) {
+        hipLaunchKernelGGL(k_wf_trace, dim3(trace_blocks), b, lds, st, P, St, B, in);
+        hipLaunchKernelGGL(k_wf_reset, dim3(1), dim3(64), 0, st, B, 1 - in);
+        if (delta) hipLaunchKernelGGL((k_wf_init_event<L, true>), g, b, 0, st, P, S, B, in);
+        else hipLaunchKernelGGL((k_wf_init_event<L, false>), g, b, 0, st, P, S, B, in);
+        in = 1 - in;
+    }
+}
+
 // Explicit instantiation (X empty) or extern declaration (X = extern) of every
 // launcher for one L.
 #define DR_LAUNCHERS(X, L)                                                                                          \
@@ -552,4 +778,6 @@ void launch_eval(dim3 g, dim3 b, hipStream_t st, const DevScene& S, const float*
     X template void launch_eval_sm<L>(dim3, dim3, hipStream_t, const DevScene&, const float*, int, float, float*,   \
                                       float*, uint32_t*, uint32_t*, int);                                           \
     X template void launch_eval<L>(dim3, dim3, hipStream_t, const DevScene&, const float*, int, float, float*, float*, \
-                                   float*, uint32_t*, uint32_t*);
+                                   float*, uint32_t*, uint32_t*);                                                  \
+    X template void launch_wf_init<L>(dim3, dim3, int, hipStream_t, const KParams&, const DevScene&, const DevScene&, \
+                                      const KBufs&, bool);

@@ -402,7 +402,7 @@ struct dr_chains {
     uint64_t seed = 0;
     int n_partials = 0;
     int record = 0, count = 0;
-    dr_launch_cfg launch{256, 2, 1, 2, 0, 0, 50, 50, 0, DR_NODE_CACHE_AUTO};
+    dr_launch_cfg launch{256, 2, 1, 2, 0, 0, 50, 50, 0, DR_NODE_CACHE_AUTO, 0};
     int n_cu = 256;
     int lds_limit = 65536;             // bytes of LDS one block may use
     int lds_per_cu = 163840;           // bytes of LDS one compute unit holds
@@ -488,9 +488,16 @@ static void enqueue_init(dr_chains* c, uint32_t frame, int from_device, hipStrea
     // wavefronts per SIMD: it always takes the automatic cache for that shape
     DevScene S = c->scene->ds;
     S.n_top = node_cache_size(c, blk, false, DR_NODE_CACHE_AUTO);
-    const size_t lds = stack_bytes(S, blk) + (size_t)S.n_top * sizeof(DevNode);
-    if (c->scene->has_delta) hipLaunchKernelGGL(k_init_eval<true>, g, b, lds, st, P, S, c->kb);
-    else hipLaunchKernelGGL(k_init_eval<false>, g, b, lds, st, P, S, c->kb);
+    if (c->launch.wavefront) {
+        // ray waves: persistent traversal blocks (more than fit at once; the
+        // extra ones find the queue drained)
+        DR_DISPATCH_L(c->kp.L, launch_wf_init, g, b, c->n_cu * 4, st, P, c->scene->ds, S, c->kb,
+                      c->scene->has_delta);
+    } else {
+        const size_t lds = stack_bytes(S, blk) + (size_t)S.n_top * sizeof(DevNode);
+        if (c->scene->has_delta) hipLaunchKernelGGL(k_init_eval<true>, g, b, lds, st, P, S, c->kb);
+        else hipLaunchKernelGGL(k_init_eval<false>, g, b, lds, st, P, S, c->kb);
+    }
     hipLaunchKernelGGL(k_reduce_p, dim3(c->n_partials), dim3(256), 0, st, P, c->kb);
     hipLaunchKernelGGL(k_finish_k0, dim3(1), dim3(64), 0, st, P, c->kb, c->n_partials, (double)c->P.k0, (double)c->P.m);
     const int with_score = c->P.mode == DR_MODE_FUSED ? 1 : 0;
@@ -1038,6 +1045,12 @@ dr_status dr_chains_init(dr_scene* s, const dr_params* p, uint64_t seed, uint32_
     get(&q, sizeof(uint32_t) * N); B.key = (uint32_t*)q;
     get(&q, sizeof(uint32_t) * N); B.order = (uint32_t*)q;
     get(&q, sizeof(uint32_t) * 2 * DR_TILE_BINS); B.bins = (uint32_t*)q;
+    get(&q, sizeof(uint32_t) * DR_WF_ROWS * (size_t)N); B.wf = (uint32_t*)q;
+    get(&q, sizeof(float4) * 2 * (size_t)N); B.wf_ray = (float4*)q;
+    get(&q, sizeof(int) * (size_t)N); B.wf_hit = (int*)q;
+    get(&q, sizeof(float) * (size_t)N); B.wf_t = (float*)q;
+    get(&q, sizeof(uint32_t) * 2 * (size_t)N); B.wf_q = (uint32_t*)q;
+    get(&q, 64); B.wf_cnt = (uint32_t*)q;
     B.sigma = p->sigma_diag;
     if (!ok) {
         c->mem.release();
@@ -1239,6 +1252,7 @@ dr_status dr_chains_set_launch(dr_chains* c, const dr_launch_cfg* cfg) {
     if (cfg->sort_by_length > 2) return fail(DR_ERR_INVALID_ARG, "dr_chains_set_launch: sort_by_length must be 0, 1 or 2");
     if (cfg->refill > 2) return fail(DR_ERR_INVALID_ARG, "dr_chains_set_launch: refill must be 0, 1 or 2");
     if (cfg->sort_by_tile > 2) return fail(DR_ERR_INVALID_ARG, "dr_chains_set_launch: sort_by_tile must be 0, 1 or 2");
+    if (cfg->wavefront > 2) return fail(DR_ERR_INVALID_ARG, "dr_chains_set_launch: wavefront must be 0, 1 or 2");
     if (cfg->node_cache > 512 && cfg->node_cache != DR_NODE_CACHE_AUTO)
         return fail(DR_ERR_INVALID_ARG, "dr_chains_set_launch: node_cache must be at most 512 (or automatic)");
     if (cfg->refill_event_pct > 100 || cfg->refill_advance_pct > 100)
@@ -1251,6 +1265,7 @@ dr_status dr_chains_set_launch(dr_chains* c, const dr_launch_cfg* cfg) {
     if (cfg->refill) c->launch.refill = cfg->refill == 1 ? 1u : 0u;
     if (cfg->sort_by_tile) c->launch.sort_by_tile = cfg->sort_by_tile == 1 ? 1u : 0u;
     if (cfg->node_cache) c->launch.node_cache = cfg->node_cache;
+    if (cfg->wavefront) c->launch.wavefront = cfg->wavefront == 1 ? 1u : 0u;
     if (cfg->refill_event_pct) c->launch.refill_event_pct = cfg->refill_event_pct;
     if (cfg->refill_advance_pct) c->launch.refill_advance_pct = cfg->refill_advance_pct;
     g_err.clear();
