@@ -92,9 +92,11 @@ TRAFFIC_TITLES = {
     "interior": "k_step_fused<8, false>: procedural interior 2,048,020 triangles, 1920x1080, L = 8, one lane per chain",
     "spheres": "k_step_fused_pair<8, false>: procedural spheres 53k triangles, 512x512, L = 8",
 }
-KERNEL_SOURCES = ["paper_2605_08916_amd/csrc/dr_lib.hip", "paper_2605_08916_amd/csrc/dr_device.h",
-                  "paper_2605_08916_amd/csrc/dr_adjoint.h", "paper_2605_08916_amd/csrc/dr_chain.h",
-                  "paper_2605_08916_amd/csrc/dr_machine.h", "include/dr.h", "paper_2605_08916_amd/build.py"]
+KERNEL_SOURCES = ["paper_2605_08916_amd/csrc/dr_lib.hip", "paper_2605_08916_amd/csrc/dr_kernels.h",
+                  "paper_2605_08916_amd/csrc/dr_device.h", "paper_2605_08916_amd/csrc/dr_adjoint.h",
+                  "paper_2605_08916_amd/csrc/dr_chain.h", "paper_2605_08916_amd/csrc/dr_machine.h",
+                  "paper_2605_08916_amd/csrc/bvh_build.cpp", "include/dr.h", "paper_2605_08916_amd/build.py"] + [
+                  f"paper_2605_08916_amd/csrc/dr_inst_{x}.hip" for x in "abcde"]
 
 
 def sources_digest():
@@ -123,10 +125,10 @@ def _pmc_rows(folder, counter):
 def write_traffic_summary(dirs, workload, chains, per_launch, cmd):
     fetch_dir, write_dir, cfetch_dir, cwrite_dir = dirs[:4]
 
-    def fused_mean(folder, counter):
-        v = [x for k, x in _pmc_rows(folder, counter) if "k_step_fused" in k]
+    def fused_mean(folder, counter, kernel="k_step_fused"):
+        v = [x for k, x in _pmc_rows(folder, counter) if kernel in k]
         if not v:
-            raise SystemExit(f"no k_step_fused dispatch with {counter} under {folder}")
+            raise SystemExit(f"no {kernel} dispatch with {counter} under {folder}")
         return sum(v) / len(v), len(v)
 
     def copy_kib(folder, counter):
@@ -166,7 +168,23 @@ def write_traffic_summary(dirs, workload, chains, per_launch, cmd):
         miss, _ = fused_mean(dirs[4], "TCC_MISS_sum")
         valu, _ = fused_mean(dirs[5], "SQ_ACTIVE_INST_VALU")
         wc, _ = fused_mean(dirs[5], "SQ_WAVE_CYCLES")
-        lines += [f"l2_hit_rate: {hit / (hit + miss):.4f}", f"valu_issue_frac: {valu / wc:.4f}"]
+        wait, _ = fused_mean(dirs[5], "SQ_WAIT_ANY")
+        lines += [f"l2_hit_rate: {hit / (hit + miss):.4f}", f"valu_issue_frac: {valu / wc:.4f}",
+                  f"wait_frac: {wait / wc:.4f}"]
+    if workload == "interior":
+        # the frame's other full path evaluation: the re-initialisation kernel
+        fi, _ = fused_mean(fetch_dir, "FETCH_SIZE", "k_init_eval")
+        wi, _ = fused_mean(write_dir, "WRITE_SIZE", "k_init_eval")
+        lines += [f"init_eval_hbm_read_bytes_per_launch: {fi * 1024.0 * fs:.0f}",
+                  f"init_eval_hbm_write_bytes_per_launch: {wi * 1024.0 * ws:.0f}"]
+        if len(dirs) >= 6:
+            hit, _ = fused_mean(dirs[4], "TCC_HIT_sum", "k_init_eval")
+            miss, _ = fused_mean(dirs[4], "TCC_MISS_sum", "k_init_eval")
+            valu, _ = fused_mean(dirs[5], "SQ_ACTIVE_INST_VALU", "k_init_eval")
+            wc, _ = fused_mean(dirs[5], "SQ_WAVE_CYCLES", "k_init_eval")
+            wait, _ = fused_mean(dirs[5], "SQ_WAIT_ANY", "k_init_eval")
+            lines += [f"init_eval_l2_hit_rate: {hit / (hit + miss):.4f}", f"init_eval_valu_issue_frac: {valu / wc:.4f}",
+                      f"init_eval_wait_frac: {wait / wc:.4f}"]
     with open(TRAFFIC_FILES[workload], "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -794,8 +812,18 @@ def main():
         if a.config == "spheres_1080p_L16":
             sigma = torch.from_numpy(inputs.per_chain_sigma(4 * (L - 1), N, seed=4)).cuda()
         ch = dr.Chains(scene, N, L, 2024, sigma=sigma)
-        for _ in range(a.warmup + a.steps):
-            ch.step(F)
+        if a.config or a.headline_spheres:
+            for _ in range(a.warmup + a.steps):
+                ch.step(F)
+        else:
+            # the real-time frame: camera move, re-initialisation, F evolve steps, resolve
+            cams = [inputs.camera_path(sc, f) for f in range(60)]
+            img = torch.zeros((3, scene.W * scene.H), device="cuda", dtype=torch.float32)
+            for i in range(a.warmup + a.steps):
+                scene.set_camera(cams[i % len(cams)])
+                ch.reinit(1 + i)
+                ch.step(F)
+                ch.resolve(img)
         torch.cuda.synchronize()
         print(json.dumps({"profile_only_launches": a.warmup + a.steps, "steps_per_launch": F, "chains": N,
                           "config": a.config or ("spheres" if a.headline_spheres else "interior")}))
