@@ -58,22 +58,33 @@ __global__ void k_begin_init(KBufs B, uint32_t frame, int from_device) {
     B.steps[2] = f;
     B.steps[1] = f << 32;
     B.steps[0] = (f << 32) + 1ull;
+    *B.queue = 0u;  // the init kernel's work queue
 }
 
 // Initialise, phase 1: x ~ mu and f(x) for every chain (Alg. 4.1).  DELTA:
-// the scene has smooth conductors or dielectrics.
+// the scene has smooth conductors or dielectrics.  Persistent: each wavefront
+// takes the next 64 consecutive chains from the work queue (one atomic) until
+// the queue is drained, so a wavefront slot never idles waiting for the other
+// wavefronts of its block, and the top nodes are copied to LDS once per
+// resident block.
 template <bool DELTA>
 __global__ void __launch_bounds__(256) k_init_eval(KParams P, DevScene S, KBufs B) {
     extern __shared__ uint32_t s_stack[];
     cache_top_nodes(S);  // the top nodes precede the stacks in LDS
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t* stk = s_stack + S.n_top * 32 + threadIdx.x;
+    const int lane = threadIdx.x & 63;
     const uint64_t s0 = B.steps[1];
     Counters ctr = {0, 0, 0};
-    if (c < P.N) {
+    while (true) {
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(B.queue, 64u);
+        base = __shfl(base, 0);
+        if (base >= (uint32_t)P.N) break;
+        const int c = (int)base + lane;
+        if (c >= P.N) continue;
         regen(P.seed, P.d, P.N, B.x + c, c, s0);
         int nv;
-        const V3 f = path_forward<false, DELTA>(S, P.L, SoaU{B.x + c, P.N}, B.rec + c, P.N,
-                                                s_stack + S.n_top * 32 + threadIdx.x, blockDim.x, ctr, &nv,
+        const V3 f = path_forward<false, DELTA>(S, P.L, SoaU{B.x + c, P.N}, B.rec + c, P.N, stk, blockDim.x, ctr, &nv,
                                                 B.occ + c, false);
         B.p_tmp[c] = lum(f);
         B.f_tmp[c] = f.x;
@@ -495,8 +506,15 @@ static void enqueue_init(dr_chains* c, uint32_t frame, int from_device, hipStrea
                       c->scene->has_delta);
     } else {
         const size_t lds = stack_bytes(S, blk) + (size_t)S.n_top * sizeof(DevNode);
-        if (c->scene->has_delta) hipLaunchKernelGGL(k_init_eval<true>, g, b, lds, st, P, S, c->kb);
-        else hipLaunchKernelGGL(k_init_eval<false>, g, b, lds, st, P, S, c->kb);
+        // persistent grid: as many blocks as can be resident at once
+        int per_cu = 0;
+        if (c->scene->has_delta)
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_init_eval<true>, blk, lds);
+        else
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_init_eval<false>, blk, lds);
+        const dim3 gp((unsigned)std::max(1L, std::min((long)g.x, (long)c->n_cu * std::max(per_cu, 1))));
+        if (c->scene->has_delta) hipLaunchKernelGGL(k_init_eval<true>, gp, b, lds, st, P, S, c->kb);
+        else hipLaunchKernelGGL(k_init_eval<false>, gp, b, lds, st, P, S, c->kb);
     }
     hipLaunchKernelGGL(k_reduce_p, dim3(c->n_partials), dim3(256), 0, st, P, c->kb);
     hipLaunchKernelGGL(k_finish_k0, dim3(1), dim3(64), 0, st, P, c->kb, c->n_partials, (double)c->P.k0, (double)c->P.m);
