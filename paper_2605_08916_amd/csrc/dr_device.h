@@ -410,41 +410,79 @@ __device__ __forceinline__ void pop_entry(int& node, int& pleaf, int& sp, const 
 // box tests are conservative, so every triangle at or before the candidate's
 // distance is still tested, and the tie rule does not depend on order).  An
 // any-hit query that hits the candidate is done.
-__device__ int trace(const DevScene& S, V3 o, V3 d, float tmax, bool anyhit, float& t_hit, uint32_t* stk, int stride,
-                     Counters& ctr, int hint = -1) {
-    t_hit = tmax;
-    if (!(tmax > S.tmin)) return -1;
-    float bt = tmax;
-    int best = -1;
-    uint32_t best_prim = 0xFFFFFFFFu;
-    ctr.rays++;
-    if (hint >= 0 && hint < S.n_tris) {
-        const DevTri T = S.tris[hint];
-        float t;
-        ctr.tris++;
-        if (tri_test(T, o, d, S.tmin, t) && t <= bt) {
-            if (anyhit) {
-                if (t < tmax) return hint;
-            } else {
-                bt = t;
-                best = hint;
-                best_prim = __float_as_uint(T.v0.w);
+//
+// TWO: each lane runs a second query from the same origin (closest hit along
+// db over (tmin, inf), if b_on, with its own hint) right after its first
+// ends, in the same wavefront loop and on the same (then empty) stack.  The
+// wavefront then iterates as long as its longest per-lane sum of the two
+// traversals rather than the sum of the two longest, and the lanes done with
+// their first query keep working while others finish theirs.  Each query's
+// result is the one it has alone.
+template <bool TWO>
+__device__ __forceinline__ void trace_core(const DevScene& S, V3 o, V3 d, float tmax, bool anyhit, int hint, bool b_on,
+                                           V3 db, int hint_b, int& res_a, float& t_a, int& res_b, float& t_b,
+                                           uint32_t* stk, int stride, Counters& ctr) {
+    float bt, qmax = tmax;
+    int best, sp = 0, node = -1, pleaf = 0;
+    uint32_t best_prim;
+    bool found = false, qany = anyhit;
+    V3 qd = d;
+    RaySlab rs;
+    // set up one query: the hint test, then the root (node stays -1 when
+    // there is no query or the hint settles an any-hit query)
+    auto start = [&](V3 dd, float mx, bool any, int h) {
+        qd = dd;
+        qmax = mx;
+        qany = any;
+        bt = mx;
+        best = -1;
+        best_prim = 0xFFFFFFFFu;
+        found = false;
+        sp = 0;
+        pleaf = 0;
+        node = -1;
+        if (!(mx > S.tmin)) return;
+        ctr.rays++;
+        if (h >= 0 && h < S.n_tris) {
+            const DevTri T = S.tris[h];
+            float t;
+            ctr.tris++;
+            if (tri_test(T, o, dd, S.tmin, t) && t <= bt) {
+                if (any) {
+                    if (t < mx) {
+                        found = true;
+                        best = h;
+                        return;
+                    }
+                } else {
+                    bt = t;
+                    best = h;
+                    best_prim = __float_as_uint(T.v0.w);
+                }
             }
         }
-    }
-    const RaySlab rs = ray_slab(o, d);
-    int sp = 0, node = 0, pleaf = 0;
-    bool found = false;
+        rs = ray_slab(o, dd);
+        node = 0;
+    };
+    start(d, tmax, anyhit, hint);
+    int phase = 0;
     const int cap = S.stack_cap;
     while (true) {
+        if (TWO && phase == 0 && node < 0 && pleaf == 0) {
+            // first query over (its stack is empty): keep its answer, start the second
+            res_a = qany ? (found ? best : -1) : best;
+            t_a = bt;
+            phase = 1;
+            start(db, b_on ? INFINITY : -1.0f, false, hint_b);
+        }
         const bool has_leaf = pleaf != 0, can_visit = node >= 0;
         const uint64_t ml = __ballot(has_leaf), mv = __ballot(can_visit);
         if (!(ml | mv)) break;
         const int nl = __popcll(ml);
         if (nl && (mv == 0 || 100 * nl >= DR_LEAF_PCT * __popcll(ml | mv))) {
             if (has_leaf) {
-                const bool f = S.leaf_batch == 2 ? test_leaf<2>(S, pleaf, o, d, tmax, anyhit, bt, best, best_prim, ctr)
-                                                 : test_leaf<4>(S, pleaf, o, d, tmax, anyhit, bt, best, best_prim, ctr);
+                const bool f = S.leaf_batch == 2 ? test_leaf<2>(S, pleaf, o, qd, qmax, qany, bt, best, best_prim, ctr)
+                                                 : test_leaf<4>(S, pleaf, o, qd, qmax, qany, bt, best, best_prim, ctr);
                 pleaf = 0;
                 if (f) {
                     found = true;
@@ -504,9 +542,21 @@ __device__ int trace(const DevScene& S, V3 o, V3 d, float tmax, bool anyhit, flo
             }
         }
     }
-    t_hit = bt;
-    if (anyhit) return found ? best : -1;
-    return best;
+    if (TWO) {
+        res_b = best;
+        t_b = bt;
+    } else {
+        res_a = qany ? (found ? best : -1) : best;
+        t_a = bt;
+    }
+}
+
+__device__ int trace(const DevScene& S, V3 o, V3 d, float tmax, bool anyhit, float& t_hit, uint32_t* stk, int stride,
+                     Counters& ctr, int hint = -1) {
+    int ra, rb;
+    float tb;
+    trace_core<false>(S, o, d, tmax, anyhit, hint, false, d, -1, ra, t_hit, rb, tb, stk, stride, ctr);
+    return ra;
 }
 
 // ---------------------------------------------------------------------------
@@ -732,10 +782,14 @@ __device__ __forceinline__ void trace_vertex_rays(const DevScene& S, V3 x, bool 
         nslot = cont ? (odd ? ro : r) : -1;
         tn = odd ? to : tt;
     } else {
+        // the shadow query, then the continuation, back to back in one loop
         float ts;
-        occluder = shadow ? trace(S, x, wl, smax, true, ts, stk, stride, ctr, hint_s) : -1;
+        int ra, rb;
+        trace_core<true>(S, x, wl, shadow ? smax : -1.0f, true, hint_s, cont, wi, hint_c, ra, ts, rb, tn, stk, stride,
+                         ctr);
+        occluder = shadow ? ra : -1;
         occluded = occluder >= 0;
-        nslot = cont ? trace(S, x, wi, INFINITY, false, tn, stk, stride, ctr, hint_c) : -1;
+        nslot = cont ? rb : -1;
     }
 }
 
