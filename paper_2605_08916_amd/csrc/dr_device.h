@@ -221,119 +221,6 @@ __device__ __forceinline__ DevNode load_node(const DevScene& S, int i) {
 
 __device__ __forceinline__ float f4(const float4& v, int q) { return q == 0 ? v.x : (q == 1 ? v.y : (q == 2 ? v.z : v.w)); }
 __device__ __forceinline__ int i4(const int4& v, int q) { return q == 0 ? v.x : (q == 1 ? v.y : (q == 2 ? v.z : v.w)); }
-// Component q of v for a run-time q, as a two-level select (no branches).
-__device__ __forceinline__ int sel4(const int4& v, int q) {
-    const int lo = (q & 1) ? v.y : v.x;
-    const int hi = (q & 1) ? v.w : v.z;
-    return (q & 2) ? hi : lo;
-}
-
-// Triangle tests of the hit leaf children in `leaves` (the lanes of a
-// wavefront loop over their own hit leaves, lowest child first), BATCH
-// triangles' loads in flight at once; slots past a leaf (clamped to the
-// array) are loaded but not tested.  Returns true when an any-hit query has
-// found its hit.
-template <int BATCH>
-__device__ __forceinline__ bool leaf_tests(const DevScene& S, const DevNode& n, uint32_t leaves, V3 o, V3 d, float tmax,
-                                           bool anyhit, float& bt, int& best, uint32_t& best_prim, Counters& ctr) {
-    while (leaves) {
-        const int q = __ffs(leaves) - 1;
-        leaves &= leaves - 1u;
-        const int cnt = sel4(n.count, q);
-        const int first = sel4(n.child, q);
-        for (int k0 = first; k0 < first + cnt; k0 += BATCH) {
-            DevTri T[BATCH];
-#pragma unroll
-            for (int e = 0; e < BATCH; ++e) T[e] = S.tris[min(k0 + e, S.n_tris - 1)];
-#pragma unroll
-            for (int e = 0; e < BATCH; ++e) {
-                if (k0 + e >= first + cnt) break;
-                ctr.tris++;
-                float t;
-                if (tri_test(T[e], o, d, S.tmin, t) && t <= bt) {
-                    const uint32_t prim = __float_as_uint(T[e].v0.w);
-                    if (anyhit && t < tmax) {
-                        best = k0 + e;
-                        return true;
-                    }
-                    if (t < bt || (t == bt && prim < best_prim)) {
-                        bt = t;
-                        best = k0 + e;
-                        best_prim = prim;
-                    }
-                }
-            }
-        }
-    }
-    return false;
-}
-
-// One node visit of a ray query: tests the node's four child boxes, tests the
-// triangles of every hit leaf child (the lanes of a wavefront loop over their
-// own hit leaves, lowest child first, four triangles' loads in flight at
-// once), and returns the hit inner children sorted near to far in kc (-1 =
-// none; a fixed sorting network keeps every index static).  Returns true when
-// an any-hit query has found its hit (slot in best).
-__device__ __forceinline__ bool visit_node(const DevScene& S, int node, V3 o, V3 d, const RaySlab& rs, float tmax, bool anyhit,
-                                           float& bt, int& best, uint32_t& best_prim, int (&kc)[4], Counters& ctr) {
-    const DevNode n = load_node(S, node);
-    ctr.nodes++;
-    // all four boxes are tested without branching (an empty slot's result is
-    // masked afterwards), so the node's eight loads issue together
-    float tn[4];
-    bool hit[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-        hit[q] = slab(f4(n.lox, q), f4(n.loy, q), f4(n.loz, q), f4(n.hix, q), f4(n.hiy, q), f4(n.hiz, q), rs, S.tmin,
-                      bt, tn[q]) &
-                 (i4(n.count, q) >= 0);
-    uint32_t leaves = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) leaves |= (hit[q] & (i4(n.count, q) > 0)) ? 1u << q : 0u;
-    // the batch size is a property of the scene (2 when no leaf holds more
-    // than 2 triangles), so the branch is uniform
-    if (S.leaf_batch == 2) {
-        if (leaf_tests<2>(S, n, leaves, o, d, tmax, anyhit, bt, best, best_prim, ctr)) return true;
-    } else {
-        if (leaf_tests<4>(S, n, leaves, o, d, tmax, anyhit, bt, best, best_prim, ctr)) return true;
-    }
-    float kt[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const bool inner = hit[q] && i4(n.count, q) == 0;
-        kt[q] = inner ? tn[q] : INFINITY;
-        kc[q] = inner ? i4(n.child, q) : -1;
-    }
-#define DR_CSWAP(i, j)                                       \
-    if (kt[j] < kt[i]) {                                     \
-        const float tt_ = kt[i]; kt[i] = kt[j]; kt[j] = tt_; \
-        const int cc_ = kc[i]; kc[i] = kc[j]; kc[j] = cc_;   \
-    }
-    DR_CSWAP(0, 1)
-    DR_CSWAP(2, 3)
-    DR_CSWAP(0, 2)
-    DR_CSWAP(1, 3)
-    DR_CSWAP(1, 2)
-#undef DR_CSWAP
-    return false;
-}
-
-// Stack step after a visit: descend into the nearest hit child and push the
-// others far-first, or pop.  Returns false when the traversal is over.
-__device__ __forceinline__ bool next_node(const int (&kc)[4], int& node, int& sp, uint32_t* stk, int stride,
-                                          int cap) {
-    if (kc[0] < 0) {
-        if (sp == 0) return false;
-        node = (int)stk[(--sp) * stride];
-    } else {
-        if (kc[3] >= 0 && sp < cap) stk[(sp++) * stride] = (uint32_t)kc[3];
-        if (kc[2] >= 0 && sp < cap) stk[(sp++) * stride] = (uint32_t)kc[2];
-        if (kc[1] >= 0 && sp < cap) stk[(sp++) * stride] = (uint32_t)kc[1];
-        node = kc[0];
-    }
-    return true;
-}
-
 // Leaf entries share the traversal stack with inner nodes: a leaf of cnt
 // triangles from slot first is stored as -1 - (first << 5 | cnt) (cnt <= 16,
 // first < 2^24), inner nodes as their index (>= 0).
