@@ -288,26 +288,17 @@ __device__ __forceinline__ void pop_entry(int& node, int& pleaf, int& sp, const 
 // tests (a postponed leaf only means fewer boxes culled meanwhile), and an
 // any-hit query only reports whether a hit exists.
 //
-// hint (a triangle slot, or -1): a candidate tested before the traversal.
-// A chain's consecutive states lie close together, so the triangle its
-// previous path hit with this ray, or the one that blocked its previous
-// shadow ray, is usually hit again.  A closest-hit query that hits the
-// candidate starts with it as the best hit, so the traversal culls every box
-// beyond it from the first visit; the result is the same closest hit (the
-// box tests are conservative, so every triangle at or before the candidate's
-// distance is still tested, and the tie rule does not depend on order).  An
-// any-hit query that hits the candidate is done.
 //
 // TWO: each lane runs a second query from the same origin (closest hit along
-// db over (tmin, inf), if b_on, with its own hint) right after its first
+// db over (tmin, inf), if b_on) right after its first
 // ends, in the same wavefront loop and on the same (then empty) stack.  The
 // wavefront then iterates as long as its longest per-lane sum of the two
 // traversals rather than the sum of the two longest, and the lanes done with
 // their first query keep working while others finish theirs.  Each query's
 // result is the one it has alone.
 template <bool TWO>
-__device__ __forceinline__ void trace_core(const DevScene& S, V3 o, V3 d, float tmax, bool anyhit, int hint, bool b_on,
-                                           V3 db, int hint_b, int& res_a, float& t_a, int& res_b, float& t_b,
+__device__ __forceinline__ void trace_core(const DevScene& S, V3 o, V3 d, float tmax, bool anyhit, bool b_on, V3 db,
+                                           int& res_a, float& t_a, int& res_b, float& t_b,
                                            uint32_t* stk, int stride, Counters& ctr) {
     float bt, qmax = tmax;
     int best, sp = 0, node = -1, pleaf = 0;
@@ -315,9 +306,8 @@ __device__ __forceinline__ void trace_core(const DevScene& S, V3 o, V3 d, float 
     bool found = false, qany = anyhit;
     V3 qd = d;
     RaySlab rs;
-    // set up one query: the hint test, then the root (node stays -1 when
-    // there is no query or the hint settles an any-hit query)
-    auto start = [&](V3 dd, float mx, bool any, int h) {
+    // set up one query at the root (node stays -1 when there is no query)
+    auto start = [&](V3 dd, float mx, bool any) {
         qd = dd;
         qmax = mx;
         qany = any;
@@ -330,28 +320,10 @@ __device__ __forceinline__ void trace_core(const DevScene& S, V3 o, V3 d, float 
         node = -1;
         if (!(mx > S.tmin)) return;
         ctr.rays++;
-        if (h >= 0 && h < S.n_tris) {
-            const DevTri T = S.tris[h];
-            float t;
-            ctr.tris++;
-            if (tri_test(T, o, dd, S.tmin, t) && t <= bt) {
-                if (any) {
-                    if (t < mx) {
-                        found = true;
-                        best = h;
-                        return;
-                    }
-                } else {
-                    bt = t;
-                    best = h;
-                    best_prim = __float_as_uint(T.v0.w);
-                }
-            }
-        }
         rs = ray_slab(o, dd);
         node = 0;
     };
-    start(d, tmax, anyhit, hint);
+    start(d, tmax, anyhit);
     int phase = 0;
     const int cap = S.stack_cap;
     while (true) {
@@ -360,7 +332,7 @@ __device__ __forceinline__ void trace_core(const DevScene& S, V3 o, V3 d, float 
             res_a = qany ? (found ? best : -1) : best;
             t_a = bt;
             phase = 1;
-            start(db, b_on ? INFINITY : -1.0f, false, hint_b);
+            start(db, b_on ? INFINITY : -1.0f, false);
         }
         const bool has_leaf = pleaf != 0, can_visit = node >= 0;
         const uint64_t ml = __ballot(has_leaf), mv = __ballot(can_visit);
@@ -439,10 +411,10 @@ __device__ __forceinline__ void trace_core(const DevScene& S, V3 o, V3 d, float 
 }
 
 __device__ int trace(const DevScene& S, V3 o, V3 d, float tmax, bool anyhit, float& t_hit, uint32_t* stk, int stride,
-                     Counters& ctr, int hint = -1) {
+                     Counters& ctr) {
     int ra, rb;
     float tb;
-    trace_core<false>(S, o, d, tmax, anyhit, hint, false, d, -1, ra, t_hit, rb, tb, stk, stride, ctr);
+    trace_core<false>(S, o, d, tmax, anyhit, false, d, ra, t_hit, rb, tb, stk, stride, ctr);
     return ra;
 }
 
@@ -651,37 +623,30 @@ __device__ __forceinline__ int swap_pair(int v) { return __builtin_amdgcn_update
 __device__ __forceinline__ float swap_pair(float v) { return __int_as_float(swap_pair(__float_as_int(v))); }
 
 // The shadow ray (any hit, up to smax) and the continuation ray (closest
-// hit) of a vertex; hint_s / hint_c: candidate triangles for each (-1: none).
-// occluder: the slot that blocked the shadow ray (-1 if none).
+// hit) of a vertex.
 template <bool PAIR>
 __device__ __forceinline__ void trace_vertex_rays(const DevScene& S, V3 x, bool shadow, V3 wl, float smax, bool cont,
-                                                  V3 wi, bool& occluded, int& occluder, int& nslot, float& tn,
-                                                  uint32_t* stk, int stride, Counters& ctr, int hint_s, int hint_c) {
+                                                  V3 wi, bool& occluded, int& nslot, float& tn, uint32_t* stk,
+                                                  int stride, Counters& ctr) {
     if (PAIR) {
         const bool odd = (threadIdx.x & 1) != 0;
         float tt;
         const int r = trace(S, x, odd ? wl : wi, odd ? (shadow ? smax : -1.0f) : (cont ? INFINITY : -1.0f), odd, tt,
-                            stk, stride, ctr, odd ? hint_s : hint_c);
+                            stk, stride, ctr);
         const int ro = swap_pair(r);
         const float to = swap_pair(tt);
-        occluder = shadow ? (odd ? r : ro) : -1;
-        occluded = occluder >= 0;
+        occluded = shadow && (odd ? r : ro) >= 0;
         nslot = cont ? (odd ? ro : r) : -1;
         tn = odd ? to : tt;
     } else {
         // the shadow query, then the continuation, back to back in one loop
         float ts;
         int ra, rb;
-        trace_core<true>(S, x, wl, shadow ? smax : -1.0f, true, hint_s, cont, wi, hint_c, ra, ts, rb, tn, stk, stride,
-                         ctr);
-        occluder = shadow ? ra : -1;
-        occluded = occluder >= 0;
+        trace_core<true>(S, x, wl, shadow ? smax : -1.0f, true, cont, wi, ra, ts, rb, tn, stk, stride, ctr);
+        occluded = shadow && ra >= 0;
         nslot = cont ? rb : -1;
     }
 }
-
-// Candidate slot from a record entry (rec or occ), -1 if it holds none.
-__device__ __forceinline__ int hint_slot(uint32_t r) { return r == DR_NO_VERTEX ? -1 : (int)(r >> 8); }
 
 // True when every coordinate of the point is finite (accessors over generated
 // coordinates skip the check).
@@ -696,14 +661,9 @@ __device__ __forceinline__ bool point_finite(const U& u, int d) {
     }
 }
 
-// occ (nullable, same layout as rec): per vertex, the slot that blocked its
-// shadow ray (<< 8) or DR_NO_VERTEX, written when the shadow ray is traced.
-// hint: the record rec and occ of this point hold the path of a nearby point
-// (the chain's previous state); their triangles are tried first by the ray
-// queries (results do not depend on it).
 template <bool PAIR, bool DELTA = true, class U>
 __device__ V3 path_forward(const DevScene& S, int L, const U& u, uint32_t* rec, int rs, uint32_t* stk, int stride,
-                           Counters& ctr, int* nverts = nullptr, uint32_t* occ = nullptr, bool hint = false) {
+                           Counters& ctr, int* nverts = nullptr) {
     V3 f = v3(0.f, 0.f, 0.f);
     // a point with a non-finite coordinate (a state that left the torus) has
     // f = 0: its tour is killed and regenerates
@@ -717,16 +677,15 @@ __device__ V3 path_forward(const DevScene& S, int L, const U& u, uint32_t* rec, 
     V3 d = camera_dir(C, u(0), u(1));
     float t;
     int slot;
-    const int hint0 = hint && rec ? hint_slot(rec[0]) : -1;
     if (PAIR) {
         const bool odd = (threadIdx.x & 1) != 0;
-        const int r = trace(S, C.eye, d, odd ? -1.0f : INFINITY, false, t, stk, stride, ctr, hint0);
+        const int r = trace(S, C.eye, d, odd ? -1.0f : INFINITY, false, t, stk, stride, ctr);
         slot = swap_pair(r);
         const float to = swap_pair(t);
         if (!odd) slot = r;
         else t = to;
     } else {
-        slot = trace(S, C.eye, d, INFINITY, false, t, stk, stride, ctr, hint0);
+        slot = trace(S, C.eye, d, INFINITY, false, t, stk, stride, ctr);
     }
     int j = 1;
     if (slot >= 0) {
@@ -769,13 +728,9 @@ __device__ V3 path_forward(const DevScene& S, int L, const U& u, uint32_t* rec, 
                 else cont = bsdf_sample(m, n, wo, u(4 * j), u(4 * j + 1), wi, wt);
             }
             bool occluded;
-            int occluder, ns;
+            int ns;
             float tn;
-            const int hs = hint && occ && shadow ? hint_slot(occ[(j - 1) * rs]) : -1;
-            const int hc = hint && rec && cont ? hint_slot(rec[j * rs]) : -1;
-            trace_vertex_rays<PAIR>(S, x, shadow, wl, (1.0f - 1e-4f) * r, cont, wi, occluded, occluder, ns, tn, stk,
-                                    stride, ctr, hs, hc);
-            if (occ && shadow) occ[(j - 1) * rs] = occluder >= 0 ? ((uint32_t)occluder << 8) : DR_NO_VERTEX;
+            trace_vertex_rays<PAIR>(S, x, shadow, wl, (1.0f - 1e-4f) * r, cont, wi, occluded, ns, tn, stk, stride, ctr);
             const bool contrib = shadow && !occluded;
             if (rec)
                 rec[(j - 1) * rs] = ((uint32_t)slot << 8) | ((uint32_t)(delta ? max(lobe, 0) : li) << 1) |

@@ -29,7 +29,6 @@ struct KBufs {
     float* score;        // d x N
     uint32_t* killed;    // N
     uint32_t* rec;       // (L-1) x N, triangle slots
-    uint32_t* occ;       // (L-1) x N, slot that blocked each vertex's shadow ray (hints for the next step)
     float* accum;        // 3 x W*H, sum of (w/dt) f/p
     unsigned long long* ctr;  // [0] tours, [1] chain steps, [2] rays, [3] nodes, [4] tris, [5] adjoints
     float* k0;           // device scalar (float) ; k0d at ((double*)k0ptr)
@@ -57,7 +56,7 @@ struct KBufs {
     uint32_t* key;
     uint32_t* order;
     uint32_t* bins;
-    uint32_t* state;  // rows: x[d], score[d], rec[L-1], occ[L-1], killed, ids, then the record rows p, w, pix, f[3]
+    uint32_t* state;  // rows: x[d], score[d], rec[L-1], killed, ids, then the record rows p, w, pix, f[3]
     // ray waves (the wavefront form of a path pass): per slot the path state
     // between ray queries (DR_WF_ROWS rows), the pending ray (o, tmax | d,
     // anyhit), its answer, and two queues of slots with a ray in flight
@@ -200,9 +199,7 @@ __device__ __forceinline__ void step_fused_body(const KParams& P, const DevScene
             else move(P.seed, P.d, P.N, P.stddev, P.gt, xc, B.score + c, B.sigma ? B.sigma + id : nullptr, id, s);
             const SoaU u{xc, P.N};
             int nv;
-            // a moved chain's previous path is a hint for this one
-            const V3 f = path_forward<PAIR, DELTA>(S, L, u, B.rec + c, P.N, stk, stride, ctr, &nv, B.occ + c,
-                                                   !was_killed);
+            const V3 f = path_forward<PAIR, DELTA>(S, L, u, B.rec + c, P.N, stk, stride, ctr, &nv);
             const float p = lum(f);
             const uint32_t pix = pixel_of(S, xc[0], xc[P.N]);
             const bool alive = hold_kill_splat(P, B, S, c, id, s, k0, f, p, pix, lead);
@@ -385,8 +382,7 @@ __global__ void __launch_bounds__(256) k_plain_score(KParams P, DevScene S, KBuf
     uint32_t adj = 0;
     if (c < P.N && !B.killed[c]) {
         const SoaU u{B.x + c, P.N};
-        const V3 f = path_forward<false>(S, L, u, B.rec + c, P.N, s_stack + threadIdx.x, blockDim.x, ctr, nullptr,
-                                         B.occ + c, true);
+        const V3 f = path_forward<false>(S, L, u, B.rec + c, P.N, s_stack + threadIdx.x, blockDim.x, ctr);
         score_at<L>(P, B, S, c, lum(f));
         adj = 1;
     }
@@ -681,8 +677,6 @@ __global__ void __launch_bounds__(256) k_wf_init_event(KParams P, DevScene S, KB
         RayQ q;
         q.best = B.wf_hit[c];
         q.bt = B.wf_t[c];
-        if (ps.phase == PH_SHADOW)  // the blocker is the next step's candidate for this shadow ray
-            B.occ[(size_t)(ps.j - 1) * P.N + c] = q.best >= 0 ? ((uint32_t)q.best << 8) : DR_NO_VERTEX;
         const Cam C = load_cam(S);
         ray = sm_event<L, DELTA>(S, C, SoaU{B.x + c, P.N}, ps, q, init_rec<L>(B, S, P.N, c), ctr);
         if (ray) {

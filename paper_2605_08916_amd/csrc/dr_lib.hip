@@ -84,8 +84,7 @@ __global__ void __launch_bounds__(256) k_init_eval(KParams P, DevScene S, KBufs 
         if (c >= P.N) continue;
         regen(P.seed, P.d, P.N, B.x + c, c, s0);
         int nv;
-        const V3 f = path_forward<false, DELTA>(S, P.L, SoaU{B.x + c, P.N}, B.rec + c, P.N, stk, blockDim.x, ctr, &nv,
-                                                B.occ + c, false);
+        const V3 f = path_forward<false, DELTA>(S, P.L, SoaU{B.x + c, P.N}, B.rec + c, P.N, stk, blockDim.x, ctr, &nv);
         B.p_tmp[c] = lum(f);
         B.f_tmp[c] = f.x;
         B.f_tmp[(size_t)P.N + c] = f.y;
@@ -226,9 +225,8 @@ __global__ void __launch_bounds__(256) k_plain_forward(KParams P, DevScene S, KB
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     Counters ctr = {0, 0, 0};
     if (c < P.N) {
-        // killed chains were regenerated by the move pass: their record is no hint
         const V3 f = path_forward<false>(S, P.L, SoaU{B.x + c, P.N}, B.rec + c, P.N, s_stack + threadIdx.x, blockDim.x,
-                                         ctr, nullptr, B.occ + c, B.killed[c] == 0);
+                                         ctr);
         B.p_tmp[c] = lum(f);
         B.f_tmp[c] = f.x;
         B.f_tmp[(size_t)P.N + c] = f.y;
@@ -493,8 +491,6 @@ static void enqueue_init(dr_chains* c, uint32_t frame, int from_device, hipStrea
     hipLaunchKernelGGL(k_begin_init, dim3(1), dim3(64), 0, st, c->kb, frame, from_device);
     hipLaunchKernelGGL(k_fill_f32, dim3(1024), dim3(256), 0, st, c->kb.accum, 3 * npx);
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, c->kb.ctr, (int)C_N);
-    // no blocked shadow rays recorded yet (the hints of the first step)
-    hipLaunchKernelGGL(k_fill_u32, dim3(1024), dim3(256), 0, st, c->kb.occ, (size_t)(c->kp.L - 1) * N, DR_NO_VERTEX);
     // the init kernel runs 256-thread blocks, one lane per chain, three
     // wavefronts per SIMD: it always takes the automatic cache for that shape
     DevScene S = c->scene->ds;
@@ -1036,7 +1032,7 @@ dr_status dr_chains_init(dr_scene* s, const dr_params* p, uint64_t seed, uint32_
     void* q;
     bool ok = true;
     auto get = [&](void** ptr, size_t bytes) { if (ok && c->mem.get(ptr, bytes) != hipSuccess) ok = false; };
-    c->rows_move = 2 * d + 2 * (L - 1) + 2;
+    c->rows_move = 2 * d + (L - 1) + 2;
     c->rows_all = c->rows_move + 6;
     get(&q, sizeof(uint32_t) * c->rows_all * (size_t)N); B.state = (uint32_t*)q;
     get(&q, sizeof(uint32_t) * c->rows_all * (size_t)N); B.alt = (uint32_t*)q;
@@ -1045,7 +1041,6 @@ dr_status dr_chains_init(dr_scene* s, const dr_params* p, uint64_t seed, uint32_
         B.x = (float*)r; r += (size_t)d * N;
         B.score = (float*)r; r += (size_t)d * N;
         B.rec = r; r += (size_t)(L - 1) * N;
-        B.occ = r; r += (size_t)(L - 1) * N;
         B.killed = r; r += N;
         B.ids = r; r += N;
         B.p_tmp = (float*)r; r += N;
