@@ -190,8 +190,10 @@ __device__ __forceinline__ bool tri_test(const DevTri& T, V3 o, V3 d, float tmin
 // The first S.n_top nodes (the top levels: nodes are stored breadth-first)
 // may sit at the start of the kernel's dynamic LDS, copied there by the
 // kernel; every ray starts at the root, so its first visits read LDS.  The
-// two sources are separate branches (LDS reads and global loads) rather than
-// one generic pointer, which would compile to flat loads.
+// compiler merges the two branches into one generic (flat) load per 16
+// bytes.  Loads through address-space-qualified pointers keep them apart (LDS
+// and global instructions) but cost registers and measured 1-2% slower in the
+// one-lane kernels, so the plain form stays.
 __device__ __forceinline__ DevNode load_node(const DevScene& S, int i) {
     extern __shared__ float4 s_dyn[];
     DevNode n;
