@@ -490,26 +490,30 @@ class Refs:
 
 
 def realtime_loop(torch, dr, scene, cams, N, L, K, W, mode, frame_steps=None, refs=None, mrse_frames=(),
-                  seed=2024, budget_ms=33.3, tune=True):
+                  seed=2024, budget_ms=33.3, tune=True, init_refill=None):
     """The real-time loop: one captured frame graph (re-initialise for the
     new camera, n evolve steps, resolve), replayed once per displayed frame
     along the camera path.  n = frame_steps, or as many steps as fit the
     frame budget after the re-initialisation and the resolve (at least 1).
     Everything runs on one stream of its own (the library calls take torch's
-    current stream)."""
+    current stream).  init_refill (1 on, 2 off) sets the initialise pass's
+    form before the autotuner (which may change it) runs."""
     stream = torch.cuda.Stream()
     img = torch.zeros((3, scene.W * scene.H), device="cuda", dtype=torch.float32)
     scene.set_camera(cams[0])
     tuned = None
     with torch.cuda.stream(stream):
         ch = dr.Chains(scene, N, L, seed, mode=mode)
+        if init_refill:
+            ch.set_launch(init_refill=init_refill)
         if tune and mode == dr.DR_MODE_FUSED:
             # the launch autotuner on the live chains (they are re-initialised next)
             from paper_2605_08916_amd import autotune
             t = autotune.tune(ch, reps=2, use_cache=False, per_launch=frame_steps or 1, restore=False,
                               keep_within=0.03)
+            ti = autotune.tune_init(ch)
             tuned = {"cfg": t["cfg"], "ms_per_step": t["ms"], "default_ms_per_step": t["current_ms"],
-                     "candidates": len(t["sweep"])}
+                     "candidates": len(t["sweep"]), "init_ms": ti}
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         for rep in range(2):  # the second pass is the calibration
             ev[0].record(stream)
@@ -639,8 +643,10 @@ def realtime_line(a, torch, dr, inputs):
     # (identical decisions from identical streams, so the same image: the
     # frame-time ratio is the speed ratio at equal MRSE)
     if not a.no_plain:
+        # the same initialise form as the fused loop: the frames differ only in the steps
+        irf = (rt.get("autotune") or {}).get("init_ms", {}).get("init_refill")
         pr, cp, _ = realtime_loop(torch, dr, scene, cams, N, L, min(K, 4), 1, dr.DR_MODE_PLAIN, n, refs,
-                                  mrse_frames[:2])
+                                  mrse_frames[:2], init_refill=irf)
         cp.close()
         res["plain"] = pr
         res["fused_over_plain"] = pr["ms_per_frame"] / rt["ms_per_frame"]

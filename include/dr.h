@@ -284,13 +284,18 @@ dr_status dr_stats(dr_chains* c, dr_counters* out, void* hip_stream);
  * alternating launches of a traversal kernel whose persistent lanes take
  * the next pending ray as theirs finishes, and an event kernel that shades
  * each path's vertex and issues its next ray - instead of one lane
- * following one path; 2: off).
+ * following one path; 2: off), and init_refill (1: the initialise pass
+ * evaluates its paths with the ray-refill state machine - a lane whose ray or
+ * path ends takes its next event or chain while the others keep traversing,
+ * events run once three quarters of the busy lanes wait for one; takes
+ * precedence over wavefront; 2: off).
  * Zeros keep the current
  * value.  Defaults: 256 threads, 4 blocks per compute unit, 1 chain per pop,
  * 2 lanes per chain when n_chains is below two wavefronts per SIMD
  * (n_cu * 512) else 1, sorting off (it pays only when chains outnumber the
  * resident lanes several times over), refill off, thresholds 50 and 50,
- * tile ordering off, automatic node cache, ray waves off (on the scenes
+ * tile ordering off, automatic node cache, straight-line initialise pass
+ * (init_refill off), ray waves off (on the scenes
  * measured here the state round trips between the two kernels cost more than
  * the denser traversal saves).  The form, the ray waves and the order in which chains are processed never change results. */
 #define DR_NODE_CACHE_AUTO 0xFFFFFFFFu
@@ -306,6 +311,7 @@ typedef struct {
     uint32_t sort_by_tile;
     uint32_t node_cache;
     uint32_t wavefront;
+    uint32_t init_refill;
 } dr_launch_cfg;
 dr_status dr_chains_set_launch(dr_chains* c, const dr_launch_cfg* cfg);
 dr_status dr_chains_get_launch(dr_chains* c, dr_launch_cfg* cfg);

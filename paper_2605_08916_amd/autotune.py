@@ -103,6 +103,28 @@ def staged_candidates(ch: "dr.Chains", timer) -> list:
     return results
 
 
+def tune_init(ch: "dr.Chains", reps: int = 2, frame0: int = 1 << 20) -> dict:
+    """Time the initialise pass in its straight-line and ray-refill forms on
+    the live chains (it re-initialises them) and apply the faster."""
+    import torch
+    s = torch.cuda.current_stream()
+    out = {}
+    for rf in (2, 1):
+        ch.set_launch(init_refill=rf)
+        ch.reinit(frame0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for r in range(reps):
+            ch.reinit(frame0 + 1 + r)
+        e1.record(s)
+        torch.cuda.synchronize()
+        out["refill" if rf == 1 else "straight"] = e0.elapsed_time(e1) / reps
+    best = 1 if out["refill"] < out["straight"] else 2
+    ch.set_launch(init_refill=best)
+    out["init_refill"] = best
+    return out
+
+
 def tune(ch: "dr.Chains", reps: int = 3, use_cache: bool = True, verbose: bool = False, per_launch: int = 8,
          exhaustive: bool = False, restore: bool = True, keep_within: float = 0.0) -> dict:
     """Pick and apply the fastest launch configuration for this chain set
@@ -120,7 +142,7 @@ def tune(ch: "dr.Chains", reps: int = 3, use_cache: bool = True, verbose: bool =
     snap = ch.read_state() if restore else None
     full = dict(sort_by_length=2, sort_by_tile=2, refill=2, grab=1, node_cache=dr.DR_NODE_CACHE_AUTO,
                 refill_event_pct=50, refill_advance_pct=50)
-    flags = ("sort_by_length", "sort_by_tile", "refill", "wavefront")  # read back as 1/0, requested as 1 on / 2 off
+    flags = ("sort_by_length", "sort_by_tile", "refill", "wavefront", "init_refill")  # read back 1/0, requested 1 on / 2 off
     current = {k: ((1 if v else 2) if k in flags else v) for k, v in ch.get_launch().items()}
     ch.set_launch(**current)
     current_ms = _time(ch, reps, per_launch)

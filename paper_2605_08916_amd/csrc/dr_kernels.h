@@ -580,6 +580,70 @@ __device__ __forceinline__ InitRec<L> init_rec(const KBufs& B, const DevScene& S
     return InitRec<L>{B.rec, B.pix_tmp, B.key, B.ids, B.p_tmp, B.f_tmp, B.x, N, c, S.W, S.H};
 }
 
+// Initialise pass, path evaluation with the ray-refill state machine
+// (persistent): a lane takes the next chain from the work queue, draws x ~ mu
+// and follows the chain's path one event at a time; events (shade a hit,
+// issue the next ray, or end the path and store p, f, the pixel and the
+// record) run once thresh percent of the busy lanes wait for one, otherwise
+// the lanes with a ray in flight take one traversal step.  A lane whose ray
+// or path ends takes new work while the others keep traversing.  The same
+// arithmetic as k_init_eval, so the same state.
+template <int L, bool DELTA>
+__global__ void __launch_bounds__(256) k_init_sm(KParams P, DevScene S, KBufs B, int thresh) {
+    extern __shared__ uint32_t s_stack[];
+    cache_top_nodes(S);  // the top nodes precede the stacks in LDS
+    uint32_t* stk = s_stack + S.n_top * 32 + threadIdx.x;
+    const int stride = blockDim.x;
+    const int lane = threadIdx.x & 63;
+    const uint64_t s0 = B.steps[1];
+    const Cam C = load_cam(S);
+    Counters ctr = {0, 0, 0};
+    RayQ q;
+    PathSM ps;
+    ps.phase = PH_NEW;
+    int c = -1;
+    bool tracing = false, drained = false;
+    while (true) {
+        const bool need = !drained && c < 0;
+        const uint64_t nm = __ballot(need);
+        if (nm) {
+            const int leader = __ffsll((long long)nm) - 1;
+            uint32_t base = 0;
+            if (lane == leader) base = atomicAdd(B.queue, (uint32_t)__popcll(nm));
+            base = __shfl(base, leader);
+            if (need) {
+                const uint32_t it = base + (uint32_t)__popcll(nm & ((1ull << lane) - 1ull));
+                if (it < (uint32_t)P.N) {
+                    c = (int)it;
+                    regen(P.seed, P.d, P.N, B.x + c, c, s0);
+                    ps.phase = PH_NEW;
+                } else {
+                    drained = true;
+                }
+            }
+        }
+        const bool ev = !drained && !tracing;
+        const uint64_t em = __ballot(ev), tm = __ballot(tracing);
+        if (!em && !tm) break;
+        const int nev = __popcll(em), ntr = __popcll(tm);
+        if (nev && (!ntr || 100 * nev >= thresh * (nev + ntr))) {
+            if (ev) {
+                tracing = sm_event<L, DELTA>(S, C, SoaU{B.x + c, P.N}, ps, q, init_rec<L>(B, S, P.N, c), ctr);
+                if (!tracing) c = -1;
+            }
+        } else {
+            uint64_t ml, mv;
+            ray_masks(q, tracing, ml, mv);
+            if (tracing && ray_step(S, q, stk, stride, ctr, ml, mv)) tracing = false;
+        }
+    }
+    if (P.count) {
+        wave_add(&B.ctr[C_RAYS], ctr.rays);
+        wave_add(&B.ctr[C_NODES], ctr.nodes);
+        wave_add(&B.ctr[C_TRIS], ctr.tris);
+    }
+}
+
 // Initialise pass, first wave: x ~ mu and the camera ray of every chain.
 template <int L, bool DELTA>
 __global__ void __launch_bounds__(256) k_wf_init_begin(KParams P, DevScene S, KBufs B) {
@@ -738,6 +802,14 @@ void launch_eval(dim3 g, dim3 b, hipStream_t st, const DevScene& S, const float*
     hipLaunchKernelGGL(k_eval<L>, g, b, stack_bytes(S, b.x), st, S, u, n, eps, fo, logp, grad, rs, ro);
 }
 
+template <int L>
+void launch_init_sm(dim3 g, dim3 b, hipStream_t st, const KParams& P, const DevScene& S, const KBufs& B, int thresh,
+                    bool delta) {
+    const size_t lds = stack_bytes(S, b.x) + (size_t)S.n_top * sizeof(DevNode);
+    if (delta) hipLaunchKernelGGL((k_init_sm<L, true>), g, b, lds, st, P, S, B, thresh);
+    else hipLaunchKernelGGL((k_init_sm<L, false>), g, b, lds, st, P, S, B, thresh);
+}
+
 // The initialise pass's path evaluation as ray waves: the first wave, then
 // 2(L-1) rounds of traversal and events (a path issues at most that many
 // rays after its camera ray).  Graph-capturable: a fixed number of launches,
@@ -774,4 +846,5 @@ void launch_wf_init(dim3 g, dim3 b, int trace_blocks, hipStream_t st, const KPar
     X template void launch_eval<L>(dim3, dim3, hipStream_t, const DevScene&, const float*, int, float, float*, float*, \
                                    float*, uint32_t*, uint32_t*);                                                  \
     X template void launch_wf_init<L>(dim3, dim3, int, hipStream_t, const KParams&, const DevScene&, const DevScene&, \
-                                      const KBufs&, bool);
+                                      const KBufs&, bool);                                                          \
+    X template void launch_init_sm<L>(dim3, dim3, hipStream_t, const KParams&, const DevScene&, const KBufs&, int, bool);

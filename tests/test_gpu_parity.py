@@ -801,24 +801,26 @@ def test_node_cache_does_not_change_results(scenes, lanes):
 @pytest.mark.parametrize("which,L,N", [("tiny", 4, 3000), ("spheres_small", 8, 20000), ("specular", 8, 20000)])
 def test_wavefront_init_matches_straight_line(scenes, which, L, N):
     """The initialise pass evaluated as ray waves (traversal and event
-    kernels alternating) leaves exactly the state the one-lane kernel does:
+    kernels alternating) or with the ray-refill state machine leaves exactly
+    the state the one-lane kernel does:
     positions, kill decisions, p, f/p, pixels, path records, scores, k0 and
     the tour count; the frame buffers differ only by the atomics' order."""
-    say(f"[wavefront init] scene={which} L={L} N={N}")
+    say(f"[wavefront and refill init] scene={which} L={L} N={N}")
     S = dr.Scene(scenes[which])
     out = []
-    for wf in (2, 1):
+    for wf, rf in ((2, 2), (1, 2), (2, 1)):
         ch = dr.Chains(S, N, L, 31, frame=2)
-        ch.set_launch(wavefront=wf)
+        ch.set_launch(wavefront=wf, init_refill=rf)
         ch.set_record(True)
         ch.reinit(5)
         out.append(ch.read_state())
         ch.close()
-    a, b = out
-    for k in ("x", "killed", "p", "pixel", "f_over_p", "path_rec", "score", "weight"):
-        assert np.array_equal(a[k], b[k]), k
-    assert a["k0"] == b["k0"] and a["tour_count"] == b["tour_count"]
-    assert np.allclose(a["accum"], b["accum"], rtol=1e-5, atol=0)
+    a = out[0]
+    for b in out[1:]:
+        for k in ("x", "killed", "p", "pixel", "f_over_p", "path_rec", "score", "weight"):
+            assert np.array_equal(a[k], b[k]), k
+        assert a["k0"] == b["k0"] and a["tour_count"] == b["tour_count"]
+        assert np.allclose(a["accum"], b["accum"], rtol=1e-5, atol=0)
 
 
 @pytest.mark.parametrize("order", ["none", "length", "tile"])
@@ -1047,7 +1049,7 @@ def test_autotune_restores_chains(scenes, tmp_path, monkeypatch):
     a.step(2)
     b.step(2)
     entry = autotune.tune(a, reps=1, use_cache=True, per_launch=2)
-    flags = ("sort_by_length", "sort_by_tile", "refill", "wavefront")  # 1 on, 2 off in a request; 1/0 when read back
+    flags = ("sort_by_length", "sort_by_tile", "refill", "wavefront", "init_refill")  # 1 on, 2 off; 1/0 read back
     applied = {k: (int(v == 1) if k in flags else v) for k, v in entry["cfg"].items()}
     got = a.get_launch()
     assert {k: got[k] for k in applied} == applied
