@@ -892,17 +892,24 @@ def test_large_configs_sampled_parity(orc, name):
     _compare_step(orc, sc, L, st, gs, os_, idx, 91, step0, 100.0)
 
 
-@pytest.mark.parametrize("which", ["interior", "specular"])
+@pytest.mark.parametrize("which", ["interior", "specular", "c4"])
 def test_adjoint_long_paths_with_segment_recompute(orc, which):
     """Path length 16 (d = 60): the adjoint keeps one checkpoint per 8-vertex
     segment and recomputes each segment in the reverse sweep (through delta
     vertices too, in the specular box).  Checked against the oracle's
-    forward-mode score and central differences (h = 1e-3) on the device."""
+    forward-mode score and central differences (h = 1e-3) on the device, for
+    every coordinate.  "c4" is the differentiation-stress configuration
+    itself: the 53k-triangle spheres at 1920x1080 with 4,096 sampled chain
+    states (initialised chains are uniform points of the torus)."""
+    n = 1024
     if which == "interior":
         sc = inputs.procedural_interior(n_inst=40, subdiv=3, width=320, height=180)
+    elif which == "c4":
+        sc = inputs.CONFIGS["spheres_1080p_L16"][0]()
+        n = 4096
     else:
         sc = inputs.specular_box(width=128, height=128)
-    L, n, h = 16, 1024, 1e-3
+    L, h = 16, 1e-3
     d = 4 * (L - 1)
     say(f"[adjoint L16] {sc['indices'].shape[0]} triangles, n={n}")
     u, (f, logp, g), (fo, po, go), match = _eval_both(orc, sc, L, n, seed=12)
@@ -916,7 +923,8 @@ def test_adjoint_long_paths_with_segment_recompute(orc, which):
     # long paths: some samples reach the second 8-vertex segment
     nverts = (r0 != -1).sum(1).cpu().numpy()
     say(f"  samples with more than 8 vertices: {(nverts > 8).sum()}")
-    assert (nverts > 8).sum() > 20
+    # the open spheres scene lets most paths escape early; the closed scenes exercise the recompute more
+    assert (nverts > 8).sum() > (10 if which == "c4" else 20)
     checked = bad = 0
     for i in range(d):
         e = torch.zeros_like(ut)
@@ -930,7 +938,7 @@ def test_adjoint_long_paths_with_segment_recompute(orc, which):
         checked += same.sum()
         bad += (same & (np.abs(fd - g[:, i]) > tol)).sum()
     say(f"  FD checked {checked}, outside tolerance {bad}")
-    assert checked > 5000 and bad <= 0.01 * checked
+    assert checked > 5000 * n // 1024 and bad <= 0.01 * checked
 
 
 def test_delta_closed_forms_on_device():
