@@ -273,7 +273,7 @@ __device__ __forceinline__ void pop_entry(int& node, int& pleaf, int& sp, const 
     else ++sp;
 }
 
-#define DR_LEAF_PCT 50  // leaf round once this share of the wavefront's busy lanes hold a pending leaf
+#define DR_LEAF_PCT 40  // leaf round once this share of the wavefront's busy lanes hold a pending leaf
 
 // One ray query over (tmin, tmax): the closest hit (ties in t go to the lower
 // input triangle index) or, with anyhit, the first hit found.  Returns the
