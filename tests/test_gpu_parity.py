@@ -823,6 +823,30 @@ def test_wavefront_init_matches_straight_line(scenes, which, L, N):
         assert np.allclose(a["accum"], b["accum"], rtol=1e-5, atol=0)
 
 
+@pytest.mark.parametrize("N", [1, 63, 65, 257])
+def test_init_forms_with_ragged_chain_counts(scenes, N):
+    """Chain counts below, just under and just over one wavefront (and a
+    ragged multiple of a block): the persistent straight-line, ray-refill and
+    ray-wave initialise passes give the same state, and every chain holds a
+    finite p and a pixel inside the image."""
+    say(f"[ragged init] N={N}")
+    S = dr.Scene(scenes["spheres_small"])
+    out = []
+    for wf, rf in ((2, 2), (2, 1), (1, 2)):
+        ch = dr.Chains(S, N, 8, 77, frame=1)
+        ch.set_launch(wavefront=wf, init_refill=rf)
+        ch.set_record(True)
+        ch.reinit(3)
+        out.append(ch.read_state())
+        ch.close()
+    a = out[0]
+    assert np.all(np.isfinite(a["p"])) and np.all(a["pixel"] < 128 * 128)
+    for b in out[1:]:
+        for k in ("x", "killed", "p", "pixel", "f_over_p", "path_rec", "score", "weight"):
+            assert np.array_equal(a[k], b[k]), k
+        assert a["k0"] == b["k0"] and a["tour_count"] == b["tour_count"]
+
+
 @pytest.mark.parametrize("order", ["none", "length", "tile"])
 def test_captured_frames_replay_like_eager(scenes, order):
     """A captured frame (re-init + n steps + resolve) replayed several times,
