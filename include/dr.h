@@ -284,7 +284,9 @@ dr_status dr_stats(dr_chains* c, dr_counters* out, void* hip_stream);
  * alternating launches of a traversal kernel whose persistent lanes take
  * the next pending ray as theirs finishes, and an event kernel that shades
  * each path's vertex and issues its next ray - instead of one lane
- * following one path; 2: off), and init_refill (1: the initialise pass
+ * following one path; 2: off; turning it on allocates its buffers the first
+ * time, about 180 bytes per chain, DR_ERR_OUT_OF_MEMORY if that fails, with
+ * no field changed), and init_refill (1: the initialise pass
  * evaluates its paths with the ray-refill state machine - a lane whose ray or
  * path ends takes its next event or chain while the others keep traversing,
  * events run once three quarters of the busy lanes wait for one; takes

@@ -482,6 +482,29 @@ static int node_cache_size(const dr_chains* c, int blk, bool pair, uint32_t nc) 
 // 2M-triangle scenes.
 #define DR_INIT_EVENT_PCT 75
 
+// Buffers of the ray-wave initialise form (path states, pending rays, their
+// answers, two slot queues): allocated the first time the form is selected.
+static hipError_t ensure_wf_buffers(dr_chains* c) {
+    if (c->kb.wf) return hipSuccess;
+    const size_t N = (size_t)c->kp.N;
+    void *a = nullptr, *r = nullptr, *h = nullptr, *t = nullptr, *q = nullptr, *n = nullptr;
+    hipError_t e = c->mem.get(&a, sizeof(uint32_t) * DR_WF_ROWS * N);
+    if (e == hipSuccess) e = c->mem.get(&r, sizeof(float4) * 2 * N);
+    if (e == hipSuccess) e = c->mem.get(&h, sizeof(int) * N);
+    if (e == hipSuccess) e = c->mem.get(&t, sizeof(float) * N);
+    if (e == hipSuccess) e = c->mem.get(&q, sizeof(uint32_t) * 2 * N);
+    if (e == hipSuccess) e = c->mem.get(&n, 64);
+    if (e != hipSuccess) return e;
+    KBufs& B = c->kb;
+    B.wf_ray = (float4*)r;
+    B.wf_hit = (int*)h;
+    B.wf_t = (float*)t;
+    B.wf_q = (uint32_t*)q;
+    B.wf_cnt = (uint32_t*)n;
+    B.wf = (uint32_t*)a;  // last: marks the set complete
+    return hipSuccess;
+}
+
 // Enqueue the initialise pass (Alg. 4.1).  from_device: take the frame index
 // from the device frame counter plus one (used inside captured frames).
 static void enqueue_init(dr_chains* c, uint32_t frame, int from_device, hipStream_t st) {
@@ -505,7 +528,7 @@ static void enqueue_init(dr_chains* c, uint32_t frame, int from_device, hipStrea
         // extra ones find the queue drained)
         const dim3 gp((unsigned)std::max(1L, std::min((long)g.x, (long)c->n_cu * 4)));
         DR_DISPATCH_L(c->kp.L, launch_init_sm, gp, b, st, P, S, c->kb, DR_INIT_EVENT_PCT, c->scene->has_delta);
-    } else if (c->launch.wavefront) {
+    } else if (c->launch.wavefront && c->kb.wf) {
         // ray waves: persistent traversal blocks (more than fit at once; the
         // extra ones find the queue drained)
         DR_DISPATCH_L(c->kp.L, launch_wf_init, g, b, c->n_cu * 4, st, P, c->scene->ds, S, c->kb,
@@ -1068,12 +1091,7 @@ dr_status dr_chains_init(dr_scene* s, const dr_params* p, uint64_t seed, uint32_
     get(&q, sizeof(uint32_t) * N); B.key = (uint32_t*)q;
     get(&q, sizeof(uint32_t) * N); B.order = (uint32_t*)q;
     get(&q, sizeof(uint32_t) * 2 * DR_TILE_BINS); B.bins = (uint32_t*)q;
-    get(&q, sizeof(uint32_t) * DR_WF_ROWS * (size_t)N); B.wf = (uint32_t*)q;
-    get(&q, sizeof(float4) * 2 * (size_t)N); B.wf_ray = (float4*)q;
-    get(&q, sizeof(int) * (size_t)N); B.wf_hit = (int*)q;
-    get(&q, sizeof(float) * (size_t)N); B.wf_t = (float*)q;
-    get(&q, sizeof(uint32_t) * 2 * (size_t)N); B.wf_q = (uint32_t*)q;
-    get(&q, 64); B.wf_cnt = (uint32_t*)q;
+    B.wf = nullptr;  // the ray-wave buffers are allocated when that form is first selected
     B.sigma = p->sigma_diag;
     if (!ok) {
         c->mem.release();
@@ -1281,6 +1299,12 @@ dr_status dr_chains_set_launch(dr_chains* c, const dr_launch_cfg* cfg) {
         return fail(DR_ERR_INVALID_ARG, "dr_chains_set_launch: node_cache must be at most 512 (or automatic)");
     if (cfg->refill_event_pct > 100 || cfg->refill_advance_pct > 100)
         return fail(DR_ERR_INVALID_ARG, "dr_chains_set_launch: refill thresholds are percentages (1..100)");
+    // the one request that allocates, before any field changes (a failed call changes nothing)
+    if (cfg->wavefront == 1) {
+        HIP_TRY(hipSetDevice(c->scene->device));
+        if (ensure_wf_buffers(c) != hipSuccess)
+            return fail(DR_ERR_OUT_OF_MEMORY, "dr_chains_set_launch: ray-wave buffer allocation failed");
+    }
     if (cfg->block) c->launch.block = cfg->block;
     if (cfg->blocks_per_cu) c->launch.blocks_per_cu = cfg->blocks_per_cu;
     if (cfg->grab) c->launch.grab = cfg->grab;
