@@ -276,10 +276,11 @@ __device__ __forceinline__ void pop_entry(int& node, int& pleaf, int& sp, const 
 #define DR_LEAF_PCT 40  // leaf round once this share of the wavefront's busy lanes hold a pending leaf
 
 // One ray query over (tmin, tmax): the closest hit (ties in t go to the lower
-// input triangle index) or, with anyhit, the first hit found.  Returns the
-// triangle slot (leaf order) or -1; tmax <= tmin means "no ray" and returns -1
-// at once (used by paired lanes that have nothing to trace).  stk is this
-// lane's LDS stack, entries at stk[k * stride].
+// input triangle index) or, with anyhit, the first hit found.  The answer
+// (res_a, t_a) is the triangle slot (leaf order) or -1 and the hit distance
+// (tmax if none); tmax <= tmin means "no ray" and answers -1 at once (used
+// by paired lanes that have nothing to trace).  stk is this lane's LDS stack,
+// entries at stk[k * stride].
 //
 // Leaf tests are postponed (speculative traversal): a lane that reaches a leaf
 // holds it as pending and keeps visiting nodes (further leaves go to the
@@ -290,14 +291,13 @@ __device__ __forceinline__ void pop_entry(int& node, int& pleaf, int& sp, const 
 // tests (a postponed leaf only means fewer boxes culled meanwhile), and an
 // any-hit query only reports whether a hit exists.
 //
-//
 // TWO: each lane runs a second query from the same origin (closest hit along
-// db over (tmin, inf), if b_on) right after its first
+// db over (tmin, inf), if b_on; answer in res_b, t_b) right after its first
 // ends, in the same wavefront loop and on the same (then empty) stack.  The
 // wavefront then iterates as long as its longest per-lane sum of the two
 // traversals rather than the sum of the two longest, and the lanes done with
 // their first query keep working while others finish theirs.  Each query's
-// result is the one it has alone.
+// answer is the one it has alone.
 template <bool TWO>
 __device__ __forceinline__ void trace_core(const DevScene& S, V3 o, V3 d, float tmax, bool anyhit, bool b_on, V3 db,
                                            int& res_a, float& t_a, int& res_b, float& t_b,
@@ -412,6 +412,7 @@ __device__ __forceinline__ void trace_core(const DevScene& S, V3 o, V3 d, float 
     }
 }
 
+// One query (trace_core without a second): returns the slot or -1, t_hit the distance.
 __device__ int trace(const DevScene& S, V3 o, V3 d, float tmax, bool anyhit, float& t_hit, uint32_t* stk, int stride,
                      Counters& ctr) {
     int ra, rb;
