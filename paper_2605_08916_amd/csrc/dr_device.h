@@ -264,13 +264,23 @@ __device__ __forceinline__ bool test_leaf(const DevScene& S, int code, V3 o, V3 
 // Next work from the stack: an inner node to visit, or a leaf to hold as the
 // pending one (if the lane already holds one, the leaf stays on the stack
 // and the lane waits for the next leaf round).
-__device__ __forceinline__ void pop_entry(int& node, int& pleaf, int& sp, const uint32_t* stk, int stride) {
+// so is the stack height as an element offset (entries times stride), so a
+// push or pop is an add rather than a multiply.
+__device__ __forceinline__ void pop_entry(int& node, int& pleaf, int& so, const uint32_t* stk, int stride) {
     node = -1;
-    if (sp == 0) return;
-    const int e = (int)stk[(--sp) * stride];
+    if (so == 0) return;
+    so -= stride;
+    const int e = (int)stk[so];
     if (e >= 0) node = e;
     else if (pleaf == 0) pleaf = e;
-    else ++sp;
+    else so += stride;
+}
+// Push v if the stack (capacity cap_o as an element offset) has room.
+__device__ __forceinline__ void push_entry(int& so, uint32_t* stk, int stride, int cap_o, uint32_t v) {
+    if (so < cap_o) {
+        stk[so] = v;
+        so += stride;
+    }
 }
 
 #define DR_LEAF_PCT 40  // leaf round once this share of the wavefront's busy lanes hold a pending leaf
@@ -303,7 +313,7 @@ __device__ __forceinline__ void trace_core(const DevScene& S, V3 o, V3 d, float 
                                            int& res_a, float& t_a, int& res_b, float& t_b,
                                            uint32_t* stk, int stride, Counters& ctr) {
     float bt, qmax = tmax;
-    int best, sp = 0, node = -1, pleaf = 0;
+    int best, so = 0, node = -1, pleaf = 0;
     uint32_t best_prim;
     bool found = false, qany = anyhit;
     V3 qd = d;
@@ -317,7 +327,7 @@ __device__ __forceinline__ void trace_core(const DevScene& S, V3 o, V3 d, float 
         best = -1;
         best_prim = 0xFFFFFFFFu;
         found = false;
-        sp = 0;
+        so = 0;
         pleaf = 0;
         node = -1;
         if (!(mx > S.tmin)) return;
@@ -327,7 +337,7 @@ __device__ __forceinline__ void trace_core(const DevScene& S, V3 o, V3 d, float 
     };
     start(d, tmax, anyhit);
     int phase = 0;
-    const int cap = S.stack_cap;
+    const int cap_o = S.stack_cap * stride;
     while (true) {
         if (TWO && phase == 0 && node < 0 && pleaf == 0) {
             // first query over (its stack is empty): keep its answer, start the second
@@ -348,9 +358,9 @@ __device__ __forceinline__ void trace_core(const DevScene& S, V3 o, V3 d, float 
                 if (f) {
                     found = true;
                     node = -1;
-                    sp = 0;
+                    so = 0;
                 } else if (node < 0) {
-                    pop_entry(node, pleaf, sp, stk, stride);
+                    pop_entry(node, pleaf, so, stk, stride);
                 }
             }
         } else if (can_visit) {
@@ -369,7 +379,7 @@ __device__ __forceinline__ void trace_core(const DevScene& S, V3 o, V3 d, float 
                 if (hit[q] && i4(n.count, q) > 0) {
                     const int code = leaf_code(i4(n.child, q), i4(n.count, q));
                     if (pleaf == 0) pleaf = code;
-                    else if (sp < cap) stk[(sp++) * stride] = (uint32_t)code;
+                    else push_entry(so, stk, stride, cap_o, (uint32_t)code);
                 }
             }
             // hit inner children: visit the nearest next, push the others
@@ -394,12 +404,12 @@ __device__ __forceinline__ void trace_core(const DevScene& S, V3 o, V3 d, float 
             DR_CSWAP(1, 2)
 #undef DR_CSWAP
             if (kc[0] >= 0) {
-                if (kc[3] >= 0 && sp < cap) stk[(sp++) * stride] = (uint32_t)kc[3];
-                if (kc[2] >= 0 && sp < cap) stk[(sp++) * stride] = (uint32_t)kc[2];
-                if (kc[1] >= 0 && sp < cap) stk[(sp++) * stride] = (uint32_t)kc[1];
+                if (kc[3] >= 0) push_entry(so, stk, stride, cap_o, (uint32_t)kc[3]);
+                if (kc[2] >= 0) push_entry(so, stk, stride, cap_o, (uint32_t)kc[2]);
+                if (kc[1] >= 0) push_entry(so, stk, stride, cap_o, (uint32_t)kc[1]);
                 node = kc[0];
             } else {
-                pop_entry(node, pleaf, sp, stk, stride);
+                pop_entry(node, pleaf, so, stk, stride);
             }
         }
     }

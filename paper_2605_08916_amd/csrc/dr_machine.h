@@ -31,7 +31,7 @@ struct RayQ {
     float tmax, bt;
     int best;
     uint32_t best_prim;
-    int node, sp, pleaf;
+    int node, sp, pleaf;  // sp: stack height as an element offset (entries times stride)
     bool anyhit, found;
 };
 
@@ -73,7 +73,7 @@ __device__ __forceinline__ void ray_masks(const RayQ& q, bool tracing, uint64_t&
 // is the hit slot (or -1) and, for a closest-hit query, q.bt its distance.
 __device__ __forceinline__ bool ray_step(const DevScene& S, RayQ& q, uint32_t* stk, int stride, Counters& ctr,
                                          uint64_t ml, uint64_t mv) {
-    const int cap = S.stack_cap;
+    const int cap_o = S.stack_cap * stride;
     const int nl = __popcll(ml);
     if (nl && (mv == 0 || 100 * nl >= DR_LEAF_PCT * __popcll(ml | mv))) {
         if (q.pleaf != 0) {
@@ -104,7 +104,7 @@ __device__ __forceinline__ bool ray_step(const DevScene& S, RayQ& q, uint32_t* s
             if (hit[k] && i4(n.count, k) > 0) {
                 const int code = leaf_code(i4(n.child, k), i4(n.count, k));
                 if (q.pleaf == 0) q.pleaf = code;
-                else if (q.sp < cap) stk[(q.sp++) * stride] = (uint32_t)code;
+                else push_entry(q.sp, stk, stride, cap_o, (uint32_t)code);
             }
         }
         float kt[4];
@@ -127,9 +127,9 @@ __device__ __forceinline__ bool ray_step(const DevScene& S, RayQ& q, uint32_t* s
         DR_CSWAP(1, 2)
 #undef DR_CSWAP
         if (kc[0] >= 0) {
-            if (kc[3] >= 0 && q.sp < cap) stk[(q.sp++) * stride] = (uint32_t)kc[3];
-            if (kc[2] >= 0 && q.sp < cap) stk[(q.sp++) * stride] = (uint32_t)kc[2];
-            if (kc[1] >= 0 && q.sp < cap) stk[(q.sp++) * stride] = (uint32_t)kc[1];
+            if (kc[3] >= 0) push_entry(q.sp, stk, stride, cap_o, (uint32_t)kc[3]);
+            if (kc[2] >= 0) push_entry(q.sp, stk, stride, cap_o, (uint32_t)kc[2]);
+            if (kc[1] >= 0) push_entry(q.sp, stk, stride, cap_o, (uint32_t)kc[1]);
             q.node = kc[0];
         } else {
             pop_entry(q.node, q.pleaf, q.sp, stk, stride);
