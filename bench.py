@@ -673,6 +673,34 @@ def realtime_line(a, torch, dr, inputs):
         res["pt_equal_time_33ms"] = {"spp": spp, "frames": pm, "mrse_mean": float(np.mean([p["mrse"] for p in pm]))}
         res["mrse_reference"] = ("independent path tracing, two 32-spp halves per frame (seeds 100000+f, "
                                  "200000+f); MRSE against their mean minus the halves' own noise")
+        # ---- a static view (frame 0): MRSE after 1, 4, 16 and 64 evolve steps
+        # from one re-initialisation, at 1,048,576 and at N chains: how the
+        # image error falls with steps and with chains once the start-up
+        # bias of a fresh initialisation has decayed
+        scene.set_camera(cams[0])
+        r1, r2 = refs.get(0)
+        conv = {}
+        for n_ch in sorted({1 << 20, N}):
+            cc = dr.Chains(scene, n_ch, L, 77, mode=dr.DR_MODE_FUSED)
+            cc.set_launch(**{k: v for k, v in launch_cfg.items() if k in ("block", "blocks_per_cu", "grab",
+                                                                          "lanes_per_chain", "node_cache")})
+            img0 = torch.zeros((3, scene.W * scene.H), device="cuda", dtype=torch.float32)
+            cc.reinit(1)
+            done, rows = 0, []
+            t_ms = 0.0
+            for total in (1, 4, 16, 64):
+                e0.record()
+                cc.step(total - done)
+                e1.record()
+                torch.cuda.synchronize()
+                t_ms += e0.elapsed_time(e1)
+                done = total
+                cc.resolve(img0)
+                m = mrse_split(img0.cpu().numpy().astype(np.float64), r1, r2)[0]
+                rows.append({"steps": total, "mrse": m, "step_ms_total": t_ms})
+            cc.close()
+            conv[str(n_ch)] = rows
+        res["static_view_convergence"] = {"frame": 0, "by_chains": conv}
     # ---- the same loop with 1,048,576 chains (one GPU's share at 4 GPUs)
     if not a.no_secondary and N > (1 << 20):
         r1m, c1, _ = realtime_loop(torch, dr, scene, cams, 1 << 20, L, min(K, 10), 2, dr.DR_MODE_FUSED, None, refs,
