@@ -701,12 +701,19 @@ def realtime_line(a, torch, dr, inputs):
             cc.close()
             conv[str(n_ch)] = rows
         res["static_view_convergence"] = {"frame": 0, "by_chains": conv}
-    # ---- the same loop with 1,048,576 chains (one GPU's share at 4 GPUs)
+    # ---- the same loop with 1,048,576 chains (one GPU's share at 4 GPUs) and
+    # with one chain per pixel (the paper's dispatch size, Sec. 6)
     if not a.no_secondary and N > (1 << 20):
         r1m, c1, _ = realtime_loop(torch, dr, scene, cams, 1 << 20, L, min(K, 10), 2, dr.DR_MODE_FUSED, None, refs,
                                    mrse_frames, tune=not a.no_tune)
         c1.close()
         res["realtime_1M_chains"] = r1m
+        npx = scene.W * scene.H
+        if npx < N:
+            rpx, cpx, _ = realtime_loop(torch, dr, scene, cams, npx, L, min(K, 10), 2, dr.DR_MODE_FUSED, None, refs,
+                                        mrse_frames, tune=not a.no_tune)
+            cpx.close()
+            res["realtime_one_chain_per_pixel"] = rpx
     if not a.no_secondary:
         res["procedural_spheres_53k"] = spheres_line(a, torch, dr, inputs, secondary=True)
     if not a.no_cpu_baseline:

@@ -798,7 +798,8 @@ def test_node_cache_does_not_change_results(scenes, lanes):
         assert a["tour_count"] == b["tour_count"]
 
 
-@pytest.mark.parametrize("which,L,N", [("tiny", 4, 3000), ("spheres_small", 8, 20000), ("specular", 8, 20000)])
+@pytest.mark.parametrize("which,L,N", [("tiny", 4, 3000), ("spheres_small", 8, 20000), ("specular", 8, 20000),
+                                       ("interior", 8, 65536)])
 def test_wavefront_init_matches_straight_line(scenes, which, L, N):
     """The initialise pass evaluated as ray waves (traversal and event
     kernels alternating) or with the ray-refill state machine leaves exactly
@@ -806,7 +807,8 @@ def test_wavefront_init_matches_straight_line(scenes, which, L, N):
     positions, kill decisions, p, f/p, pixels, path records, scores, k0 and
     the tour count; the frame buffers differ only by the atomics' order."""
     say(f"[wavefront and refill init] scene={which} L={L} N={N}")
-    S = dr.Scene(scenes[which])
+    # the interior: the 2M-triangle tree, whose traversals run deepest
+    S = dr.Scene(inputs.procedural_interior() if which == "interior" else scenes[which])
     out = []
     for wf, rf in ((2, 2), (1, 2), (2, 1)):
         ch = dr.Chains(S, N, L, 31, frame=2)
