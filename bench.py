@@ -679,6 +679,10 @@ def realtime_line(a, torch, dr, inputs):
         # bias of a fresh initialisation has decayed
         scene.set_camera(cams[0])
         r1, r2 = refs.get(0)
+        # a second, 8x larger reference of the same frame (two 256-spp halves):
+        # the MRSE against it shows how much of the figure is reference noise
+        h1 = scene.pt_render(L, 300000, 256).cpu().numpy().astype(np.float64)
+        h2 = scene.pt_render(L, 400000, 256).cpu().numpy().astype(np.float64)
         conv = {}
         for n_ch in sorted({1 << 20, N}):
             cc = dr.Chains(scene, n_ch, L, 77, mode=dr.DR_MODE_FUSED)
@@ -696,11 +700,13 @@ def realtime_line(a, torch, dr, inputs):
                 t_ms += e0.elapsed_time(e1)
                 done = total
                 cc.resolve(img0)
-                m = mrse_split(img0.cpu().numpy().astype(np.float64), r1, r2)[0]
-                rows.append({"steps": total, "mrse": m, "step_ms_total": t_ms})
+                im0 = img0.cpu().numpy().astype(np.float64)
+                rows.append({"steps": total, "mrse": mrse_split(im0, r1, r2)[0],
+                             "mrse_ref256": mrse_split(im0, h1, h2)[0], "step_ms_total": t_ms})
             cc.close()
             conv[str(n_ch)] = rows
-        res["static_view_convergence"] = {"frame": 0, "by_chains": conv}
+        res["static_view_convergence"] = {"frame": 0, "by_chains": conv,
+                                          "reference": "mrse: two 32-spp halves; mrse_ref256: two 256-spp halves"}
     # ---- the same loop with 1,048,576 chains (one GPU's share at 4 GPUs) and
     # with one chain per pixel (the paper's dispatch size, Sec. 6)
     if not a.no_secondary and N > (1 << 20):
