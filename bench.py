@@ -687,7 +687,7 @@ def realtime_line(a, torch, dr, inputs):
         for n_ch in sorted({1 << 20, N}):
             cc = dr.Chains(scene, n_ch, L, 77, mode=dr.DR_MODE_FUSED)
             cc.set_launch(**{k: v for k, v in launch_cfg.items() if k in ("block", "blocks_per_cu", "grab",
-                                                                          "lanes_per_chain", "node_cache")})
+                                                                          "lanes_per_chain")})
             img0 = torch.zeros((3, scene.W * scene.H), device="cuda", dtype=torch.float32)
             cc.reinit(1)
             done, rows = 0, []

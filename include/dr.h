@@ -273,13 +273,7 @@ dr_status dr_stats(dr_chains* c, dr_counters* out, void* hip_stream);
  * each launch, order the chains by the screen tile of their film coordinates,
  * 64 x 64 tiles in Morton order, killed chains last, so a wavefront's camera
  * rays and the shadow rays from their hits are coherent; takes precedence
- * over sort_by_length; 2: off), and node_cache (the number of top BVH nodes,
- * stored breadth-first, each block of the straight-line fused kernel copies
- * into LDS at start, 128 bytes each, at most 512; 1 caches only the root;
- * DR_NODE_CACHE_AUTO: up to 341 (five levels) with two lanes per chain, up to
- * 85 (four levels) with one, fewer when the stacks of a deep tree leave too
- * little LDS for two (paired) or three (one lane) wavefronts per SIMD to stay
- * resident; explicit values are cut only to what fits one block), and
+ * over sort_by_length; 2: off), and
  * wavefront (1: the initialise pass evaluates its paths as ray waves -
  * alternating launches of a traversal kernel whose persistent lanes take
  * the next pending ray as theirs finishes, and an event kernel that shades
@@ -296,11 +290,10 @@ dr_status dr_stats(dr_chains* c, dr_counters* out, void* hip_stream);
  * 2 lanes per chain when n_chains is below two wavefronts per SIMD
  * (n_cu * 512) else 1, sorting off (it pays only when chains outnumber the
  * resident lanes several times over), refill off, thresholds 50 and 50,
- * tile ordering off, automatic node cache, straight-line initialise pass
+ * tile ordering off, straight-line initialise pass
  * (init_refill off), ray waves off (on the scenes
  * measured here the state round trips between the two kernels cost more than
  * the denser traversal saves).  The form, the ray waves and the order in which chains are processed never change results. */
-#define DR_NODE_CACHE_AUTO 0xFFFFFFFFu
 typedef struct {
     uint32_t block;
     uint32_t blocks_per_cu;
@@ -311,7 +304,6 @@ typedef struct {
     uint32_t refill_event_pct;
     uint32_t refill_advance_pct;
     uint32_t sort_by_tile;
-    uint32_t node_cache;
     uint32_t wavefront;
     uint32_t init_refill;
 } dr_launch_cfg;

@@ -28,7 +28,6 @@ CACHE = os.environ.get("DR_AUTOTUNE_CACHE", os.path.join(os.path.expanduser("~")
 BLOCKS = (64, 128, 256)
 BLOCKS_PER_CU = (1, 2, 3, 4, 6, 8)
 GRABS = (1, 2, 4)          # chains per lane per queue pop
-NODE_CACHES = (dr.DR_NODE_CACHE_AUTO, 1, 21, 85)
 LANES = (1, 2)
 # chain ordering before a launch: (sort_by_length, sort_by_tile), 1 on, 2 off
 ORDERS = ((2, 2), (1, 2), (2, 1))
@@ -37,8 +36,8 @@ REFILL_PCTS = ((50, 50), (75, 50), (75, 75), (90, 75))  # (event, advance) thres
 
 def candidates():
     """Every launch configuration the exhaustive sweep times: the
-    straight-line form over block x blocks-per-CU x grab x lanes x node cache
-    x ordering, and the ray-refill
+    straight-line form over block x blocks-per-CU x grab x lanes x ordering,
+    and the ray-refill
     form (one lane per chain) over block x blocks-per-CU x ordering x
     thresholds."""
     out = []
@@ -47,9 +46,8 @@ def candidates():
             for by_len, by_tile in ORDERS:
                 for grab in GRABS:
                     for lanes in LANES:
-                        for nc in NODE_CACHES:
-                            out.append(dict(block=block, blocks_per_cu=bpc, grab=grab, lanes_per_chain=lanes,
-                                            sort_by_length=by_len, sort_by_tile=by_tile, refill=2, node_cache=nc))
+                        out.append(dict(block=block, blocks_per_cu=bpc, grab=grab, lanes_per_chain=lanes,
+                                        sort_by_length=by_len, sort_by_tile=by_tile, refill=2))
                 for ev, adv in REFILL_PCTS:
                     out.append(dict(block=block, blocks_per_cu=bpc, sort_by_length=by_len, sort_by_tile=by_tile,
                                     refill=1, refill_event_pct=ev, refill_advance_pct=adv))
@@ -59,7 +57,9 @@ def candidates():
 def _key(ch: "dr.Chains") -> str:
     import torch
     name = torch.cuda.get_device_name()
-    return f"{name}|L{ch.L}|N{ch.N}|T{int(ch.scene.sc['indices'].shape[0])}"
+    # the leading tag changes whenever the launch fields do, so entries that
+    # name fields the library no longer has are never applied
+    return f"launch2|{name}|L{ch.L}|N{ch.N}|T{int(ch.scene.sc['indices'].shape[0])}"
 
 
 def _load() -> dict:
@@ -93,12 +93,11 @@ def staged_candidates(ch: "dr.Chains", timer) -> list:
             results.append((timer(c), c))
         return min(results, key=lambda r: r[0])[1]
 
-    base = dict(sort_by_length=2, sort_by_tile=2, refill=2, grab=1, node_cache=dr.DR_NODE_CACHE_AUTO)
+    base = dict(sort_by_length=2, sort_by_tile=2, refill=2, grab=1)
     best = run([dict(base, block=b, blocks_per_cu=k) for b in BLOCKS for k in BLOCKS_PER_CU])
     best = run([dict(best, lanes_per_chain=n) for n in LANES])
     best = run([dict(best, sort_by_length=a, sort_by_tile=b) for a, b in ORDERS[1:]])
     best = run([dict(best, grab=g) for g in GRABS[1:]])
-    best = run([dict(best, node_cache=n) for n in NODE_CACHES[1:]])
     run([dict(best, refill=1, refill_event_pct=ev, refill_advance_pct=adv) for ev, adv in REFILL_PCTS])
     return results
 
@@ -140,8 +139,7 @@ def tune(ch: "dr.Chains", reps: int = 3, use_cache: bool = True, verbose: bool =
         ch.set_launch(**cfg)
         return cache[key]
     snap = ch.read_state() if restore else None
-    full = dict(sort_by_length=2, sort_by_tile=2, refill=2, grab=1, node_cache=dr.DR_NODE_CACHE_AUTO,
-                refill_event_pct=50, refill_advance_pct=50)
+    full = dict(sort_by_length=2, sort_by_tile=2, refill=2, grab=1, refill_event_pct=50, refill_advance_pct=50)
     flags = ("sort_by_length", "sort_by_tile", "refill", "wavefront", "init_refill")  # read back 1/0, requested 1 on / 2 off
     current = {k: ((1 if v else 2) if k in flags else v) for k, v in ch.get_launch().items()}
     ch.set_launch(**current)

@@ -67,9 +67,11 @@ __device__ __forceinline__ float u24(uint32_t w) { return (float)(w >> 8) * (1.0
 // ---------------------------------------------------------------------------
 // 4-wide BVH node (128 B, two cache lines fetched together per visit): the
 // boxes of its four children in SOA form (lo/hi per axis for children 0..3),
-// then per child: index and count.  count > 0: leaf of `count` triangles
-// starting at slot `child`; count == 0: inner node index `child`; count < 0:
-// empty slot.
+// then per child the traversal-stack entry and the triangle count.  child >= 0:
+// inner node index; child < 0: a leaf, already in its stack form (leaf_code
+// below).  count is the leaf's triangle count (0 for an inner node, -1 for an
+// empty slot) and is read only by the host; an empty slot's box is NaN, which
+// the slab test never reports as hit.
 struct alignas(128) DevNode {
     float4 lox, loy, loz, hix, hiy, hiz;
     int4 child, count;
@@ -94,17 +96,9 @@ struct DevScene {
     int stack_cap;   // traversal stack entries per lane (the tree's exact worst case, <= DR_STACK)
     int n_tris;
     int leaf_batch;  // triangles fetched together per leaf iteration: 2 if no leaf holds more, else 4
-    int n_top;       // top nodes the launching kernel holds in LDS (0: none)
+    int n_nodes;     // nodes in the array
 };
 
-// Copies the first S.n_top nodes into the start of the dynamic LDS (all
-// threads of the block call it, before any traversal).
-__device__ __forceinline__ void cache_top_nodes(const DevScene& S) {
-    extern __shared__ float4 s_dyn[];
-    const float4* g = reinterpret_cast<const float4*>(S.nodes);
-    for (int k = threadIdx.x; k < 8 * S.n_top; k += blockDim.x) s_dyn[k] = g[k];
-    __syncthreads();
-}
 struct Cam {
     V3 eye, cu, cv, cw;
 };
@@ -132,41 +126,87 @@ __device__ __forceinline__ float safe_rcp(float d) {
 // is crossed at t = (p - o_a) inv_a, computed as one FMA p * inv_a + c with
 // c = -(o_a inv_a).  The rounding of o_a inv_a (and of c) is at most
 // |o_a inv_a| 2^-23 in t, so each axis's interval is widened by
-// E_a = |o_a inv_a| 2^-22, folded into the constants: the plane that bounds
-// the interval from below (the low plane when inv_a >= 0, else the high one)
-// takes c - E_a, the other c + E_a.  With the far distance also widened
+// E_a = |o_a inv_a| 2^-22, folded into the constants: the near plane takes
+// c - E_a, the far one c + E_a.  With the far distance also widened
 // relatively (the final FMA's own rounding), no box a ray truly enters
 // within (tmin, tmax) is ever culled.  The reciprocal itself is the
 // hardware one (within a few ulp): its error scales an axis's whole
 // interval by one factor, which the far distance's relative widening
 // (4e-7) also covers.
-struct RaySlab {
-    V3 inv, clo, chi;  // clo / chi: constants of the low / high plane per axis
+//
+// Which of a box's two planes on an axis the ray meets first depends only on
+// the sign of its direction there: the low plane when inv_a >= 0, else the
+// high one.  So per ray the near and far plane vectors of each axis sit at
+// fixed byte offsets of the SoA node (lo_x at 0, lo_y 16, lo_z 32, hi_x 48,
+// hi_y 64, hi_z 80): they are fetched from there, and the test needs no
+// per-axis min / max.  For a box with lo <= hi the near distance is then the
+// smaller of the two (the FMA is monotone in each operand and the near
+// constant is below the far one), so this is the usual slab test, value for
+// value.
+struct RayOrd {
+    V3 inv, cn, cf;       // reciprocal direction; near / far plane constants
+    uint32_t noff, foff;  // byte offsets of the near / far planes, one byte per axis
 };
-__device__ __forceinline__ float slab_const(float o, float inv, bool low) {
+__device__ __forceinline__ void plane_consts(float o, float inv, float& cn, float& cf) {
     const float oi = o * inv;
     const float e = fabsf(oi) * 2.384185791015625e-07f;  // 2^-22
-    return (low == (inv >= 0.0f)) ? -(oi + e) : -(oi - e);
+    cn = -(oi + e);
+    cf = -(oi - e);
 }
-__device__ __forceinline__ RaySlab ray_slab(V3 o, V3 d) {
-    RaySlab r;
+__device__ __forceinline__ RayOrd ray_ord(V3 o, V3 d) {
+    RayOrd r;
     r.inv = v3(safe_rcp(d.x), safe_rcp(d.y), safe_rcp(d.z));
-    r.clo = v3(slab_const(o.x, r.inv.x, true), slab_const(o.y, r.inv.y, true), slab_const(o.z, r.inv.z, true));
-    r.chi = v3(slab_const(o.x, r.inv.x, false), slab_const(o.y, r.inv.y, false), slab_const(o.z, r.inv.z, false));
+    plane_consts(o.x, r.inv.x, r.cn.x, r.cf.x);
+    plane_consts(o.y, r.inv.y, r.cn.y, r.cf.y);
+    plane_consts(o.z, r.inv.z, r.cn.z, r.cf.z);
+    const bool nx = r.inv.x < 0.0f, ny = r.inv.y < 0.0f, nz = r.inv.z < 0.0f;
+    r.noff = (nx ? 48u : 0u) | (ny ? 64u : 16u) << 8 | (nz ? 80u : 32u) << 16;
+    r.foff = (nx ? 0u : 48u) | (ny ? 16u : 64u) << 8 | (nz ? 32u : 80u) << 16;
     return r;
 }
 
-// Slab test over (tmin, tmax) with the per-ray constants above; tnear is the
-// entry distance (used to order the children).
-__device__ __forceinline__ bool slab(float lx, float ly, float lz, float hx, float hy, float hz, const RaySlab& r,
-                                     float tmin, float tmax, float& tnear) {
-    const float tx0 = fmaf(lx, r.inv.x, r.clo.x), tx1 = fmaf(hx, r.inv.x, r.chi.x);
-    const float ty0 = fmaf(ly, r.inv.y, r.clo.y), ty1 = fmaf(hy, r.inv.y, r.chi.y);
-    const float tz0 = fmaf(lz, r.inv.z, r.clo.z), tz1 = fmaf(hz, r.inv.z, r.chi.z);
-    const float tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), tmin));
-    const float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fmaxf(tz0, tz1)) * 1.0000004f;
-    tnear = tn;
-    return tn <= fminf(tf, tmax);
+// NaN-propagating minimum / maximum: a NaN box (an empty child slot) never
+// passes, and no operand needs canonicalising.  Every other operand is finite
+// (|inv| <= 1e20, finite planes), where they equal fminf / fmaxf except on the
+// sign of a zero, which cannot change a decision (tnear >= tmin > 0).
+__device__ __forceinline__ float mn(float a, float b) { return __builtin_elementwise_minimum(a, b); }
+__device__ __forceinline__ float mx(float a, float b) { return __builtin_elementwise_maximum(a, b); }
+// Component q of a vector (q is a compile-time constant after unrolling).
+__device__ __forceinline__ float f4(const float4& v, int q) { return q == 0 ? v.x : (q == 1 ? v.y : (q == 2 ? v.z : v.w)); }
+__device__ __forceinline__ int i4(const int4& v, int q) { return q == 0 ? v.x : (q == 1 ? v.y : (q == 2 ? v.z : v.w)); }
+// Buffer resource over the scene's node array (raw, byte offsets, range
+// checked against the array's size).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t node_rsrc(const DevScene& S) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)S.nodes, (short)0, S.n_nodes * (int)sizeof(DevNode), 0x00020000);
+}
+// The four child boxes of node `node` against one ray: hit[q] and tnear[q];
+// returns the children's stack entries.  Seven 16-byte fetches through the
+// buffer resource rn (32-bit offsets: the per-lane plane offsets come from the
+// ray, the axis offsets fold into the instructions).  The top levels stay in
+// the L1 and L2 (an LDS copy of them measured no faster with this form).
+__device__ __forceinline__ int4 box4_ord(__amdgpu_buffer_rsrc_t rn, int node, const RayOrd& r, float tmin, float tmax,
+                                         bool hit[4], float tn[4]) {
+    typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+    const uint32_t b = (uint32_t)node << 7;
+    auto ld = [&](uint32_t off) {
+        const u4 v = __builtin_amdgcn_raw_buffer_load_b128(rn, b + off, 0, 0);
+        return make_float4(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), __uint_as_float(v.w));
+    };
+    const float4 nx = ld(r.noff & 0xffu), fx = ld(r.foff & 0xffu);
+    const float4 ny = ld((r.noff >> 8) & 0xffu), fy = ld((r.foff >> 8) & 0xffu);
+    const float4 nz = ld(r.noff >> 16), fz = ld(r.foff >> 16);
+    const u4 c = __builtin_amdgcn_raw_buffer_load_b128(rn, b + 96u, 0, 0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const float tnx = fmaf(f4(nx, q), r.inv.x, r.cn.x), tfx = fmaf(f4(fx, q), r.inv.x, r.cf.x);
+        const float tny = fmaf(f4(ny, q), r.inv.y, r.cn.y), tfy = fmaf(f4(fy, q), r.inv.y, r.cf.y);
+        const float tnz = fmaf(f4(nz, q), r.inv.z, r.cn.z), tfz = fmaf(f4(fz, q), r.inv.z, r.cf.z);
+        const float t0 = mx(mx(tnx, tny), mx(tnz, tmin));
+        const float t1 = mn(mn(tfx, tfy), tfz) * 1.0000004f;
+        tn[q] = t0;
+        hit[q] = t0 <= mn(t1, tmax);
+    }
+    return make_int4((int)c.x, (int)c.y, (int)c.z, (int)c.w);
 }
 
 // Moller-Trumbore, two-sided; t in (tmin, inf) before the caller's range test.
@@ -187,46 +227,11 @@ __device__ __forceinline__ bool tri_test(const DevTri& T, V3 o, V3 d, float tmin
     return t > tmin;
 }
 
-// The first S.n_top nodes (the top levels: nodes are stored breadth-first)
-// may sit at the start of the kernel's dynamic LDS, copied there by the
-// kernel; every ray starts at the root, so its first visits read LDS.  The
-// compiler merges the two branches into one generic (flat) load per 16
-// bytes.  Loads through address-space-qualified pointers keep them apart (LDS
-// and global instructions) but cost registers and measured 1-2% slower in the
-// one-lane kernels, so the plain form stays.
-__device__ __forceinline__ DevNode load_node(const DevScene& S, int i) {
-    extern __shared__ float4 s_dyn[];
-    DevNode n;
-    if (i < S.n_top) {
-        const float4* p = s_dyn + 8 * i;
-        n.lox = p[0];
-        n.loy = p[1];
-        n.loz = p[2];
-        n.hix = p[3];
-        n.hiy = p[4];
-        n.hiz = p[5];
-        n.child = reinterpret_cast<const int4*>(p)[6];
-        n.count = reinterpret_cast<const int4*>(p)[7];
-    } else {
-        const float4* p = reinterpret_cast<const float4*>(S.nodes + i);
-        n.lox = p[0];
-        n.loy = p[1];
-        n.loz = p[2];
-        n.hix = p[3];
-        n.hiy = p[4];
-        n.hiz = p[5];
-        n.child = reinterpret_cast<const int4*>(p)[6];
-        n.count = reinterpret_cast<const int4*>(p)[7];
-    }
-    return n;
-}
-
-__device__ __forceinline__ float f4(const float4& v, int q) { return q == 0 ? v.x : (q == 1 ? v.y : (q == 2 ? v.z : v.w)); }
-__device__ __forceinline__ int i4(const int4& v, int q) { return q == 0 ? v.x : (q == 1 ? v.y : (q == 2 ? v.z : v.w)); }
 // Leaf entries share the traversal stack with inner nodes: a leaf of cnt
 // triangles from slot first is stored as -1 - (first << 5 | cnt) (cnt <= 16,
-// first < 2^24), inner nodes as their index (>= 0).
-__device__ __forceinline__ int leaf_code(int first, int cnt) { return -1 - ((first << 5) | cnt); }
+// first < 2^24), inner nodes as their index (>= 0).  The scene upload writes
+// leaves in this form into the nodes' child fields.
+__host__ __device__ __forceinline__ int leaf_code(int first, int cnt) { return -1 - ((first << 5) | cnt); }
 
 // Triangle tests of one leaf; returns true when an any-hit query has found
 // its hit (slot in best).
@@ -317,7 +322,8 @@ __device__ __forceinline__ void trace_core(const DevScene& S, V3 o, V3 d, float 
     uint32_t best_prim;
     bool found = false, qany = anyhit;
     V3 qd = d;
-    RaySlab rs;
+    RayOrd rs;
+    const __amdgpu_buffer_rsrc_t rn = node_rsrc(S);
     // set up one query at the root (node stays -1 when there is no query)
     auto start = [&](V3 dd, float mx, bool any) {
         qd = dd;
@@ -332,7 +338,7 @@ __device__ __forceinline__ void trace_core(const DevScene& S, V3 o, V3 d, float 
         node = -1;
         if (!(mx > S.tmin)) return;
         ctr.rays++;
-        rs = ray_slab(o, dd);
+        rs = ray_ord(o, dd);
         node = 0;
     };
     start(d, tmax, anyhit);
@@ -364,20 +370,15 @@ __device__ __forceinline__ void trace_core(const DevScene& S, V3 o, V3 d, float 
                 }
             }
         } else if (can_visit) {
-            const DevNode n = load_node(S, node);
             ctr.nodes++;
             float tn[4];
             bool hit[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                hit[q] = slab(f4(n.lox, q), f4(n.loy, q), f4(n.loz, q), f4(n.hix, q), f4(n.hiy, q), f4(n.hiz, q), rs,
-                              S.tmin, bt, tn[q]) &
-                         (i4(n.count, q) >= 0);
+            const int4 child = box4_ord(rn, node, rs, S.tmin, bt, hit, tn);
             // hit leaves: the first becomes the pending leaf if the lane holds none, the others wait on the stack
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                if (hit[q] && i4(n.count, q) > 0) {
-                    const int code = leaf_code(i4(n.child, q), i4(n.count, q));
+                const int code = i4(child, q);
+                if (hit[q] && code < 0) {
                     if (pleaf == 0) pleaf = code;
                     else push_entry(so, stk, stride, cap_o, (uint32_t)code);
                 }
@@ -388,9 +389,9 @@ __device__ __forceinline__ void trace_core(const DevScene& S, V3 o, V3 d, float 
             int kc[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const bool inner = hit[q] && i4(n.count, q) == 0;
+                const bool inner = hit[q] && i4(child, q) >= 0;
                 kt[q] = inner ? tn[q] : INFINITY;
-                kc[q] = inner ? i4(n.child, q) : -1;
+                kc[q] = inner ? i4(child, q) : -1;
             }
 #define DR_CSWAP(i, j)                                       \
     if (kt[j] < kt[i]) {                                     \

@@ -152,8 +152,7 @@ template <int L, bool PAIR, bool DELTA>
 __device__ __forceinline__ void step_fused_body(const KParams& P, const DevScene& S, const KBufs& B, uint32_t nsteps,
                                                 uint32_t grab, int sorted) {
     extern __shared__ uint32_t s_stack[];
-    cache_top_nodes(S);  // the top nodes precede the stacks in LDS
-    uint32_t* stk = s_stack + S.n_top * 32 + threadIdx.x;
+    uint32_t* stk = s_stack + threadIdx.x;
     const int stride = blockDim.x;
     const int lane = threadIdx.x & 63;
     const bool lead = PAIR ? (lane & 1) == 0 : true;
@@ -591,8 +590,7 @@ __device__ __forceinline__ InitRec<L> init_rec(const KBufs& B, const DevScene& S
 template <int L, bool DELTA>
 __global__ void __launch_bounds__(256) k_init_sm(KParams P, DevScene S, KBufs B, int thresh) {
     extern __shared__ uint32_t s_stack[];
-    cache_top_nodes(S);  // the top nodes precede the stacks in LDS
-    uint32_t* stk = s_stack + S.n_top * 32 + threadIdx.x;
+    uint32_t* stk = s_stack + threadIdx.x;
     const int stride = blockDim.x;
     const int lane = threadIdx.x & 63;
     const uint64_t s0 = B.steps[1];
@@ -671,8 +669,7 @@ __global__ void __launch_bounds__(256) k_wf_init_begin(KParams P, DevScene S, KB
 // run trace()'s speculative traversal and store the answer.
 static __global__ void __launch_bounds__(256) k_wf_trace(KParams P, DevScene S, KBufs B, int in) {
     extern __shared__ uint32_t s_stack[];
-    cache_top_nodes(S);
-    uint32_t* stk = s_stack + S.n_top * 32 + threadIdx.x;
+    uint32_t* stk = s_stack + threadIdx.x;
     const int stride = blockDim.x;
     const int lane = threadIdx.x & 63;
     const uint32_t n = B.wf_cnt[in];
@@ -770,7 +767,7 @@ void launch_init_acc(dim3 g, dim3 b, hipStream_t st, const KParams& P, const Dev
 template <int L>
 void launch_fused(dim3 g, dim3 b, hipStream_t st, const KParams& P, const DevScene& S, const KBufs& B,
                          uint32_t n, uint32_t grab, bool pair, int sorted, bool delta) {
-    const size_t lds = stack_bytes(S, b.x) + (size_t)S.n_top * sizeof(DevNode);
+    const size_t lds = stack_bytes(S, b.x);
     if (delta) {
         if (pair) hipLaunchKernelGGL((k_step_fused_pair<L, true>), g, b, lds, st, P, S, B, n, grab, sorted);
         else hipLaunchKernelGGL((k_step_fused<L, true>), g, b, lds, st, P, S, B, n, grab, sorted);
@@ -805,7 +802,7 @@ void launch_eval(dim3 g, dim3 b, hipStream_t st, const DevScene& S, const float*
 template <int L>
 void launch_init_sm(dim3 g, dim3 b, hipStream_t st, const KParams& P, const DevScene& S, const KBufs& B, int thresh,
                     bool delta) {
-    const size_t lds = stack_bytes(S, b.x) + (size_t)S.n_top * sizeof(DevNode);
+    const size_t lds = stack_bytes(S, b.x);
     if (delta) hipLaunchKernelGGL((k_init_sm<L, true>), g, b, lds, st, P, S, B, thresh);
     else hipLaunchKernelGGL((k_init_sm<L, false>), g, b, lds, st, P, S, B, thresh);
 }
@@ -816,15 +813,15 @@ void launch_init_sm(dim3 g, dim3 b, hipStream_t st, const KParams& P, const DevS
 // queue lengths in device memory.
 template <int L>
 void launch_wf_init(dim3 g, dim3 b, int trace_blocks, hipStream_t st, const KParams& P, const DevScene& S,
-                    const DevScene& St, const KBufs& B, bool delta) {
-    const size_t lds = stack_bytes(St, b.x) + (size_t)St.n_top * sizeof(DevNode);
+                    const KBufs& B, bool delta) {
+    const size_t lds = stack_bytes(S, b.x);
     hipLaunchKernelGGL(k_wf_reset, dim3(1), dim3(64), 0, st, B, 0);
     hipLaunchKernelGGL(k_wf_reset, dim3(1), dim3(64), 0, st, B, 1);
     if (delta) hipLaunchKernelGGL((k_wf_init_begin<L, true>), g, b, 0, st, P, S, B);
     else hipLaunchKernelGGL((k_wf_init_begin<L, false>), g, b, 0, st, P, S, B);
     int in = 0;
     for (int r = 0; r < 2 * (L - 1); ++r) {
-        hipLaunchKernelGGL(k_wf_trace, dim3(trace_blocks), b, lds, st, P, St, B, in);
+        hipLaunchKernelGGL(k_wf_trace, dim3(trace_blocks), b, lds, st, P, S, B, in);
         hipLaunchKernelGGL(k_wf_reset, dim3(1), dim3(64), 0, st, B, 1 - in);
         if (delta) hipLaunchKernelGGL((k_wf_init_event<L, true>), g, b, 0, st, P, S, B, in);
         else hipLaunchKernelGGL((k_wf_init_event<L, false>), g, b, 0, st, P, S, B, in);
@@ -845,6 +842,6 @@ void launch_wf_init(dim3 g, dim3 b, int trace_blocks, hipStream_t st, const KPar
                                       float*, uint32_t*, uint32_t*, int);                                           \
     X template void launch_eval<L>(dim3, dim3, hipStream_t, const DevScene&, const float*, int, float, float*, float*, \
                                    float*, uint32_t*, uint32_t*);                                                  \
-    X template void launch_wf_init<L>(dim3, dim3, int, hipStream_t, const KParams&, const DevScene&, const DevScene&, \
+    X template void launch_wf_init<L>(dim3, dim3, int, hipStream_t, const KParams&, const DevScene&, \
                                       const KBufs&, bool);                                                          \
     X template void launch_init_sm<L>(dim3, dim3, hipStream_t, const KParams&, const DevScene&, const KBufs&, int, bool);

@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -65,13 +66,11 @@ __global__ void k_begin_init(KBufs B, uint32_t frame, int from_device) {
 // the scene has smooth conductors or dielectrics.  Persistent: each wavefront
 // takes the next 64 consecutive chains from the work queue (one atomic) until
 // the queue is drained, so a wavefront slot never idles waiting for the other
-// wavefronts of its block, and the top nodes are copied to LDS once per
-// resident block.
+// wavefronts of its block.
 template <bool DELTA>
 __global__ void __launch_bounds__(256) k_init_eval(KParams P, DevScene S, KBufs B) {
     extern __shared__ uint32_t s_stack[];
-    cache_top_nodes(S);  // the top nodes precede the stacks in LDS
-    uint32_t* stk = s_stack + S.n_top * 32 + threadIdx.x;
+    uint32_t* stk = s_stack + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const uint64_t s0 = B.steps[1];
     Counters ctr = {0, 0, 0};
@@ -411,10 +410,8 @@ struct dr_chains {
     uint64_t seed = 0;
     int n_partials = 0;
     int record = 0, count = 0;
-    dr_launch_cfg launch{256, 2, 1, 2, 0, 0, 50, 50, 0, DR_NODE_CACHE_AUTO, 0, 0};
+    dr_launch_cfg launch{256, 2, 1, 2, 0, 0, 50, 50, 0, 0, 0};
     int n_cu = 256;
-    int lds_limit = 65536;             // bytes of LDS one block may use
-    int lds_per_cu = 163840;           // bytes of LDS one compute unit holds
     int rows_move = 0, rows_all = 0;  // state rows moved per sorted launch / restored before host access
     bool permuted = false;            // chains may sit outside the slot of their id
 };
@@ -447,35 +444,6 @@ DR_EXTERN_L(16)
         case 16: FN<16>(__VA_ARGS__); break; \
         default: break;                      \
     }
-
-// LDS is handed to blocks in granules; a block's stacks plus cached nodes are
-// rounded up to this before they count against the compute unit's LDS.
-#define DR_LDS_GRANULE 2048
-
-// Top BVH nodes a block of `blk` threads caches in LDS (they precede the
-// stacks in the block's dynamic LDS).  Automatic (DR_NODE_CACHE_AUTO): up to
-// five levels with paired lanes, four with one lane, and no more than leaves
-// room, in whole LDS granules, for the wavefronts the kernel keeps resident
-// (two per SIMD paired, three with one lane, the register limit): the stacks
-// of a deep tree take most of the LDS themselves, and one granule too many
-// per block drops a block from every compute unit.  Explicit values are cut
-// only to what fits one block.
-static int node_cache_size(const dr_chains* c, int blk, bool pair, uint32_t nc) {
-    const DevScene& S = c->scene->ds;
-    const size_t stack_b = stack_bytes(S, blk);
-    if (nc == DR_NODE_CACHE_AUTO) {
-        const int waves_cu = 4 * (pair ? 2 : 3), waves_block = std::max(1, blk / 64);
-        const int blocks_cu = (waves_cu + waves_block - 1) / waves_block;
-        const size_t budget = ((size_t)c->lds_per_cu / (size_t)blocks_cu) / DR_LDS_GRANULE * DR_LDS_GRANULE;
-        const size_t room = budget > stack_b ? budget - stack_b : 0;
-        nc = (uint32_t)std::min<size_t>(pair ? 341u : 85u, room / sizeof(DevNode));
-    }
-    int n_top = (int)std::min<uint32_t>(nc, c->scene->n_nodes);
-    // the cached nodes and the stacks share the block's LDS: fewer nodes if they would not fit
-    if (stack_b + (size_t)n_top * sizeof(DevNode) > (size_t)c->lds_limit)
-        n_top = (int)(((size_t)c->lds_limit > stack_b ? (size_t)c->lds_limit - stack_b : 0) / sizeof(DevNode));
-    return n_top;
-}
 
 // Event threshold of the ray-refill initialise kernel (percent of the busy
 // lanes waiting for an event): the best of 30, 50, 75 and 90 on the 53k- and
@@ -519,10 +487,7 @@ static void enqueue_init(dr_chains* c, uint32_t frame, int from_device, hipStrea
     hipLaunchKernelGGL(k_begin_init, dim3(1), dim3(64), 0, st, c->kb, frame, from_device);
     hipLaunchKernelGGL(k_fill_f32, dim3(1024), dim3(256), 0, st, c->kb.accum, 3 * npx);
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, c->kb.ctr, (int)C_N);
-    // the init kernel runs 256-thread blocks, one lane per chain, three
-    // wavefronts per SIMD: it always takes the automatic cache for that shape
-    DevScene S = c->scene->ds;
-    S.n_top = node_cache_size(c, blk, false, DR_NODE_CACHE_AUTO);
+    const DevScene& S = c->scene->ds;
     if (c->launch.init_refill) {
         // ray-refill form: persistent blocks (more than fit at once; the
         // extra ones find the queue drained)
@@ -531,10 +496,9 @@ static void enqueue_init(dr_chains* c, uint32_t frame, int from_device, hipStrea
     } else if (c->launch.wavefront && c->kb.wf) {
         // ray waves: persistent traversal blocks (more than fit at once; the
         // extra ones find the queue drained)
-        DR_DISPATCH_L(c->kp.L, launch_wf_init, g, b, c->n_cu * 4, st, P, c->scene->ds, S, c->kb,
-                      c->scene->has_delta);
+        DR_DISPATCH_L(c->kp.L, launch_wf_init, g, b, c->n_cu * 4, st, P, S, c->kb, c->scene->has_delta);
     } else {
-        const size_t lds = stack_bytes(S, blk) + (size_t)S.n_top * sizeof(DevNode);
+        const size_t lds = stack_bytes(S, blk);
         // persistent grid: as many blocks as can be resident at once
         int per_cu = 0;
         if (c->scene->has_delta)
@@ -591,8 +555,7 @@ static bool enqueue_steps(dr_chains* c, uint32_t n_steps, hipStream_t st) {
         const long lanes = (long)N * (pair ? 2 : 1);
         int blocks = (int)(c->n_cu * c->launch.blocks_per_cu);
         blocks = (int)std::max(1L, std::min((long)blocks, (lanes + blk - 1) / blk));
-        DevScene S = c->scene->ds;
-        S.n_top = node_cache_size(c, blk, pair, c->launch.node_cache);
+        const DevScene& S = c->scene->ds;
         DR_DISPATCH_L(P.L, launch_fused, dim3(blocks), dim3(blk), st, P, S, c->kb, n_steps, c->launch.grab, pair,
                       sorted, c->scene->has_delta);
     } else {
@@ -784,8 +747,7 @@ dr_status dr_scene_create(const dr_scene_desc* desc, int device, dr_scene** out)
         }
         return k;
     };
-    // nodes laid out breadth-first before the depth-first rest (at least the
-    // largest LDS node cache, 512 nodes)
+    // the first 512 nodes laid out breadth-first, the rest depth-first
     constexpr int DR_BFS_TOP = 512;
     std::vector<DevNode> dn;
     std::vector<int> need;  // worst-case traversal stack entries below each device node
@@ -795,10 +757,11 @@ dr_status dr_scene_create(const dr_scene_desc* desc, int device, dr_scene** out)
         std::vector<std::vector<int>> kids;  // device children (inner) per device node
         auto fill_leafroot = [&]() {
             DevNode r{};
-            r.lox = make_float4(blo[0], 1.f, 1.f, 1.f); r.loy = make_float4(blo[1], 1.f, 1.f, 1.f);
-            r.loz = make_float4(blo[2], 1.f, 1.f, 1.f); r.hix = make_float4(bhi[0], 0.f, 0.f, 0.f);
-            r.hiy = make_float4(bhi[1], 0.f, 0.f, 0.f); r.hiz = make_float4(bhi[2], 0.f, 0.f, 0.f);
-            r.child = make_int4(~nodes[0].a, 0, 0, 0);
+            const float nan = std::numeric_limits<float>::quiet_NaN();
+            r.lox = make_float4(blo[0], nan, nan, nan); r.loy = make_float4(blo[1], nan, nan, nan);
+            r.loz = make_float4(blo[2], nan, nan, nan); r.hix = make_float4(bhi[0], nan, nan, nan);
+            r.hiy = make_float4(bhi[1], nan, nan, nan); r.hiz = make_float4(bhi[2], nan, nan, nan);
+            r.child = make_int4(leaf_code(~nodes[0].a, nodes[0].b), 0, 0, 0);
             r.count = make_int4(nodes[0].b, -1, -1, -1);
             dn.push_back(r);
             kids.emplace_back();
@@ -809,9 +772,10 @@ dr_status dr_scene_create(const dr_scene_desc* desc, int device, dr_scene** out)
             dn.emplace_back();
             kids.emplace_back();
             // breadth-first for the first nodes (indices grow level by level,
-            // so the top levels come first: the kernels keep those in LDS),
-            // depth-first below them, so that each deeper subtree's nodes lie
-            // together in memory and a ray descending it stays on nearby lines
+            // so the top levels, which every ray visits, share a few cache
+            // lines), depth-first below them, so that each deeper subtree's
+            // nodes lie together in memory and a ray descending it stays on
+            // nearby lines
             std::vector<Item> deep;  // depth-first stack
             work.push_back({0, 0});
             size_t w = 0;
@@ -828,8 +792,8 @@ dr_status dr_scene_create(const dr_scene_desc* desc, int device, dr_scene** out)
                 float lo[3][4], hi[3][4];
                 int cidx[4], ccnt[4];
                 for (int q = 0; q < 4; ++q) {
-                    if (q >= k) {
-                        for (int a2 = 0; a2 < 3; ++a2) { lo[a2][q] = 1.f; hi[a2][q] = 0.f; }
+                    if (q >= k) {  // empty slot: a NaN box, which no ray hits
+                        for (int a2 = 0; a2 < 3; ++a2) lo[a2][q] = hi[a2][q] = std::numeric_limits<float>::quiet_NaN();
                         cidx[q] = 0;
                         ccnt[q] = -1;
                         continue;
@@ -837,7 +801,7 @@ dr_status dr_scene_create(const dr_scene_desc* desc, int device, dr_scene** out)
                     const int c = ch[q];
                     for (int a2 = 0; a2 < 3; ++a2) { lo[a2][q] = blo[3 * c + a2]; hi[a2][q] = bhi[3 * c + a2]; }
                     if (nodes[c].a < 0) {
-                        cidx[q] = ~nodes[c].a;
+                        cidx[q] = leaf_code(~nodes[c].a, nodes[c].b);
                         ccnt[q] = nodes[c].b;
                     } else {
                         cidx[q] = (int)dn.size();
@@ -954,6 +918,7 @@ dr_status dr_scene_create(const dr_scene_desc* desc, int device, dr_scene** out)
     S->ds.lights = (const float4*)dlights;
     S->ds.n_lights = (int)desc->n_lights;
     S->ds.n_tris = (int)T;
+    S->ds.n_nodes = (int)dn.size();
     {
         int max_count = 0;
         for (const DevNode& nd : dn)
@@ -1036,15 +1001,6 @@ dr_status dr_chains_init(dr_scene* s, const dr_params* p, uint64_t seed, uint32_
     c->P = *p;
     c->seed = seed;
     c->n_cu = g_num_cu(s->device);
-    {
-        int lim = 0;
-        if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, s->device) == hipSuccess && lim > 0)
-            c->lds_limit = lim;
-        lim = 0;
-        if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, s->device) == hipSuccess &&
-            lim > 0)
-            c->lds_per_cu = lim;
-    }
     // two lanes per chain while chains alone cannot fill two wavefronts per
     // SIMD (4 SIMDs per compute unit, 64 lanes per wavefront); one otherwise
     c->launch.lanes_per_chain = (uint64_t)p->n_chains < (uint64_t)c->n_cu * 4 * 64 * 2 ? 2u : 1u;
@@ -1295,8 +1251,6 @@ dr_status dr_chains_set_launch(dr_chains* c, const dr_launch_cfg* cfg) {
     if (cfg->sort_by_tile > 2) return fail(DR_ERR_INVALID_ARG, "dr_chains_set_launch: sort_by_tile must be 0, 1 or 2");
     if (cfg->wavefront > 2) return fail(DR_ERR_INVALID_ARG, "dr_chains_set_launch: wavefront must be 0, 1 or 2");
     if (cfg->init_refill > 2) return fail(DR_ERR_INVALID_ARG, "dr_chains_set_launch: init_refill must be 0, 1 or 2");
-    if (cfg->node_cache > 512 && cfg->node_cache != DR_NODE_CACHE_AUTO)
-        return fail(DR_ERR_INVALID_ARG, "dr_chains_set_launch: node_cache must be at most 512 (or automatic)");
     if (cfg->refill_event_pct > 100 || cfg->refill_advance_pct > 100)
         return fail(DR_ERR_INVALID_ARG, "dr_chains_set_launch: refill thresholds are percentages (1..100)");
     // the one request that allocates, before any field changes (a failed call changes nothing)
@@ -1312,7 +1266,6 @@ dr_status dr_chains_set_launch(dr_chains* c, const dr_launch_cfg* cfg) {
     if (cfg->sort_by_length) c->launch.sort_by_length = cfg->sort_by_length == 1 ? 1u : 0u;
     if (cfg->refill) c->launch.refill = cfg->refill == 1 ? 1u : 0u;
     if (cfg->sort_by_tile) c->launch.sort_by_tile = cfg->sort_by_tile == 1 ? 1u : 0u;
-    if (cfg->node_cache) c->launch.node_cache = cfg->node_cache;
     if (cfg->wavefront) c->launch.wavefront = cfg->wavefront == 1 ? 1u : 0u;
     if (cfg->init_refill) c->launch.init_refill = cfg->init_refill == 1 ? 1u : 0u;
     if (cfg->refill_event_pct) c->launch.refill_event_pct = cfg->refill_event_pct;

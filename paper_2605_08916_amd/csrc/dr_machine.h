@@ -27,7 +27,7 @@ namespace dr {
 // the wavefront's leaf rounds.
 struct RayQ {
     V3 o, d;
-    RaySlab rs;
+    RayOrd rs;
     float tmax, bt;
     int best;
     uint32_t best_prim;
@@ -54,7 +54,7 @@ __device__ __forceinline__ bool ray_begin(const DevScene& S, RayQ& q, V3 o, V3 d
         q.node = -1;
         return false;
     }
-    q.rs = ray_slab(o, d);
+    q.rs = ray_ord(o, d);
     ctr.rays++;
     return true;
 }
@@ -90,19 +90,14 @@ __device__ __forceinline__ bool ray_step(const DevScene& S, RayQ& q, uint32_t* s
             }
         }
     } else if (q.node >= 0) {
-        const DevNode n = load_node(S, q.node);
         ctr.nodes++;
         float tn[4];
         bool hit[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-            hit[k] = slab(f4(n.lox, k), f4(n.loy, k), f4(n.loz, k), f4(n.hix, k), f4(n.hiy, k), f4(n.hiz, k), q.rs,
-                          S.tmin, q.bt, tn[k]) &
-                     (i4(n.count, k) >= 0);
+        const int4 child = box4_ord(node_rsrc(S), q.node, q.rs, S.tmin, q.bt, hit, tn);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            if (hit[k] && i4(n.count, k) > 0) {
-                const int code = leaf_code(i4(n.child, k), i4(n.count, k));
+            const int code = i4(child, k);
+            if (hit[k] && code < 0) {
                 if (q.pleaf == 0) q.pleaf = code;
                 else push_entry(q.sp, stk, stride, cap_o, (uint32_t)code);
             }
@@ -111,9 +106,9 @@ __device__ __forceinline__ bool ray_step(const DevScene& S, RayQ& q, uint32_t* s
         int kc[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const bool inner = hit[k] && i4(n.count, k) == 0;
+            const bool inner = hit[k] && i4(child, k) >= 0;
             kt[k] = inner ? tn[k] : INFINITY;
-            kc[k] = inner ? i4(n.child, k) : -1;
+            kc[k] = inner ? i4(child, k) : -1;
         }
 #define DR_CSWAP(i, j)                                       \
     if (kt[j] < kt[i]) {                                     \

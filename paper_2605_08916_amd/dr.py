@@ -60,7 +60,6 @@ class dr_camera(C.Structure):
                 ("width", C.c_uint32), ("height", C.c_uint32)]
 
 
-DR_NODE_CACHE_AUTO = 0xFFFFFFFF
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
@@ -139,7 +138,7 @@ class dr_launch_cfg(C.Structure):
     _fields_ = [("block", C.c_uint32), ("blocks_per_cu", C.c_uint32), ("grab", C.c_uint32),
                 ("lanes_per_chain", C.c_uint32), ("sort_by_length", C.c_uint32), ("refill", C.c_uint32),
                 ("refill_event_pct", C.c_uint32), ("refill_advance_pct", C.c_uint32), ("sort_by_tile", C.c_uint32),
-                ("node_cache", C.c_uint32), ("wavefront", C.c_uint32), ("init_refill", C.c_uint32)]
+                ("wavefront", C.c_uint32), ("init_refill", C.c_uint32)]
 
 
 _lib = None
@@ -427,11 +426,11 @@ class Chains:
         return {k: getattr(c, k) for k, _ in dr_counters._fields_}
 
     def set_launch(self, block=0, blocks_per_cu=0, grab=0, lanes_per_chain=0, sort_by_length=0, refill=0,
-                   refill_event_pct=0, refill_advance_pct=0, sort_by_tile=0, node_cache=0, wavefront=0,
+                   refill_event_pct=0, refill_advance_pct=0, sort_by_tile=0, wavefront=0,
                    init_refill=0):
         """Zero keeps a field; sort_by_length, refill, sort_by_tile, wavefront and init_refill: 1 on, 2 off."""
         cfg = dr_launch_cfg(block, blocks_per_cu, grab, lanes_per_chain, sort_by_length, refill, refill_event_pct,
-                            refill_advance_pct, sort_by_tile, node_cache, wavefront, init_refill)
+                            refill_advance_pct, sort_by_tile, wavefront, init_refill)
         _check(lib().dr_chains_set_launch(self.h, C.byref(cfg)))
 
     def get_launch(self) -> dict:

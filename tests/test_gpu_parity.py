@@ -777,27 +777,6 @@ def test_refill_form_matches_straight_line(scenes, which, L, N):
         assert np.allclose(a["accum"], b["accum"], rtol=1e-5, atol=1e-6)
 
 
-@pytest.mark.parametrize("lanes", [1, 2])
-def test_node_cache_does_not_change_results(scenes, lanes):
-    """Reading the top BVH levels from LDS (none, 21, 85 or 341 nodes, or the
-    automatic choice) gives exactly the same chains."""
-    S = dr.Scene(scenes["spheres_small"])
-    say(f"[node cache] lanes={lanes} {S.stats()}")
-    out = []
-    for nc in (1, 21, 85, 341, dr.DR_NODE_CACHE_AUTO):
-        ch = dr.Chains(S, 3000, 8, 17, k0=250.0)
-        ch.set_launch(lanes_per_chain=lanes, node_cache=nc)
-        assert ch.get_launch()["node_cache"] == nc
-        ch.step(3)
-        ch.step(2)
-        out.append(ch.read_state())
-    a = out[0]
-    for b in out[1:]:
-        assert np.array_equal(a["x"], b["x"]) and np.array_equal(a["killed"], b["killed"])
-        assert np.array_equal(a["score"][:, a["killed"] == 0], b["score"][:, b["killed"] == 0])
-        assert a["tour_count"] == b["tour_count"]
-
-
 @pytest.mark.parametrize("which,L,N", [("tiny", 4, 3000), ("spheres_small", 8, 20000), ("specular", 8, 20000),
                                        ("interior", 8, 65536)])
 def test_wavefront_init_matches_straight_line(scenes, which, L, N):
@@ -1088,9 +1067,9 @@ def test_autotune_restores_chains(scenes, tmp_path, monkeypatch):
     got = a.get_launch()
     assert {k: got[k] for k in applied} == applied
     # staged search: block x blocks per CU, then lanes, orderings, queue batch
-    # depth (grab), node cache and the refill form, each from the best so far
+    # depth (grab) and the refill form, each from the best so far
     assert len(entry["sweep"]) == 2 * 2 + len(autotune.LANES) + (len(autotune.ORDERS) - 1) + (
-        len(autotune.GRABS) - 1) + (len(autotune.NODE_CACHES) - 1) + len(autotune.REFILL_PCTS)
+        len(autotune.GRABS) - 1) + len(autotune.REFILL_PCTS)
     assert entry["ms"] == min([ms for ms, _ in entry["sweep"]] + [entry["current_ms"]])
     a.step(3)
     b.step(3)
