@@ -66,9 +66,11 @@ __global__ void k_begin_init(KBufs B, uint32_t frame, int from_device) {
 // the scene has smooth conductors or dielectrics.  Persistent: each wavefront
 // takes the next 64 consecutive chains from the work queue (one atomic) until
 // the queue is drained, so a wavefront slot never idles waiting for the other
-// wavefronts of its block.
+// wavefronts of its block.  Registers capped for three wavefronts per SIMD,
+// as in the one-lane evolve kernel.
 template <bool DELTA>
-__global__ void __launch_bounds__(256) k_init_eval(KParams P, DevScene S, KBufs B) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+k_init_eval(KParams P, DevScene S, KBufs B) {
     extern __shared__ uint32_t s_stack[];
     uint32_t* stk = s_stack + threadIdx.x;
     const int lane = threadIdx.x & 63;
