@@ -525,7 +525,7 @@ def realtime_loop(torch, dr, scene, cams, N, L, K, W, mode, frame_steps=None, re
             ev[3].record(stream)
             stream.synchronize()
         reinit_ms, step_ms, resolve_ms = (ev[i].elapsed_time(ev[i + 1]) for i in range(3))
-        n = frame_steps or max(1, int((budget_ms - reinit_ms - resolve_ms) / step_ms))
+        n = frame_steps if frame_steps is not None else max(1, int((budget_ms - reinit_ms - resolve_ms) / step_ms))
         frame = ch.capture_frame(n, True, img, stream)
     for i in range(W):
         scene.set_camera(cams[i % len(cams)])
@@ -720,6 +720,13 @@ def realtime_line(a, torch, dr, inputs):
                                         mrse_frames, tune=not a.no_tune)
             cpx.close()
             res["realtime_one_chain_per_pixel"] = rpx
+        # the paper's own frame model: one dispatch per frame, the initialise
+        # pass alone whenever the camera has moved (Sec. 4.3, Sec. 6)
+        rin, cin, _ = realtime_loop(torch, dr, scene, cams, N, L, min(K, 10), 2, dr.DR_MODE_FUSED, 0, refs,
+                                    mrse_frames, tune=False)
+        cin.close()
+        rin["frame_is"] = "initialise pass + resolve: one dispatch per frame, the initialise one after a camera move"
+        res["realtime_initialise_only"] = rin
     if not a.no_secondary:
         res["procedural_spheres_53k"] = spheres_line(a, torch, dr, inputs, secondary=True)
     if not a.no_cpu_baseline:

@@ -4,12 +4,11 @@ It searches the kernel form (straight-line or ray-refill), the threads per
 block, the resident blocks per compute unit of the persistent grid, the number
 of consecutive chains a lane (or lane pair) takes per pop of the device work
 queue (the queue's batch depth), lanes per chain, the ordering of chains
-(none, by path length, by screen tile), the number of top BVH nodes cached in
-LDS and the refill thresholds.  Each candidate is timed on the live chain set
+(none, by path length, by screen tile) and the refill thresholds.  Each candidate is timed on the live chain set
 as `dr_step(n)` launches (n steps per launch, as the caller will issue them)
 with HIP events on the launch stream.  The default search is staged
 (coordinate descent: block x blocks per CU first, then each other dimension
-in turn from the best so far, about 30 candidates); `exhaustive=True` times
+in turn from the best so far, about 28 candidates); `exhaustive=True` times
 the full product.  The fastest configuration is cached in a JSON file keyed
 by device name, path length, chain count, triangle count and steps per
 launch.  The chain state is saved before and restored after the sweep
