@@ -218,6 +218,36 @@ def test_eval_matches_oracle(orc, scenes, which, L, n):
     _check_eval(orc.Scene(scenes[which]), L, u.astype(np.float64), dev, match)
 
 
+def test_root_leaf_and_empty_child_slots(orc, scenes):
+    """The empty room of the tiny scene (its 10 wall triangles and the 2 of
+    its ceiling light) fits one leaf of 16: the root node then holds that
+    leaf beside three empty slots (NaN boxes no ray passes).  Its evaluations
+    match the oracle and, bit for bit, those of a tree of one-triangle
+    leaves."""
+    sc = dict(scenes["tiny"])
+    keep = np.r_[0:10, 30:32]
+    sc["indices"] = sc["indices"][keep].copy()
+    sc["tri_material"] = sc["tri_material"][keep].copy()
+    L, n = 4, 4000
+    u, dev, _, match = _eval_both(orc, sc, L, n, seed=21)
+    say(f"[root leaf] path-signature match {match.mean():.5f}")
+    assert match.mean() > 0.995
+    _check_eval(orc.Scene(sc), L, u.astype(np.float64), dev, match)
+    ut = torch.from_numpy(u).cuda()
+    outs = []
+    for ml in (16, 1):
+        S = dr.Scene(sc, max_leaf=ml)
+        st = S.stats()
+        say(f"  max_leaf={ml} {st}")
+        if ml == 16:
+            assert st["n_nodes"] == 1
+        outs.append(S.eval_logp_grad(L, ut, grad=True, rec=True))
+        torch.cuda.synchronize()
+        S.close()
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)
+
+
 @pytest.mark.parametrize("which,L,n", [("tiny", 4, 3000), ("spheres_small", 8, 20000), ("specular", 8, 20000)])
 def test_forward_only_eval_matches_eval_with_score(scenes, which, L, n):
     """Forward-only evaluation (the ray-refill evaluator) returns exactly the
