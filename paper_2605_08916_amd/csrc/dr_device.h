@@ -174,10 +174,21 @@ __device__ __forceinline__ float mx(float a, float b) { return __builtin_element
 // Component q of a vector (q is a compile-time constant after unrolling).
 __device__ __forceinline__ float f4(const float4& v, int q) { return q == 0 ? v.x : (q == 1 ? v.y : (q == 2 ? v.z : v.w)); }
 __device__ __forceinline__ int i4(const int4& v, int q) { return q == 0 ? v.x : (q == 1 ? v.y : (q == 2 ? v.z : v.w)); }
-// Buffer resource over the scene's node array (raw, byte offsets, range
-// checked against the array's size).
+// Buffer resources over the scene's node and triangle arrays (raw, byte
+// offsets, range checked against the array's size: below 2^31 bytes for the
+// at most 2^24 - 1 triangles a scene holds).  A fetch through one needs a
+// 32-bit offset instead of a 64-bit address.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t node_rsrc(const DevScene& S) {
     return __builtin_amdgcn_make_buffer_rsrc((void*)S.nodes, (short)0, S.n_nodes * (int)sizeof(DevNode), 0x00020000);
+}
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tri_rsrc(const DevScene& S) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)S.tris, (short)0, S.n_tris * (int)sizeof(DevTri), 0x00020000);
+}
+// 16 bytes at byte offset off of a buffer.
+__device__ __forceinline__ float4 ld16(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+    const u4 v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    return make_float4(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), __uint_as_float(v.w));
 }
 // The four child boxes of node `node` against one ray: hit[q] and tnear[q];
 // returns the children's stack entries.  Seven 16-byte fetches through the
@@ -186,16 +197,11 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t node_rsrc(const DevScene& S) {
 // the L1 and L2 (an LDS copy of them measured no faster with this form).
 __device__ __forceinline__ int4 box4_ord(__amdgpu_buffer_rsrc_t rn, int node, const RayOrd& r, float tmin, float tmax,
                                          bool hit[4], float tn[4]) {
-    typedef uint32_t u4 __attribute__((ext_vector_type(4)));
     const uint32_t b = (uint32_t)node << 7;
-    auto ld = [&](uint32_t off) {
-        const u4 v = __builtin_amdgcn_raw_buffer_load_b128(rn, b + off, 0, 0);
-        return make_float4(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), __uint_as_float(v.w));
-    };
-    const float4 nx = ld(r.noff & 0xffu), fx = ld(r.foff & 0xffu);
-    const float4 ny = ld((r.noff >> 8) & 0xffu), fy = ld((r.foff >> 8) & 0xffu);
-    const float4 nz = ld(r.noff >> 16), fz = ld(r.foff >> 16);
-    const u4 c = __builtin_amdgcn_raw_buffer_load_b128(rn, b + 96u, 0, 0);
+    const float4 nx = ld16(rn, b + (r.noff & 0xffu)), fx = ld16(rn, b + (r.foff & 0xffu));
+    const float4 ny = ld16(rn, b + ((r.noff >> 8) & 0xffu)), fy = ld16(rn, b + ((r.foff >> 8) & 0xffu));
+    const float4 nz = ld16(rn, b + (r.noff >> 16)), fz = ld16(rn, b + (r.foff >> 16));
+    const float4 cf = ld16(rn, b + 96u);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const float tnx = fmaf(f4(nx, q), r.inv.x, r.cn.x), tfx = fmaf(f4(fx, q), r.inv.x, r.cf.x);
@@ -206,25 +212,25 @@ __device__ __forceinline__ int4 box4_ord(__amdgpu_buffer_rsrc_t rn, int node, co
         tn[q] = t0;
         hit[q] = t0 <= mn(t1, tmax);
     }
-    return make_int4((int)c.x, (int)c.y, (int)c.z, (int)c.w);
+    return make_int4(__float_as_int(cf.x), __float_as_int(cf.y), __float_as_int(cf.z), __float_as_int(cf.w));
 }
 
 // Moller-Trumbore, two-sided; t in (tmin, inf) before the caller's range test.
-// The reciprocal of the determinant is the hardware one (1 ulp).
+// The reciprocal of the determinant is the hardware one (1 ulp).  Evaluated
+// without early exits (a wavefront's lanes diverge on them anyway); the
+// conditions keep the branching form's treatment of NaN (a NaN barycentric
+// does not reject), so the answers are the same.
 __device__ __forceinline__ bool tri_test(const DevTri& T, V3 o, V3 d, float tmin, float& t) {
     const V3 e1 = xyz(T.e1), e2 = xyz(T.e2);
     const V3 pv = cross(d, e2);
     const float det = dot(e1, pv);
-    if (det == 0.0f) return false;
     const float inv = __builtin_amdgcn_rcpf(det);
     const V3 tv = o - xyz(T.v0);
     const float b1 = dot(tv, pv) * inv;
-    if (b1 < 0.0f || b1 > 1.0f) return false;
     const V3 qv = cross(tv, e1);
     const float b2 = dot(d, qv) * inv;
-    if (b2 < 0.0f || b1 + b2 > 1.0f) return false;
     t = dot(e2, qv) * inv;
-    return t > tmin;
+    return (det != 0.0f) & !(b1 < 0.0f || b1 > 1.0f) & !(b2 < 0.0f || b1 + b2 > 1.0f) & (t > tmin);
 }
 
 // Leaf entries share the traversal stack with inner nodes: a leaf of cnt
@@ -240,10 +246,16 @@ __device__ __forceinline__ bool test_leaf(const DevScene& S, int code, V3 o, V3 
                                           int& best, uint32_t& best_prim, Counters& ctr) {
     const int v = -1 - code;
     const int first = v >> 5, cnt = v & 31;
+    const __amdgpu_buffer_rsrc_t rt = tri_rsrc(S);
     for (int k0 = first; k0 < first + cnt; k0 += BATCH) {
         DevTri T[BATCH];
 #pragma unroll
-        for (int e = 0; e < BATCH; ++e) T[e] = S.tris[min(k0 + e, S.n_tris - 1)];
+        for (int e = 0; e < BATCH; ++e) {
+            const uint32_t off = (uint32_t)min(k0 + e, S.n_tris - 1) * (uint32_t)sizeof(DevTri);
+            T[e].v0 = ld16(rt, off);
+            T[e].e1 = ld16(rt, off + 16u);
+            T[e].e2 = ld16(rt, off + 32u);
+        }
 #pragma unroll
         for (int e = 0; e < BATCH; ++e) {
             if (k0 + e >= first + cnt) break;
