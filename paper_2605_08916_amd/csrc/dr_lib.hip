@@ -725,28 +725,69 @@ dr_status dr_scene_create(const dr_scene_desc* desc, int device, dr_scene** out)
             }
         }
     }
-    // Collapse the binary tree into 4-wide nodes: a node takes its two
-    // children and keeps replacing the inner child of largest surface area by
-    // that child's two children until it has four.  Device nodes are created
-    // in depth-first order; leaves stay embedded in their parent.
+    // Collapse the binary tree into 4-wide nodes with the fewest expected node
+    // visits.  Under the surface-area model a ray visits a node with
+    // probability proportional to the area of its box, so the collapse
+    // minimises the summed area of the 4-wide nodes (the leaves, and so the
+    // triangle tests, are the binary tree's whatever the collapse).  Dynamic
+    // programming over the binary tree, children before parents (after the
+    // optimal wide-BVH collapse of Ylitie, Karras and Laine, HPG 2017):
+    // cost[4 n + i - 1] is the least summed area of the 4-wide nodes within
+    // binary subtree n when n may take at most i slots of its parent's node:
+    // one slot (a leaf, or a 4-wide node whose four slots its two subtrees
+    // share), or, for i >= 2, n dissolved into its subtrees' slots.  pick
+    // records the choice: for i = 1 the slots of n's own node given to its
+    // first child, for i >= 2 0 (keep n as one slot) or the slots given to
+    // its first child.  Device nodes are created in depth-first order; leaves
+    // stay embedded in their parent.
     auto area = [&](int i) {
-        const float dx = bhi[3 * i] - blo[3 * i], dy = bhi[3 * i + 1] - blo[3 * i + 1], dz = bhi[3 * i + 2] - blo[3 * i + 2];
+        const double dx = (double)bhi[3 * i] - blo[3 * i], dy = (double)bhi[3 * i + 1] - blo[3 * i + 1],
+                     dz = (double)bhi[3 * i + 2] - blo[3 * i + 2];
         return dx * dy + dy * dz + dz * dx;
     };
-    auto gather = [&](int i, int out[4]) {
-        int k = 0;
-        out[k++] = nodes[i].a;
-        out[k++] = nodes[i].b;
-        while (k < 4) {
-            int best = -1;
-            float ba = -1.f;
-            for (int q = 0; q < k; ++q)
-                if (nodes[out[q]].a >= 0 && area(out[q]) > ba) { ba = area(out[q]); best = q; }
-            if (best < 0) break;
-            const int c = out[best];
-            out[best] = nodes[c].a;
-            out[k++] = nodes[c].b;
+    std::vector<double> cost(4 * NN, 0.0);
+    std::vector<uint8_t> pick(4 * NN, 0);
+    for (auto it = topo.rbegin(); it != topo.rend(); ++it) {
+        const int n = *it;
+        if (nodes[n].a < 0) continue;  // a leaf takes one slot and adds no node
+        const size_t ca = 4 * (size_t)nodes[n].a, cb = 4 * (size_t)nodes[n].b, cn = 4 * (size_t)n;
+        double best = INFINITY;
+        for (int j = 1; j <= 3; ++j) {
+            const double c = cost[ca + j - 1] + cost[cb + 3 - j];
+            if (c < best) { best = c; pick[cn] = (uint8_t)j; }
         }
+        const double as_node = area(n) + best;
+        cost[cn] = as_node;
+        for (int i = 2; i <= 4; ++i) {
+            cost[cn + i - 1] = as_node;
+            pick[cn + i - 1] = 0;
+            for (int j = 1; j < i; ++j) {
+                const double c = cost[ca + j - 1] + cost[cb + i - j - 1];
+                if (c < cost[cn + i - 1]) { cost[cn + i - 1] = c; pick[cn + i - 1] = (uint8_t)j; }
+            }
+        }
+    }
+    // the slots of binary subtree x given at most i of them
+    struct Expand {
+        const std::vector<dr_bvh_node>& nodes;
+        const std::vector<uint8_t>& pick;
+        void operator()(int x, int i, int out[4], int& k) const {
+            const int j = i > 1 && nodes[x].a >= 0 ? pick[4 * (size_t)x + i - 1] : 0;
+            if (j == 0) {
+                out[k++] = x;
+                return;
+            }
+            (*this)(nodes[x].a, j, out, k);
+            (*this)(nodes[x].b, i - j, out, k);
+        }
+    };
+    const Expand expand{nodes, pick};
+    // the children of the 4-wide node made from inner binary node n
+    auto gather = [&](int n, int out[4]) {
+        int k = 0;
+        const int j = pick[4 * (size_t)n];
+        expand(nodes[n].a, j, out, k);
+        expand(nodes[n].b, 4 - j, out, k);
         return k;
     };
     // the first 512 nodes laid out breadth-first, the rest depth-first
