@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--plain", action="store_true",
+                    help="with --profile-only: the plain multi-kernel form instead of the fused one")
     ap.add_argument("--no-mrse", action="store_true")
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the 53k-triangle secondary line and the 1,048,576-chain loop")
@@ -865,7 +867,7 @@ def main():
         sigma = None
         if a.config == "spheres_1080p_L16":
             sigma = torch.from_numpy(inputs.per_chain_sigma(4 * (L - 1), N, seed=4)).cuda()
-        ch = dr.Chains(scene, N, L, 2024, sigma=sigma)
+        ch = dr.Chains(scene, N, L, 2024, sigma=sigma, mode=dr.DR_MODE_PLAIN if a.plain else dr.DR_MODE_FUSED)
         if a.config or a.headline_spheres:
             for _ in range(a.warmup + a.steps):
                 ch.step(F)
@@ -880,7 +882,8 @@ def main():
                 ch.resolve(img)
         torch.cuda.synchronize()
         print(json.dumps({"profile_only_launches": a.warmup + a.steps, "steps_per_launch": F, "chains": N,
-                          "config": a.config or ("spheres" if a.headline_spheres else "interior")}))
+                          "config": a.config or ("spheres" if a.headline_spheres else "interior"),
+                          "form": "plain" if a.plain else "fused"}))
         return
     if a.config and a.config != "interior":
         run_config(a, torch, dr, inputs)
